@@ -1,0 +1,181 @@
+"""Benchmark: KIFMM matvec on one MI355X, SVD-compressed M2L vs dense M2L.
+
+Workload: 2**20 collocation points (centroids of a level-8 icosphere of
+radius 1, seeded subset), density 1 + 0.5 Y_2^0 + N(0, 0.01), p = 6
+(152 surface points), eps = 1e-6, leaf size 64, FP32 evaluation with the M2L
+and translation GEMMs on FP32 MFMA. A step is one full matvec phi = F sigma
+(all stages: permute, S2M, M2M, M2L, L2L, L2T, S2T) with sigma resident in HBM.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Prints one JSON line. `value` is the SVD-M2L matvec time in ms (lower is
+better); the dense-M2L matvec on the same points, the per-stage times, the M2L
+roofline and the accuracy of both against the FP64 oracle ride along.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "KIFMM matvec ms + M2L MFMA util at N=1M p=6: SVD-M2L vs dense-M2L, same acc"
+PEAK_FP32_MFMA_TFLOPS = 157.3
+N, P, EPS, LEAF = 1 << 20, 6, 1e-6, 64
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_plan(plan, sd, out, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.apply(sd, out)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        plan.apply(sd, out)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms, calls = plan.profile_read()
+    plan.profile(False)
+    return start.elapsed_time(stop) / steps, wall, {k: v / calls for k, v in stage_ms.items()}
+
+
+def traffic_record(info):
+    """HBM bytes per M2L launch from a committed rocprofv3 --pmc summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "m2l_traffic_sphere1m_p6.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1211_2517_amd", "csrc", "kernels.hip"), "rb").read()
+    if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline():
+    """The oracle (FP64, numpy) as it stands, timed on a bounded sample of the
+    workload: the same sphere recipe at N = 2**17 points, dense-M2L KIFMM
+    evaluation only (tree and operators built before the clock starts)."""
+    import oracle
+    import workloads
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        cores = 1
+    n = 1 << 17
+    x = workloads.sphere_points(n, workloads.SEED_BASE + 1)
+    s = workloads.sphere_density(x, workloads.SEED_BASE + 101)
+    tree = oracle.build_tree(x, LEAF)
+    ops = oracle.build_operators(P, EPS, LEAF, mode="dense")
+    t0 = time.perf_counter()
+    oracle.fmm(x, s, P, EPS, LEAF, ops=ops, tree=tree)
+    secs = time.perf_counter() - t0
+    return {"value": secs * 1e3 * (N / n), "unit": "ms", "cores": cores, "kind": "oracle",
+            "sample": f"oracle dense-M2L KIFMM (FP64 numpy) on a {n}-point sphere of the same recipe "
+                      f"(p=6, eps=1e-6, leaf 64): {secs:.2f} s, scaled x{N // n} to N=2^20 by the O(N) cost"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
+              f"multi-GPU path; the per-GPU kernel is measured at N=1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1211_2517_amd as K
+    import workloads
+
+    log("generating the 2^20-point sphere")
+    x = workloads.sphere_points(N, workloads.SEED_BASE + 1)
+    s = workloads.sphere_density(x, workloads.SEED_BASE + 101)
+    sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
+    out = torch.empty_like(sd)
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "sphere1m_p6_samples.json")))
+    idx = np.asarray(golden["sample"])
+    ref = np.asarray(golden["phi_dense"])
+    ref_direct = np.asarray(golden["phi_direct"])
+
+    res = {}
+    for name, dense in (("svd", False), ("dense", True)):
+        log(f"plan {name}")
+        plan = K.Plan(x, p=P, eps=EPS, leaf_size=LEAF, precision="fp32", dense_m2l=dense)
+        info = plan.info()
+        log(f"{name}: depth {info['depth']} k {info['k']} v_pairs {info['v_pairs']} "
+            f"plan {info['plan_seconds']:.1f}s; timing {args.steps} steps")
+        ms, wall, stages = time_plan(plan, sd, out, args.steps, args.warmup)
+        got = out.double().cpu().numpy()[idx]
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        err_direct = float(np.linalg.norm(got - ref_direct) / np.linalg.norm(ref_direct))
+        log(f"{name}: {ms:.3f} ms/step, err vs FP64 oracle {err:.2e}, stages {stages}")
+        res[name] = dict(ms=ms, wall=wall, stages=stages, info=info, err=err, err_direct=err_direct)
+        plan.close()
+
+    svd = res["svd"]
+    info = svd["info"]
+    m2l_ms = svd["stages"]["m2l"]
+    achieved = info["flops"]["m2l"] / (m2l_ms * 1e-3) / 1e12
+    dense_m2l = res["dense"]["info"]["flops"]["m2l"] / (res["dense"]["stages"]["m2l"] * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": round(svd["ms"], 4),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(svd["ms"], 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sphere-2^20 icosphere centroids, p=6, eps=1e-6, leaf 64, FP32 MFMA M2L",
+                   "n": N, "p": P, "eps": EPS, "leaf_size": LEAF, "depth": info["depth"], "k": info["k"],
+                   "n_eq": info["n_eq"], "v_pairs": info["v_pairs"],
+                   "p2p_interactions": info["p2p_interactions"]},
+        "dense_m2l_ms_per_step": round(res["dense"]["ms"], 4),
+        "speedup_vs_dense_m2l": round(res["dense"]["ms"] / svd["ms"], 3),
+        "m2l_speedup_vs_dense_m2l": round(res["dense"]["stages"]["m2l"] / m2l_ms, 3),
+        "m2l_mfma_util": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+        "m2l_mfma_util_dense": round(dense_m2l / PEAK_FP32_MFMA_TFLOPS, 4),
+        "stage_ms": {k: round(v, 4) for k, v in svd["stages"].items()},
+        "stage_ms_dense": {k: round(v, 4) for k, v in res["dense"]["stages"].items()},
+        "err_vs_fp64_dense_oracle": {"svd_fp32": svd["err"], "dense_fp32": res["dense"]["err"]},
+        "fmm_err_vs_direct_sum": {"svd_fp32": svd["err_direct"], "dense_fp32": res["dense"]["err_direct"]},
+        "roofline": {"bound": "mfma", "kernel": "gg_kernel (M2L, compressed, FP32 MFMA)",
+                     "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
+                     "flops_per_launch": info["flops"]["m2l"], "avg_launch_ms": round(m2l_ms, 4),
+                     "traffic": traffic_record(info)},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host cores")
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,189 @@
+/*
+ * kifmm.h - C ABI of the MI355X (gfx950) SVD-accelerated kernel-independent FMM.
+ *
+ * The library evaluates the single-layer Laplace potential of N point sources
+ * at the same N points (eq. (1) of Cao, Wen, Rong, "A SVD accelerated
+ * kernel-independent fast multipole method and its application to BEM",
+ * with G(x,y) = 1/(4 pi |x-y|) of Sec. 4 and the self pair contributing 0):
+ *
+ *     phi_i = sum_{j != i} sigma_j / (4 pi |x_i - x_j|)
+ *
+ * by the KIFMM of Sec. 2 whose M2L translations are compressed by the
+ * stage-1 SVD of Sec. 3.1 and whose upward and downward passes use the
+ * reduced operators of Sec. 3.3 (or, with opts.dense_m2l, the uncompressed
+ * operators). The evaluation order is the complete algorithm of Sec. 4.3.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns an int status (KIFMM_OK = 0 or a negative code); no
+ *    C++ exception crosses the ABI. kifmm_last_error() gives a thread-local
+ *    message for the last failing call on the calling thread.
+ *  - Host pointers are read during the call only and may be freed after it.
+ *  - Device pointers (sigma, phi, g, out) point to memory of the plan's device;
+ *    they hold float for KIFMM_FP32 and KIFMM_BF16X3 plans and double for
+ *    KIFMM_FP64 plans, in the caller's point order. The caller keeps them alive
+ *    until the stream has finished the work.
+ *  - The apply calls are asynchronous on `stream` (a hipStream_t, 0 for the
+ *    null stream), allocate nothing, copy nothing between host and device and
+ *    may be captured in a HIP graph. Applies of one plan must not overlap in
+ *    time (they share the plan's workspace): issue them on one stream or
+ *    order them with events.
+ */
+#ifndef KIFMM_H
+#define KIFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kifmm_plan_s* kifmm_plan_t;   /* opaque; owns its device memory */
+typedef struct kifmm_group_s* kifmm_group_t; /* opaque; several plans in one HIP graph */
+
+enum {
+    KIFMM_OK = 0,
+    KIFMM_EINVAL = -1,     /* invalid argument (sizes, null pointers, ranges) */
+    KIFMM_ENOMEM = -2,     /* host or device allocation failed, or opts.mem_limit exceeded */
+    KIFMM_EHIP = -3,       /* a HIP runtime call or kernel launch failed */
+    KIFMM_ENONFINITE = -4, /* a point coordinate is NaN or infinite */
+    KIFMM_ESTATE = -5      /* call not valid for this plan (e.g. apply on a host-only plan) */
+};
+
+enum {
+    KIFMM_FP64 = 0,  /* every device stage in double */
+    KIFMM_FP32 = 1,  /* every device stage in float; M2L/translation GEMMs on FP32 MFMA */
+    KIFMM_BF16X3 = 2 /* as FP32, but the M2L GEMM as three BF16 MFMA products (hi*hi + hi*lo +
+                        lo*hi) with FP32 accumulation */
+};
+
+typedef struct {
+    int precision;      /* KIFMM_FP64 / KIFMM_FP32 / KIFMM_BF16X3; default KIFMM_FP32 */
+    double cd;          /* surface constant C_d of d = C_d / sqrt(leaf_size) (Sec. 4.1); default 0.5 */
+    double pinv_rcond;  /* relative cutoff of the truncated-SVD pseudo-inverses of the
+                           check-to-equivalent matrices; default 1e-10 */
+    int depth;          /* 0 = automatic (smallest level whose cubes all hold <= leaf_size
+                           points); > 0 forces the leaf level */
+    int max_depth;      /* cap of the automatic depth; default 16, at most 20 */
+    int dense_m2l;      /* 1 = uncompressed operators (n_eq-dimensional, the baseline); default 0 */
+    int max_nrhs;       /* largest nrhs accepted by kifmm_apply_batched; default 1, at most 16 */
+    int device;         /* HIP device ordinal; default 0; -1 builds a host-only plan (tree,
+                           lists and operators, no device memory: info/export calls only) */
+    size_t mem_limit;   /* fail with KIFMM_ENOMEM if the plan's device memory would exceed
+                           this many bytes; 0 = no limit */
+    int tile_targets;   /* target boxes per M2L work tile; 0 = autotune on the device */
+} kifmm_opts_t;
+
+/* Per-stage counters; index with the KIFMM_STAGE_* values. */
+enum {
+    KIFMM_STAGE_P2M = 0, KIFMM_STAGE_M2M = 1, KIFMM_STAGE_M2L = 2, KIFMM_STAGE_L2L = 3,
+    KIFMM_STAGE_L2P = 4, KIFMM_STAGE_P2P = 5, KIFMM_STAGE_PERM = 6, KIFMM_STAGE_COUNT = 7
+};
+
+typedef struct {
+    int depth;              /* leaf level L */
+    int k;                  /* reduced dimension (n_eq when dense_m2l) */
+    int n_eq;               /* surface points per cube, p^3 - (p-2)^3 */
+    int k_pad;              /* k rounded up to a multiple of 16 (device row stride) */
+    int precision;
+    int dense_m2l;
+    int64_t n;              /* points */
+    int64_t n_leaf;         /* nonempty leaves */
+    int64_t n_box;          /* nonempty cubes at levels 0..L */
+    int64_t near_pairs;     /* (target leaf, source leaf) near-field pairs */
+    int64_t p2p_interactions; /* point-point interactions of the near field (self included) */
+    int64_t v_pairs;        /* M2L (target, source) pairs over levels 2..L */
+    int64_t v_pairs_level[21];
+    int64_t boxes_level[21];
+    double r0;              /* root half-width */
+    double flops[KIFMM_STAGE_COUNT];  /* algorithmic flops per apply (unpadded) */
+    double bytes[KIFMM_STAGE_COUNT];  /* algorithmic HBM bytes per apply */
+    size_t device_bytes;    /* device memory owned by the plan */
+    int m2l_tile_targets;   /* tile size in use */
+    double sigma0;          /* largest singular value of K_fat (svd mode), else 0 */
+    double plan_seconds;    /* wall time of the plan call */
+} kifmm_info_t;
+
+/* Fill `o` with the defaults listed above. Returns KIFMM_EINVAL if o is NULL. */
+int kifmm_opts_default(kifmm_opts_t* o);
+
+/* Build a plan (Alg. Step 1, Sec. 4.3): octree over the points (Sec. 2.1), near
+ * and interaction fields, surfaces (Sec. 2.1 with d of Sec. 4.1), operators in
+ * FP64 (S, M, K, L, T of eqs. (3)-(7); stage-1 SVD of Sec. 3.1 keeping singular
+ * values >= eps * Sigma_00; reduced operators of Sec. 3.3), the M2L work
+ * schedule, and the upload of all of it to the device.
+ *   points:    host, n x 3 row-major doubles (x0,y0,z0,x1,...); copied.
+ *   n >= 1; 2 <= p <= 16 (points per cube side; n_eq = p^3 - (p-2)^3);
+ *   0 <= eps < 1 (eps = 0 keeps every singular vector); leaf_size >= 1.
+ *   out:       receives the plan; set to NULL on failure.
+ * Errors: KIFMM_EINVAL, KIFMM_ENONFINITE, KIFMM_ENOMEM, KIFMM_EHIP. */
+int kifmm_plan(const double* points, int64_t n, int p, double eps, int leaf_size,
+               kifmm_plan_t* out);
+/* As kifmm_plan with options (NULL = defaults). */
+int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_size,
+                  const kifmm_opts_t* opts, kifmm_plan_t* out);
+
+/* phi = F sigma, the FMM approximation of eq. (1) (Alg. Steps 2-4, Sec. 4.3).
+ *   sigma, phi: device, n elements each, caller order; must not alias. */
+int kifmm_apply(kifmm_plan_t plan, const void* sigma, void* phi, void* stream);
+
+/* out = F^T g by the transposed passes (L2T^T, L2L^T up the tree, M2L with
+ * the transposed class matrices, M2M^T down the tree, S2M^T, S2T^T).
+ *   g, out: device, n elements each, caller order; must not alias. */
+int kifmm_apply_adjoint(kifmm_plan_t plan, const void* g, void* out, void* stream);
+
+/* nrhs right-hand sides at once (1 <= nrhs <= opts.max_nrhs of the plan).
+ *   sigma, phi: device, column-major n x nrhs with leading dimension ld >= n. */
+int kifmm_apply_batched(kifmm_plan_t plan, const void* sigma, void* phi, int nrhs, int64_t ld,
+                        void* stream);
+
+/* Group several plans (for instance independent point sets) so that one call
+ * runs all their applies from one captured HIP graph. The plans must outlive
+ * the group and must use one device and one precision. */
+int kifmm_group_create(const kifmm_plan_t* plans, int nplans, kifmm_group_t* out);
+/* sigma[i], phi[i]: device vectors of plan i (as in kifmm_apply). The first call
+ * with a given set of pointers captures the graph; later calls with the same
+ * pointers replay it, other pointers re-capture it. */
+int kifmm_group_apply(kifmm_group_t group, const void* const* sigma, void* const* phi,
+                      void* stream);
+void kifmm_group_destroy(kifmm_group_t group); /* NULL-safe */
+
+/* Sizes, counts and per-stage algorithmic flops/bytes of a plan. */
+int kifmm_plan_info(kifmm_plan_t plan, kifmm_info_t* info);
+
+/* Leaf cube of every point (caller order) as integer coordinates at level
+ * info.depth: leaf_coords is a host array of n x 3 int32. */
+int kifmm_plan_export_tree(kifmm_plan_t plan, int32_t* leaf_coords);
+
+/* Host FP64 copies of the plan's operators (for checks). `which`:
+ *   0 singular values of K_fat (n_eq values; dense plans: zeros)
+ *   1 U~ (n_eq x k, row-major; dense: identity)
+ *   2 S~  (k x n_eq)      3 T~ (n_eq x k)
+ *   4 M~^o (8 x k x k; o = 4*ox + 2*oy + oz, child position bits)
+ *   5 L~^o (8 x k x k)    6 K~^(t) (316 x k x k; t in lexicographic order over
+ *                            [-3,3]^3 with max|t_a| >= 2)
+ * `out` must hold the number of doubles stated; `count` (may be NULL) receives it. */
+int kifmm_plan_export_operator(kifmm_plan_t plan, int which, double* out, int64_t* count);
+
+/* Stage timing with HIP events (the tracing facility). While enabled, every
+ * apply of the plan records an event on its stream before and after each stage
+ * (KIFMM_STAGE_* order: P2M = surface evaluation + S~ GEMM, M2M, M2L, L2L,
+ * L2P = T~ GEMM, P2P = near field + L2T evaluation + scatter, PERM = permute-in).
+ * Enabled applies cannot be captured in a HIP graph. kifmm_profile(plan, 0/1)
+ * switches it and clears the totals. */
+int kifmm_profile(kifmm_plan_t plan, int enable);
+/* Waits for the recorded events and returns the summed milliseconds per stage
+ * since profiling was enabled (ms[KIFMM_STAGE_COUNT]) and the number of
+ * profiled applies (*calls, may be NULL). */
+int kifmm_profile_read(kifmm_plan_t plan, double* ms, int64_t* calls);
+
+/* Release a plan and its device memory. NULL-safe; the plan must not be in use. */
+void kifmm_destroy(kifmm_plan_t plan);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* kifmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KIFMM_H */

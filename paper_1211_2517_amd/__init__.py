@@ -1,0 +1,310 @@
+"""MI355X (gfx950) SVD-accelerated kernel-independent FMM: Python binding.
+
+Thin ctypes marshalling over the C ABI declared in include/kifmm.h. Every step
+of the evaluation runs in the library's HIP kernels; PyTorch only provides
+device memory and the current stream. There is no CPU fallback: if the
+library is not built, loading fails with an error.
+
+    plan = Plan(points, p=6, eps=1e-6, leaf_size=64)      # points: (N,3) float64, host
+    phi = plan.apply(sigma)                               # sigma: (N,) cuda float32
+    g = plan.apply_adjoint(r)
+    KifmmMatvec.apply(plan, sigma)                        # autograd: backward = adjoint
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Plan", "Group", "KifmmMatvec", "KifmmError", "load_library", "library_path",
+           "FP64", "FP32", "BF16X3", "STAGES", "EXPORTED_SYMBOLS"]
+
+FP64, FP32, BF16X3 = 0, 1, 2
+STAGES = ("p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "perm")
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+
+EXPORTED_SYMBOLS = (
+    "kifmm_opts_default", "kifmm_plan", "kifmm_plan_ex", "kifmm_apply", "kifmm_apply_adjoint",
+    "kifmm_apply_batched", "kifmm_group_create", "kifmm_group_apply", "kifmm_group_destroy",
+    "kifmm_plan_info", "kifmm_plan_export_tree", "kifmm_plan_export_operator", "kifmm_profile",
+    "kifmm_profile_read", "kifmm_destroy", "kifmm_last_error",
+)
+
+
+class KifmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"kifmm error {code}: {msg}")
+        self.code = code
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("cd", ctypes.c_double), ("pinv_rcond", ctypes.c_double),
+                ("depth", ctypes.c_int), ("max_depth", ctypes.c_int), ("dense_m2l", ctypes.c_int),
+                ("max_nrhs", ctypes.c_int), ("device", ctypes.c_int), ("mem_limit", ctypes.c_size_t),
+                ("tile_targets", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("depth", ctypes.c_int), ("k", ctypes.c_int), ("n_eq", ctypes.c_int), ("k_pad", ctypes.c_int),
+                ("precision", ctypes.c_int), ("dense_m2l", ctypes.c_int), ("n", ctypes.c_int64),
+                ("n_leaf", ctypes.c_int64), ("n_box", ctypes.c_int64), ("near_pairs", ctypes.c_int64),
+                ("p2p_interactions", ctypes.c_int64), ("v_pairs", ctypes.c_int64),
+                ("v_pairs_level", ctypes.c_int64 * 21), ("boxes_level", ctypes.c_int64 * 21),
+                ("r0", ctypes.c_double), ("flops", ctypes.c_double * 7), ("bytes", ctypes.c_double * 7),
+                ("device_bytes", ctypes.c_size_t), ("m2l_tile_targets", ctypes.c_int),
+                ("sigma0", ctypes.c_double), ("plan_seconds", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def library_path() -> str:
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "libkifmm.so")
+
+
+def load_library():
+    """Load libkifmm.so (built in-tree by paper_1211_2517_amd/build.py)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    P, I, D, I64, V = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64, ctypes.c_void_p
+    lib.kifmm_opts_default.argtypes = [ctypes.POINTER(_Opts)]
+    lib.kifmm_plan.argtypes = [P, I64, I, D, I, ctypes.POINTER(V)]
+    lib.kifmm_plan_ex.argtypes = [P, I64, I, D, I, ctypes.POINTER(_Opts), ctypes.POINTER(V)]
+    lib.kifmm_apply.argtypes = [V, P, P, P]
+    lib.kifmm_apply_adjoint.argtypes = [V, P, P, P]
+    lib.kifmm_apply_batched.argtypes = [V, P, P, I, I64, P]
+    lib.kifmm_group_create.argtypes = [ctypes.POINTER(V), I, ctypes.POINTER(V)]
+    lib.kifmm_group_apply.argtypes = [V, ctypes.POINTER(P), ctypes.POINTER(P), P]
+    lib.kifmm_group_destroy.argtypes = [V]
+    lib.kifmm_group_destroy.restype = None
+    lib.kifmm_plan_info.argtypes = [V, ctypes.POINTER(_Info)]
+    lib.kifmm_plan_export_tree.argtypes = [V, P]
+    lib.kifmm_plan_export_operator.argtypes = [V, I, P, ctypes.POINTER(I64)]
+    lib.kifmm_profile.argtypes = [V, I]
+    lib.kifmm_profile_read.argtypes = [V, P, ctypes.POINTER(I64)]
+    lib.kifmm_destroy.argtypes = [V]
+    lib.kifmm_destroy.restype = None
+    lib.kifmm_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED_SYMBOLS:
+        if not hasattr(lib, name):
+            raise ImportError(f"{path} does not export {name}")
+    _LIB = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise KifmmError(rc, load_library().kifmm_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Plan:
+    """A KIFMM plan over a fixed point set (tree, lists, operators on the device)."""
+
+    def __init__(self, points, p: int = 6, eps: float = 1e-6, leaf_size: int = 64, *,
+                 precision: str = "fp32", dense_m2l: bool = False, max_nrhs: int = 1, device: int = 0,
+                 depth: int = 0, max_depth: int = 16, cd: float = 0.5, pinv_rcond: float = 1e-10,
+                 mem_limit: int = 0, tile_targets: int = 0):
+        lib = load_library()
+        pts = np.ascontiguousarray(np.asarray(points.cpu().numpy() if hasattr(points, "cpu") else points,
+                                              dtype=np.float64))
+        if pts.ndim != 2 or pts.shape[1] != 3:
+            raise ValueError("points must have shape (N, 3)")
+        o = _Opts()
+        lib.kifmm_opts_default(ctypes.byref(o))
+        o.precision = _PREC[precision]
+        o.dense_m2l = int(bool(dense_m2l))
+        o.max_nrhs = int(max_nrhs)
+        o.device = int(device)
+        o.depth = int(depth)
+        o.max_depth = int(max_depth)
+        o.cd = float(cd)
+        o.pinv_rcond = float(pinv_rcond)
+        o.mem_limit = int(mem_limit)
+        o.tile_targets = int(tile_targets)
+        h = ctypes.c_void_p()
+        _check(lib.kifmm_plan_ex(pts.ctypes.data, pts.shape[0], int(p), float(eps), int(leaf_size),
+                                 ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.n = pts.shape[0]
+        self.p, self.eps, self.leaf_size = p, eps, leaf_size
+        self.precision = precision
+        self.device = device
+        self.max_nrhs = max_nrhs
+
+    # ------------------------------------------------------------------ info
+    def info(self) -> dict:
+        i = _Info()
+        _check(self._lib.kifmm_plan_info(self._h, ctypes.byref(i)))
+        d = {f: getattr(i, f) for f, _ in _Info._fields_}
+        d["v_pairs_level"] = list(i.v_pairs_level)[: i.depth + 1]
+        d["boxes_level"] = list(i.boxes_level)[: i.depth + 1]
+        d["flops"] = dict(zip(STAGES, list(i.flops)))
+        d["bytes"] = dict(zip(STAGES, list(i.bytes)))
+        return d
+
+    def export_tree(self) -> np.ndarray:
+        out = np.empty((self.n, 3), dtype=np.int32)
+        _check(self._lib.kifmm_plan_export_tree(self._h, out.ctypes.data))
+        return out
+
+    def export_operator(self, which: int) -> np.ndarray:
+        cnt = ctypes.c_int64()
+        _check(self._lib.kifmm_plan_export_operator(self._h, which, None, ctypes.byref(cnt)))
+        out = np.empty(cnt.value, dtype=np.float64)
+        _check(self._lib.kifmm_plan_export_operator(self._h, which, out.ctypes.data, ctypes.byref(cnt)))
+        return out
+
+    def profile(self, enable: bool = True):
+        """Switch per-stage HIP-event timing on/off (clears the totals)."""
+        _check(self._lib.kifmm_profile(self._h, int(bool(enable))))
+
+    def profile_read(self) -> tuple[dict, int]:
+        """(summed ms per stage since profiling was enabled, profiled applies)."""
+        ms = (ctypes.c_double * 7)()
+        calls = ctypes.c_int64()
+        _check(self._lib.kifmm_profile_read(self._h, ms, ctypes.byref(calls)))
+        return dict(zip(STAGES, list(ms))), calls.value
+
+    # ----------------------------------------------------------------- apply
+    def _dtype(self):
+        torch = _torch()
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    def _check_vec(self, x, name):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor) or not x.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if x.dtype != self._dtype():
+            raise TypeError(f"{name} must be {self._dtype()} for a {self.precision} plan")
+        if x.device.index != self.device:
+            raise ValueError(f"{name} is on device {x.device.index}, plan on {self.device}")
+        return x.contiguous()
+
+    def _stream(self):
+        torch = _torch()
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def apply(self, sigma, out=None):
+        sigma = self._check_vec(sigma, "sigma")
+        if sigma.shape != (self.n,):
+            raise ValueError(f"sigma must have shape ({self.n},)")
+        if out is None:
+            out = _torch().empty_like(sigma)
+        _check(self._lib.kifmm_apply(self._h, sigma.data_ptr(), out.data_ptr(), self._stream()))
+        return out
+
+    def apply_adjoint(self, g, out=None):
+        g = self._check_vec(g, "g")
+        if g.shape != (self.n,):
+            raise ValueError(f"g must have shape ({self.n},)")
+        if out is None:
+            out = _torch().empty_like(g)
+        _check(self._lib.kifmm_apply_adjoint(self._h, g.data_ptr(), out.data_ptr(), self._stream()))
+        return out
+
+    def apply_batched(self, sigma, out=None):
+        """sigma: (N, nrhs) tensor; column j is right-hand side j."""
+        torch = _torch()
+        if sigma.dim() != 2 or sigma.shape[0] != self.n:
+            raise ValueError(f"sigma must have shape ({self.n}, nrhs)")
+        nrhs = sigma.shape[1]
+        colmajor = self._check_vec(sigma.t().contiguous(), "sigma")   # (nrhs, N): column-major N x nrhs
+        res = torch.empty_like(colmajor)
+        _check(self._lib.kifmm_apply_batched(self._h, colmajor.data_ptr(), res.data_ptr(), nrhs, self.n,
+                                             self._stream()))
+        res = res.t()
+        if out is not None:
+            out.copy_(res)
+            return out
+        return res.contiguous()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.kifmm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Group:
+    """Several plans whose applies run from one captured HIP graph."""
+
+    def __init__(self, plans):
+        lib = load_library()
+        self._plans = list(plans)
+        arr = (ctypes.c_void_p * len(self._plans))(*[p._h.value for p in self._plans])
+        h = ctypes.c_void_p()
+        _check(lib.kifmm_group_create(arr, len(self._plans), ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    def apply(self, sigmas, outs):
+        n = len(self._plans)
+        if len(sigmas) != n or len(outs) != n:
+            raise ValueError("need one sigma and one output per plan")
+        for pl, s, o in zip(self._plans, sigmas, outs):
+            pl._check_vec(s, "sigma")
+            pl._check_vec(o, "out")
+        sp = (ctypes.c_void_p * n)(*[s.data_ptr() for s in sigmas])
+        op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        _check(self._lib.kifmm_group_apply(self._h, sp, op, self._plans[0]._stream()))
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.kifmm_group_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class KifmmMatvec(torch.autograd.Function):
+        """phi = F sigma with d(loss)/d(sigma) = F^T (d loss / d phi) by the
+        hand-written adjoint passes. F is linear in sigma, so nothing from the
+        forward pass is kept for the backward pass."""
+
+        @staticmethod
+        def forward(ctx, plan, sigma):
+            ctx.plan = plan
+            return plan.apply(sigma.detach())
+
+        @staticmethod
+        def backward(ctx, grad_phi):
+            return None, ctx.plan.apply_adjoint(grad_phi.contiguous())
+
+    return KifmmMatvec
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _make_autograd()
+        return getattr(_LazyAutograd._cls, name)
+
+
+KifmmMatvec = _LazyAutograd()

@@ -1,0 +1,789 @@
+// C ABI of the MI355X KIFMM library: plan construction, device upload and the
+// evaluation passes (complete algorithm of Sec. 4.3) on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kifmm.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace kifmm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+constexpr double kFourPi = 12.566370614359172953850573533118;
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct kifmm_plan_s {
+    kifmm_opts_t opts{};
+    int p = 0;
+    double eps = 0;
+    int leaf_size = 0;
+    HostTree tree;
+    HostOps ops;
+    int k = 0, kp = 0, nep = 0, R = 1, elt = 4;
+    bool on_device = false;
+    int device = 0;
+    // host schedules
+    GGSched h_leafup, h_leafdown, h_m2l;
+    std::vector<GGSched> h_up, h_down;   // indexed by target level
+    // device schedules
+    DevSched d_leafup, d_leafdown, d_m2l;
+    std::vector<DevSched> d_up, d_down;
+    // device data
+    void* pts = nullptr;
+    void* surf = nullptr;
+    int32_t* perm = nullptr;
+    int32_t* leaf_ptr = nullptr;
+    int32_t* near_ptr = nullptr;
+    int32_t* near_leaf = nullptr;
+    int32_t* near_code = nullptr;
+    void *Kt = nullptr, *KtT = nullptr, *Mt = nullptr, *MtT = nullptr, *Lt = nullptr, *LtT = nullptr;
+    void *Sop = nullptr, *SopT = nullptr, *Top = nullptr, *TopT = nullptr;
+    void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
+    std::vector<void*> allocs;
+    size_t device_bytes = 0;
+    kifmm_info_t info{};
+    // stage profiling
+    bool profiling = false;
+    std::vector<std::array<hipEvent_t, 2 * KIFMM_STAGE_COUNT>> prof_events;  // per pending apply
+    std::vector<std::array<hipEvent_t, 2 * KIFMM_STAGE_COUNT>> prof_free;
+    double prof_ms[KIFMM_STAGE_COUNT] = {0};
+    int64_t prof_calls = 0;
+};
+
+struct kifmm_group_s {
+    std::vector<kifmm_plan_t> plans;
+    std::vector<hipStream_t> side;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<const void*> key_sigma;
+    std::vector<void*> key_phi;
+    hipStream_t key_stream = nullptr;
+};
+
+namespace {
+
+void release_device(kifmm_plan_s* pl) {
+    if (!pl->allocs.empty()) {
+        int cur = 0;
+        hipGetDevice(&cur);
+        hipSetDevice(pl->device);
+        for (void* p : pl->allocs) hipFree(p);
+        hipSetDevice(cur);
+    }
+    pl->allocs.clear();
+}
+
+struct Uploader {
+    kifmm_plan_s* pl;
+    size_t limit;
+    int err = KIFMM_OK;
+    std::string msg;
+    void* alloc(size_t bytes) {
+        if (err != KIFMM_OK) return nullptr;
+        if (bytes == 0) bytes = 16;
+        bytes = (bytes + 255) & ~size_t(255);
+        if (limit && pl->device_bytes + bytes > limit) {
+            err = KIFMM_ENOMEM;
+            msg = "opts.mem_limit exceeded (" + std::to_string(pl->device_bytes + bytes) + " bytes needed)";
+            return nullptr;
+        }
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            err = KIFMM_ENOMEM;
+            msg = std::string("hipMalloc failed: ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        pl->allocs.push_back(p);
+        pl->device_bytes += bytes;
+        return p;
+    }
+    template <class V>
+    void* put(const V& v) {
+        size_t bytes = v.size() * sizeof(typename V::value_type);
+        void* p = alloc(bytes);
+        if (p && bytes) {
+            hipError_t e = hipMemcpy(p, v.data(), bytes, hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                err = KIFMM_EHIP;
+                msg = std::string("hipMemcpy failed: ") + hipGetErrorString(e);
+            }
+        }
+        return p;
+    }
+    void* zeros(size_t bytes) {
+        void* p = alloc(bytes);
+        if (p) {
+            hipError_t e = hipMemset(p, 0, (bytes + 255) & ~size_t(255));
+            if (e != hipSuccess) {
+                err = KIFMM_EHIP;
+                msg = std::string("hipMemset failed: ") + hipGetErrorString(e);
+            }
+        }
+        return p;
+    }
+};
+
+// padded table of `nblk` blocks rows x cols (row-major) from FP64 values
+template <typename T>
+std::vector<T> pad_blocks(int nblk, int rows, int cols, int rows_pad, int cols_pad,
+                          const std::function<double(int, int, int)>& f) {
+    std::vector<T> out((size_t)nblk * rows_pad * cols_pad, T(0));
+    for (int b = 0; b < nblk; ++b)
+        for (int i = 0; i < rows; ++i)
+            for (int j = 0; j < cols; ++j) out[((size_t)b * rows_pad + i) * cols_pad + j] = (T)f(b, i, j);
+    return out;
+}
+
+DevSched upload_sched(Uploader& up, const GGSched& s, int elt) {
+    DevSched d;
+    d.n_tiles = s.n_tiles();
+    d.n_chunks = s.n_chunks();
+    d.cp = s.cp;
+    d.max_tile = s.max_tile;
+    if (d.n_tiles == 0) return d;
+    d.tile_tgt0 = (const int32_t*)up.put(s.tile_tgt0);
+    d.tile_ntgt = (const int32_t*)up.put(s.tile_ntgt);
+    d.tile_chunk0 = (const int32_t*)up.put(s.tile_chunk0);
+    if (elt == 4) {
+        std::vector<float> f(s.tile_scale.begin(), s.tile_scale.end());
+        d.tile_scale = up.put(f);
+    } else {
+        d.tile_scale = up.put(s.tile_scale);
+    }
+    d.chunk_cls = (const int32_t*)up.put(s.chunk_cls);
+    d.chunk_src = (const int32_t*)up.put(s.chunk_src);
+    d.chunk_col = (const int32_t*)up.put(s.chunk_col);
+    return d;
+}
+
+int neg_class(int c) {
+    int t[3];
+    offset_of_class(c, t);
+    return class_of_offset(-t[0], -t[1], -t[2]);
+}
+
+template <typename T>
+int upload_tables(kifmm_plan_s* pl, Uploader& up) {
+    const HostOps& o = pl->ops;
+    const int k = o.k, ne = o.n_eq, kp = pl->kp, nep = pl->nep;
+    auto K = [&](int c, int i, int j) { return o.K[((size_t)c * k + i) * k + j]; };
+    pl->Kt = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(c, i, j); }));
+    pl->KtT = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(neg_class(c), j, i); }));
+    auto Mf = [&](int b, int i, int j) { return o.M[((size_t)b * k + i) * k + j]; };
+    auto Lf = [&](int b, int i, int j) { return o.L[((size_t)b * k + i) * k + j]; };
+    pl->Mt = up.put(pad_blocks<T>(8, k, k, kp, kp, Mf));
+    pl->MtT = up.put(pad_blocks<T>(8, k, k, kp, kp, [&](int b, int i, int j) { return Mf(b, j, i); }));
+    pl->Lt = up.put(pad_blocks<T>(8, k, k, kp, kp, Lf));
+    pl->LtT = up.put(pad_blocks<T>(8, k, k, kp, kp, [&](int b, int i, int j) { return Lf(b, j, i); }));
+    pl->Sop = up.put(pad_blocks<T>(1, k, ne, kp, nep, [&](int, int i, int a) { return o.S[(size_t)i * ne + a]; }));
+    pl->SopT = up.put(pad_blocks<T>(1, ne, k, nep, kp, [&](int, int a, int i) { return o.S[(size_t)i * ne + a]; }));
+    pl->Top = up.put(pad_blocks<T>(1, ne, k, nep, kp, [&](int, int a, int i) { return o.T[(size_t)a * k + i]; }));
+    pl->TopT = up.put(pad_blocks<T>(1, k, ne, kp, nep, [&](int, int i, int a) { return o.T[(size_t)a * k + i]; }));
+    std::vector<T> surf(3 * ne);
+    for (int i = 0; i < 3 * ne; ++i) surf[i] = (T)o.outer[i];
+    pl->surf = up.put(surf);
+    std::vector<T> pts(4 * (size_t)pl->tree.n, T(0));
+    for (int64_t i = 0; i < pl->tree.n; ++i)
+        for (int a = 0; a < 3; ++a) pts[4 * i + a] = (T)pl->tree.u[3 * i + a];
+    pl->pts = up.put(pts);
+    return up.err;
+}
+
+void fill_info(kifmm_plan_s* pl, double seconds) {
+    kifmm_info_t& in = pl->info;
+    const HostTree& t = pl->tree;
+    std::memset(&in, 0, sizeof(in));
+    in.depth = t.depth;
+    in.k = pl->ops.k;
+    in.n_eq = pl->ops.n_eq;
+    in.k_pad = pl->kp;
+    in.precision = pl->opts.precision;
+    in.dense_m2l = pl->opts.dense_m2l;
+    in.n = t.n;
+    in.n_leaf = t.n_leaf();
+    in.n_box = t.n_box();
+    in.near_pairs = (int64_t)t.near_leaf.size();
+    int64_t inter = 0;
+    for (int64_t e = 0; e < t.n_leaf(); ++e) {
+        int64_t ne = t.leaf_ptr[e + 1] - t.leaf_ptr[e];
+        for (int32_t q = t.near_ptr[e]; q < t.near_ptr[e + 1]; ++q)
+            inter += ne * (int64_t)(t.leaf_ptr[t.near_leaf[q] + 1] - t.leaf_ptr[t.near_leaf[q]]);
+    }
+    in.p2p_interactions = inter;
+    for (int l = 0; l <= t.depth; ++l) {
+        in.boxes_level[l] = t.level_count(l);
+        in.v_pairs_level[l] = t.v_ptr[t.level_begin[l + 1]] - t.v_ptr[t.level_begin[l]];
+        in.v_pairs += in.v_pairs_level[l];
+    }
+    in.r0 = t.r0;
+    const double k = pl->ops.k, ne = pl->ops.n_eq, nl = (double)t.n_leaf(), N = (double)t.n;
+    const double elt = pl->elt;
+    int64_t nbox_up = 0;
+    for (int l = 2; l < t.depth; ++l) nbox_up += t.level_count(l + 1);
+    const bool far = t.depth >= 2;
+    // 11 flops per point-surface or point-point kernel evaluation (3 sub, 3 mul,
+    // 2 add, rsqrt, multiply-add)
+    in.flops[KIFMM_STAGE_P2M] = far ? 11.0 * N * ne + 2.0 * k * ne * nl : 0;
+    in.flops[KIFMM_STAGE_M2M] = far ? 2.0 * k * k * (double)nbox_up : 0;
+    in.flops[KIFMM_STAGE_M2L] = 2.0 * k * k * (double)in.v_pairs;
+    in.flops[KIFMM_STAGE_L2L] = far ? 2.0 * k * k * (double)nbox_up : 0;
+    in.flops[KIFMM_STAGE_L2P] = far ? 11.0 * N * ne + 2.0 * k * ne * nl : 0;
+    in.flops[KIFMM_STAGE_P2P] = 11.0 * (double)inter;
+    int64_t nbox_m2l = 0;
+    for (int l = 2; l <= t.depth; ++l) nbox_m2l += t.level_count(l);
+    in.bytes[KIFMM_STAGE_P2M] = far ? N * (16 + elt) + nl * k * elt : 0;
+    in.bytes[KIFMM_STAGE_M2M] = far ? 2.0 * nbox_up * k * elt : 0;
+    in.bytes[KIFMM_STAGE_M2L] = 2.0 * nbox_m2l * k * elt + (double)NCLASS * k * k * elt;
+    in.bytes[KIFMM_STAGE_L2L] = far ? 3.0 * nbox_up * k * elt : 0;
+    in.bytes[KIFMM_STAGE_L2P] = far ? nl * k * elt + N * (16 + elt) : 0;
+    in.bytes[KIFMM_STAGE_P2P] = N * (16 + 2 * elt + 4);
+    in.bytes[KIFMM_STAGE_PERM] = N * (2 * elt + 4);
+    in.device_bytes = pl->device_bytes;
+    in.m2l_tile_targets = pl->h_m2l.max_tile;
+    in.sigma0 = pl->ops.sigma0;
+    in.plan_seconds = seconds;
+}
+
+int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
+    const HostTree& t = pl->tree;
+    const int L = t.depth;
+    pl->h_leafup = GGSched();
+    pl->h_leafdown = GGSched();
+    pl->h_m2l = GGSched();
+    pl->h_up.assign(L + 1, GGSched());
+    pl->h_down.assign(L + 1, GGSched());
+    const int cp = 16 / pl->R;
+    pl->h_leafup.cp = pl->h_leafdown.cp = pl->h_m2l.cp = cp;
+    for (auto& s : pl->h_up) s.cp = cp;
+    for (auto& s : pl->h_down) s.cp = cp;
+    if (L < 2) return KIFMM_OK;
+    const int64_t nleaf = t.n_leaf();
+    const int64_t lb = t.level_begin[L];
+    const int leaf_tile = std::max(16, 128 / pl->R);
+    {
+        std::vector<int32_t> ptr(nleaf + 1), src(nleaf), cls(nleaf, 0);
+        for (int64_t e = 0; e <= nleaf; ++e) ptr[e] = (int32_t)e;
+        for (int64_t e = 0; e < nleaf; ++e) src[e] = (int32_t)e;
+        gg_append(pl->h_leafup, lb, nleaf, ptr.data(), src.data(), cls.data(), leaf_tile, 1.0 / kFourPi);
+        for (int64_t e = 0; e < nleaf; ++e) src[e] = (int32_t)(lb + e);
+        gg_append(pl->h_leafdown, 0, nleaf, ptr.data(), src.data(), cls.data(), leaf_tile, 1.0);
+    }
+    const int updown_tile = std::max(16, 64 / pl->R);
+    for (int l = 2; l < L; ++l) {
+        // targets at level l, sources their children at level l+1 (class = octant)
+        const int64_t b0 = t.level_begin[l], nb = t.level_count(l);
+        std::vector<int32_t> ptr(1, 0), src, cls;
+        for (int64_t b = 0; b < nb; ++b) {
+            for (int o = 0; o < 8; ++o) {
+                int32_t ch = t.box_child[8 * (b0 + b) + o];
+                if (ch >= 0) {
+                    src.push_back(ch);
+                    cls.push_back(o);
+                }
+            }
+            ptr.push_back((int32_t)src.size());
+        }
+        gg_append(pl->h_up[l], b0, nb, ptr.data(), src.data(), cls.data(), updown_tile, 1.0);
+    }
+    for (int l = 3; l <= L; ++l) {
+        // targets at level l, source their parent at level l-1 (class = own octant)
+        const int64_t b0 = t.level_begin[l], nb = t.level_count(l);
+        std::vector<int32_t> ptr(nb + 1), src(nb), cls(nb);
+        for (int64_t b = 0; b < nb; ++b) {
+            ptr[b] = (int32_t)b;
+            src[b] = t.box_parent[b0 + b];
+            cls[b] = (int32_t)(t.box_key[b0 + b] & 7);
+        }
+        ptr[nb] = (int32_t)nb;
+        gg_append(pl->h_down[l], b0, nb, ptr.data(), src.data(), cls.data(), updown_tile, 1.0);
+    }
+    for (int l = 2; l <= L; ++l) {
+        // every box of levels 2..L gets a tile slot, so that M2L initialises its
+        // local coefficients even when its interaction field is empty
+        const int64_t b0 = t.level_begin[l], nb = t.level_count(l);
+        gg_append(pl->h_m2l, b0, nb, &t.v_ptr[b0], t.v_src.data(), t.v_cls.data(), m2l_tile,
+                  1.0 / t.half_width(l));
+    }
+    return KIFMM_OK;
+}
+
+int default_m2l_tile(const kifmm_plan_s* pl) {
+    if (pl->opts.tile_targets > 0) return pl->opts.tile_targets;
+    const size_t budget = gg_lds_limit();
+    int tile = (int)(budget / ((size_t)(pl->kp + 4) * pl->elt * pl->R));
+    tile = std::min(tile, 256);
+    return std::max(tile, 1);
+}
+
+int check_plan_for_apply(kifmm_plan_t plan) {
+    if (!plan) return fail(KIFMM_EINVAL, "plan is NULL");
+    if (!plan->on_device) return fail(KIFMM_ESTATE, "plan was built host-only (opts.device = -1)");
+    return KIFMM_OK;
+}
+
+#define KIFMM_HIP(call)                                                                  \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) return fail(KIFMM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld, bool adjoint,
+               hipStream_t st) {
+    const HostTree& t = pl->tree;
+    const int L = t.depth;
+    const int elt = pl->elt, R = pl->R, kp = pl->kp, nep = pl->nep;
+    const int MBk = kp / 16, KPk = kp / 16, MBe = nep / 16, KPe = nep / 16;
+    const int64_t nleaf = t.n_leaf();
+    int cur = 0;
+    KIFMM_HIP(hipGetDevice(&cur));
+    if (cur != pl->device) KIFMM_HIP(hipSetDevice(pl->device));
+    std::array<hipEvent_t, 2 * KIFMM_STAGE_COUNT>* ev = nullptr;
+    if (pl->profiling) {
+        if (pl->prof_free.empty()) {
+            std::array<hipEvent_t, 2 * KIFMM_STAGE_COUNT> a{};
+            for (auto& e : a) KIFMM_HIP(hipEventCreate(&e));
+            pl->prof_free.push_back(a);
+        }
+        pl->prof_events.push_back(pl->prof_free.back());
+        pl->prof_free.pop_back();
+        ev = &pl->prof_events.back();
+    }
+    auto mark = [&](int stage, int end) -> hipError_t {
+        return ev ? hipEventRecord((*ev)[2 * stage + end], st) : hipSuccess;
+    };
+    // Stages without work still record both events so that every pair is valid.
+    KIFMM_HIP(mark(KIFMM_STAGE_PERM, 0));
+    KIFMM_HIP(launch_permute_in(elt, R, t.n, pl->perm, in, ld, nrhs, pl->sig_s, st));
+    KIFMM_HIP(mark(KIFMM_STAGE_PERM, 1));
+    const bool far = L >= 2;
+    KIFMM_HIP(mark(KIFMM_STAGE_P2M, 0));
+    if (far) {
+        // upward (forward) / L2T^T (adjoint): surface evaluation and the leaf GEMM
+        KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->surf, pl->ops.n_eq, nep,
+                                      pl->C, st));
+        KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->C, nep,
+                            adjoint ? pl->P : pl->Q, kp, R, 0, st));
+    }
+    KIFMM_HIP(mark(KIFMM_STAGE_P2M, 1));
+    KIFMM_HIP(mark(KIFMM_STAGE_M2M, 0));
+    if (far) {
+        if (!adjoint) {
+            for (int l = L - 1; l >= 2; --l)   // M2M
+                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->Mt, MBk, KPk, pl->Q, kp, pl->Q, kp, R, 0, st));
+        } else {
+            for (int l = L - 1; l >= 2; --l)   // L2L^T: parents at l from children at l+1
+                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->LtT, MBk, KPk, pl->P, kp, pl->P, kp, R, 0, st));
+        }
+    }
+    KIFMM_HIP(mark(KIFMM_STAGE_M2M, 1));
+    KIFMM_HIP(mark(KIFMM_STAGE_M2L, 0));
+    if (far) {
+        if (!adjoint)
+            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->Q, kp, pl->P, kp, R, 0, st));
+        else
+            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->KtT, MBk, KPk, pl->P, kp, pl->Q, kp, R, 0, st));
+    }
+    KIFMM_HIP(mark(KIFMM_STAGE_M2L, 1));
+    KIFMM_HIP(mark(KIFMM_STAGE_L2L, 0));
+    if (far) {
+        if (!adjoint) {
+            for (int l = 3; l <= L; ++l)       // L2L
+                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->Lt, MBk, KPk, pl->P, kp, pl->P, kp, R, 1, st));
+        } else {
+            for (int l = 3; l <= L; ++l)       // M2M^T: children at l from parents at l-1
+                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->MtT, MBk, KPk, pl->Q, kp, pl->Q, kp, R, 1, st));
+        }
+    }
+    KIFMM_HIP(mark(KIFMM_STAGE_L2L, 1));
+    KIFMM_HIP(mark(KIFMM_STAGE_L2P, 0));
+    if (far) {
+        if (!adjoint)
+            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, pl->P, kp, pl->E, nep, R, 0, st));
+        else
+            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, pl->Q, kp, pl->E, nep, R, 0, st));
+    }
+    KIFMM_HIP(mark(KIFMM_STAGE_L2P, 1));
+    const double rL = t.half_width(L);
+    KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
+    KIFMM_HIP(launch_eval_targets(elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->near_ptr, pl->near_leaf,
+                                  pl->near_code, far ? pl->E : nullptr, pl->surf, pl->ops.n_eq, nep,
+                                  1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
+    KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
+    if (cur != pl->device) KIFMM_HIP(hipSetDevice(cur));
+    return KIFMM_OK;
+}
+
+int collect_profile(kifmm_plan_s* pl) {
+    for (auto& a : pl->prof_events) {
+        for (int s = 0; s < KIFMM_STAGE_COUNT; ++s) {
+            float ms = 0.f;
+            KIFMM_HIP(hipEventSynchronize(a[2 * s + 1]));
+            KIFMM_HIP(hipEventElapsedTime(&ms, a[2 * s], a[2 * s + 1]));
+            pl->prof_ms[s] += ms;
+        }
+        pl->prof_calls++;
+        pl->prof_free.push_back(a);
+    }
+    pl->prof_events.clear();
+    return KIFMM_OK;
+}
+
+void destroy_profile_events(kifmm_plan_s* pl) {
+    for (auto& a : pl->prof_events)
+        for (auto e : a) (void)hipEventDestroy(e);
+    for (auto& a : pl->prof_free)
+        for (auto e : a) (void)hipEventDestroy(e);
+    pl->prof_events.clear();
+    pl->prof_free.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int kifmm_opts_default(kifmm_opts_t* o) {
+    if (!o) return fail(KIFMM_EINVAL, "opts is NULL");
+    std::memset(o, 0, sizeof(*o));
+    o->precision = KIFMM_FP32;
+    o->cd = 0.5;
+    o->pinv_rcond = 1e-10;
+    o->depth = 0;
+    o->max_depth = 16;
+    o->dense_m2l = 0;
+    o->max_nrhs = 1;
+    o->device = 0;
+    o->mem_limit = 0;
+    o->tile_targets = 0;
+    return KIFMM_OK;
+}
+
+int kifmm_plan(const double* points, int64_t n, int p, double eps, int leaf_size, kifmm_plan_t* out) {
+    return kifmm_plan_ex(points, n, p, eps, leaf_size, nullptr, out);
+}
+
+int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_size,
+                  const kifmm_opts_t* opts, kifmm_plan_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(KIFMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!points) return fail(KIFMM_EINVAL, "points is NULL");
+    kifmm_opts_t o;
+    kifmm_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.precision != KIFMM_FP64 && o.precision != KIFMM_FP32 && o.precision != KIFMM_BF16X3)
+        return fail(KIFMM_EINVAL, "unknown precision");
+    if (o.precision == KIFMM_BF16X3) return fail(KIFMM_EINVAL, "KIFMM_BF16X3 is not available in this build");
+    if (o.max_nrhs < 1 || o.max_nrhs > 16) return fail(KIFMM_EINVAL, "max_nrhs must be in [1, 16]");
+    if (o.tile_targets < 0 || o.tile_targets > 4096) return fail(KIFMM_EINVAL, "tile_targets must be in [0, 4096]");
+    if (o.device < -1) return fail(KIFMM_EINVAL, "device must be >= -1");
+    const auto t0 = std::chrono::steady_clock::now();
+    kifmm_plan_s* pl = new (std::nothrow) kifmm_plan_s();
+    if (!pl) return fail(KIFMM_ENOMEM, "host allocation failed");
+    pl->opts = o;
+    pl->p = p;
+    pl->eps = eps;
+    pl->leaf_size = leaf_size;
+    pl->elt = o.precision == KIFMM_FP64 ? 8 : 4;
+    pl->R = 1;
+    while (pl->R < o.max_nrhs) pl->R <<= 1;
+    try {
+        if (p < 2 || p > 16) throw PlanError{KIFMM_EINVAL, "p must be in [2, 16]"};
+        if (!(eps >= 0.0 && eps < 1.0)) throw PlanError{KIFMM_EINVAL, "eps must be in [0, 1)"};
+        pl->tree = build_host_tree(points, n, leaf_size, o.depth, o.max_depth);
+        pl->ops = build_host_ops(p, eps, leaf_size, o.cd, o.pinv_rcond, o.dense_m2l != 0);
+    } catch (const PlanError& e) {
+        delete pl;
+        return fail(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+        delete pl;
+        return fail(KIFMM_ENOMEM, "host allocation failed");
+    }
+    pl->k = pl->ops.k;
+    pl->kp = (pl->k + 15) / 16 * 16;
+    pl->nep = (pl->ops.n_eq + 15) / 16 * 16;
+    if (pl->kp > 19 * 16 || pl->nep > 19 * 16) {
+        delete pl;
+        return fail(KIFMM_EINVAL, "n_eq too large for the device kernels (p <= 8 supported)");
+    }
+    build_schedules(pl, default_m2l_tile(pl));
+    if (o.device >= 0) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) {
+            delete pl;
+            return fail(KIFMM_EHIP, "HIP device " + std::to_string(o.device) + " not available");
+        }
+        int cur = 0;
+        hipGetDevice(&cur);
+        hipSetDevice(o.device);
+        pl->device = o.device;
+        Uploader up{pl, o.mem_limit};
+        const HostTree& t = pl->tree;
+        pl->perm = (int32_t*)up.put(t.perm);
+        pl->leaf_ptr = (int32_t*)up.put(t.leaf_ptr);
+        pl->near_ptr = (int32_t*)up.put(t.near_ptr);
+        pl->near_leaf = (int32_t*)up.put(t.near_leaf);
+        pl->near_code = (int32_t*)up.put(t.near_code);
+        if (pl->elt == 4)
+            upload_tables<float>(pl, up);
+        else
+            upload_tables<double>(pl, up);
+        const size_t elt = pl->elt, R = pl->R;
+        pl->sig_s = up.zeros((size_t)t.n * R * elt);
+        if (t.depth >= 2) {
+            pl->C = up.zeros((size_t)t.n_leaf() * R * pl->nep * elt);
+            pl->E = up.zeros((size_t)t.n_leaf() * R * pl->nep * elt);
+            pl->Q = up.zeros((size_t)t.n_box() * R * pl->kp * elt);
+            pl->P = up.zeros((size_t)t.n_box() * R * pl->kp * elt);
+        }
+        pl->d_leafup = upload_sched(up, pl->h_leafup, pl->elt);
+        pl->d_leafdown = upload_sched(up, pl->h_leafdown, pl->elt);
+        pl->d_m2l = upload_sched(up, pl->h_m2l, pl->elt);
+        pl->d_up.resize(pl->h_up.size());
+        pl->d_down.resize(pl->h_down.size());
+        for (size_t l = 0; l < pl->h_up.size(); ++l) pl->d_up[l] = upload_sched(up, pl->h_up[l], pl->elt);
+        for (size_t l = 0; l < pl->h_down.size(); ++l) pl->d_down[l] = upload_sched(up, pl->h_down[l], pl->elt);
+        hipDeviceSynchronize();
+        hipSetDevice(cur);
+        if (up.err != KIFMM_OK) {
+            int code = up.err;
+            std::string msg = up.msg;
+            release_device(pl);
+            delete pl;
+            return fail(code, msg);
+        }
+        pl->on_device = true;
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    fill_info(pl, secs);
+    *out = pl;
+    return KIFMM_OK;
+}
+
+int kifmm_apply(kifmm_plan_t plan, const void* sigma, void* phi, void* stream) {
+    int rc = check_plan_for_apply(plan);
+    if (rc) return rc;
+    if (!sigma || !phi) return fail(KIFMM_EINVAL, "sigma and phi must be non-NULL");
+    if (sigma == phi) return fail(KIFMM_EINVAL, "sigma and phi must not alias");
+    return run_passes(plan, sigma, phi, 1, plan->tree.n, false, (hipStream_t)stream);
+}
+
+int kifmm_apply_adjoint(kifmm_plan_t plan, const void* g, void* out, void* stream) {
+    int rc = check_plan_for_apply(plan);
+    if (rc) return rc;
+    if (!g || !out) return fail(KIFMM_EINVAL, "g and out must be non-NULL");
+    if (g == out) return fail(KIFMM_EINVAL, "g and out must not alias");
+    return run_passes(plan, g, out, 1, plan->tree.n, true, (hipStream_t)stream);
+}
+
+int kifmm_apply_batched(kifmm_plan_t plan, const void* sigma, void* phi, int nrhs, int64_t ld, void* stream) {
+    int rc = check_plan_for_apply(plan);
+    if (rc) return rc;
+    if (!sigma || !phi) return fail(KIFMM_EINVAL, "sigma and phi must be non-NULL");
+    if (sigma == phi) return fail(KIFMM_EINVAL, "sigma and phi must not alias");
+    if (nrhs < 1 || nrhs > plan->opts.max_nrhs)
+        return fail(KIFMM_EINVAL, "nrhs must be in [1, opts.max_nrhs] (" + std::to_string(plan->opts.max_nrhs) + ")");
+    if (ld < plan->tree.n) return fail(KIFMM_EINVAL, "ld must be >= n");
+    return run_passes(plan, sigma, phi, nrhs, ld, false, (hipStream_t)stream);
+}
+
+int kifmm_plan_info(kifmm_plan_t plan, kifmm_info_t* info) {
+    if (!plan || !info) return fail(KIFMM_EINVAL, "plan and info must be non-NULL");
+    *info = plan->info;
+    return KIFMM_OK;
+}
+
+int kifmm_plan_export_tree(kifmm_plan_t plan, int32_t* leaf_coords) {
+    if (!plan || !leaf_coords) return fail(KIFMM_EINVAL, "plan and leaf_coords must be non-NULL");
+    std::memcpy(leaf_coords, plan->tree.leaf_coords.data(), sizeof(int32_t) * 3 * plan->tree.n);
+    return KIFMM_OK;
+}
+
+int kifmm_plan_export_operator(kifmm_plan_t plan, int which, double* out, int64_t* count) {
+    if (!plan) return fail(KIFMM_EINVAL, "plan is NULL");
+    const HostOps& o = plan->ops;
+    const std::vector<double>* v = nullptr;
+    switch (which) {
+        case 0: v = &o.sing; break;
+        case 1: v = &o.U; break;
+        case 2: v = &o.S; break;
+        case 3: v = &o.T; break;
+        case 4: v = &o.M; break;
+        case 5: v = &o.L; break;
+        case 6: v = &o.K; break;
+        default: return fail(KIFMM_EINVAL, "unknown operator id");
+    }
+    if (count) *count = (int64_t)v->size();
+    if (out) std::memcpy(out, v->data(), sizeof(double) * v->size());
+    return KIFMM_OK;
+}
+
+int kifmm_profile(kifmm_plan_t plan, int enable) {
+    int rc = check_plan_for_apply(plan);
+    if (rc) return rc;
+    if (!plan->prof_events.empty()) {
+        rc = collect_profile(plan);
+        if (rc) return rc;
+    }
+    plan->profiling = enable != 0;
+    std::fill(plan->prof_ms, plan->prof_ms + KIFMM_STAGE_COUNT, 0.0);
+    plan->prof_calls = 0;
+    return KIFMM_OK;
+}
+
+int kifmm_profile_read(kifmm_plan_t plan, double* ms, int64_t* calls) {
+    int rc = check_plan_for_apply(plan);
+    if (rc) return rc;
+    if (!ms) return fail(KIFMM_EINVAL, "ms is NULL");
+    rc = collect_profile(plan);
+    if (rc) return rc;
+    std::copy(plan->prof_ms, plan->prof_ms + KIFMM_STAGE_COUNT, ms);
+    if (calls) *calls = plan->prof_calls;
+    return KIFMM_OK;
+}
+
+void kifmm_destroy(kifmm_plan_t plan) {
+    if (!plan) return;
+    if (plan->on_device) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(plan->device);
+        destroy_profile_events(plan);
+        (void)hipSetDevice(cur);
+    }
+    release_device(plan);
+    delete plan;
+}
+
+const char* kifmm_last_error(void) { return g_last_error.c_str(); }
+
+int kifmm_group_create(const kifmm_plan_t* plans, int nplans, kifmm_group_t* out) {
+    if (!out) return fail(KIFMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!plans || nplans < 1) return fail(KIFMM_EINVAL, "need at least one plan");
+    for (int i = 0; i < nplans; ++i) {
+        int rc = check_plan_for_apply(plans[i]);
+        if (rc) return rc;
+        if (plans[i]->device != plans[0]->device || plans[i]->opts.precision != plans[0]->opts.precision)
+            return fail(KIFMM_EINVAL, "plans of a group must share device and precision");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(KIFMM_EINVAL, "a plan appears twice in the group");
+    }
+    kifmm_group_s* g = new (std::nothrow) kifmm_group_s();
+    if (!g) return fail(KIFMM_ENOMEM, "host allocation failed");
+    g->plans.assign(plans, plans + nplans);
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(plans[0]->device);
+    bool ok = hipEventCreateWithFlags(&g->fork, hipEventDisableTiming) == hipSuccess;
+    g->side.resize(nplans, nullptr);
+    g->join.resize(nplans, nullptr);
+    for (int i = 0; ok && i < nplans; ++i) {
+        ok = hipStreamCreateWithFlags(&g->side[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&g->join[i], hipEventDisableTiming) == hipSuccess;
+    }
+    hipSetDevice(cur);
+    if (!ok) {
+        kifmm_group_destroy(g);
+        return fail(KIFMM_EHIP, "stream/event creation failed");
+    }
+    *out = g;
+    return KIFMM_OK;
+}
+
+int kifmm_group_apply(kifmm_group_t g, const void* const* sigma, void* const* phi, void* stream) {
+    if (!g || !sigma || !phi) return fail(KIFMM_EINVAL, "group, sigma and phi must be non-NULL");
+    const int np = (int)g->plans.size();
+    for (int i = 0; i < np; ++i)
+        if (!sigma[i] || !phi[i] || sigma[i] == phi[i]) return fail(KIFMM_EINVAL, "bad sigma/phi pointer");
+    hipStream_t st = (hipStream_t)stream;
+    bool same = g->exec != nullptr && g->key_stream == st;
+    for (int i = 0; same && i < np; ++i) same = g->key_sigma[i] == sigma[i] && g->key_phi[i] == phi[i];
+    int cur = 0;
+    KIFMM_HIP(hipGetDevice(&cur));
+    KIFMM_HIP(hipSetDevice(g->plans[0]->device));
+    if (!same) {
+        if (g->exec) hipGraphExecDestroy(g->exec);
+        if (g->graph) hipGraphDestroy(g->graph);
+        g->exec = nullptr;
+        g->graph = nullptr;
+        hipStream_t cap = st;
+        hipStream_t own = nullptr;
+        if (cap == nullptr) {   // the null stream cannot be captured: capture on a private stream
+            KIFMM_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+            cap = own;
+        }
+        KIFMM_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        int rc = KIFMM_OK;
+        hipEventRecord(g->fork, cap);
+        for (int i = 0; i < np && rc == KIFMM_OK; ++i) {
+            hipStreamWaitEvent(g->side[i], g->fork, 0);
+            rc = run_passes(g->plans[i], sigma[i], phi[i], 1, g->plans[i]->tree.n, false, g->side[i]);
+            hipEventRecord(g->join[i], g->side[i]);
+            hipStreamWaitEvent(cap, g->join[i], 0);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(cap, &graph);
+        if (rc != KIFMM_OK || e != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            if (own) hipStreamDestroy(own);
+            hipSetDevice(cur);
+            return rc != KIFMM_OK ? rc : fail(KIFMM_EHIP, std::string("graph capture failed: ") + hipGetErrorString(e));
+        }
+        if (own) hipStreamDestroy(own);
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(graph);
+            hipSetDevice(cur);
+            return fail(KIFMM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        g->graph = graph;
+        g->key_sigma.assign(sigma, sigma + np);
+        g->key_phi.assign(phi, phi + np);
+        g->key_stream = st;
+    }
+    KIFMM_HIP(hipGraphLaunch(g->exec, st));
+    KIFMM_HIP(hipSetDevice(cur));
+    return KIFMM_OK;
+}
+
+void kifmm_group_destroy(kifmm_group_t g) {
+    if (!g) return;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    for (auto s : g->side)
+        if (s) hipStreamDestroy(s);
+    for (auto e : g->join)
+        if (e) hipEventDestroy(e);
+    if (g->fork) hipEventDestroy(g->fork);
+    delete g;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// Device kernels of the KIFMM evaluation (gfx950) and their host launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kifmm {
+
+// Device view of a grouped gather GEMM schedule (see GGSched in plan.h).
+struct DevSched {
+    int n_tiles = 0;
+    int n_chunks = 0;
+    int cp = 16;
+    int max_tile = 0;
+    const int32_t* tile_tgt0 = nullptr;
+    const int32_t* tile_ntgt = nullptr;
+    const int32_t* tile_chunk0 = nullptr;
+    const void* tile_scale = nullptr;   // float or double per precision
+    const int32_t* chunk_cls = nullptr;
+    const int32_t* chunk_src = nullptr;
+    const int32_t* chunk_col = nullptr;
+};
+
+// Y[tgt] (+)= scale * sum_chunks A[cls] X[src] for every tile of `s`.
+//  A: per-class (MB*16) x (KP16*16) row-major blocks (zero padded);
+//  X rows of length ldx (>= KP16*16), Y rows of length ldy (>= MB*16);
+//  row of (box b, right-hand side r) is b*R + r.
+// elt = 4 (FP32 MFMA) or 8 (FP64 MFMA). Returns a hipError_t.
+hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, const void* X,
+                     int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st);
+
+// Largest dynamic LDS the grouped GEMM may use per workgroup (bytes).
+size_t gg_lds_limit();
+// Per-workgroup LDS bytes of a tile of `cols` columns with MB row blocks.
+size_t gg_lds_bytes(int elt, int MB, int cols);
+
+// sig_s[i*R + r] = r < nrhs ? sigma[perm[i] + r*ld] : 0
+hipError_t launch_permute_in(int elt, int R, int64_t n, const int32_t* perm, const void* sigma,
+                             int64_t ld, int nrhs, void* sig_s, hipStream_t st);
+
+// C[(leaf*R + r)*nep + a] = sum_{j in leaf} sig_s[j*R+r] / |surf_a - u_j|   (a < n_eq; 0 for a < nep)
+hipError_t launch_eval_surface(int elt, int R, int64_t n_leaf, const void* pts, const void* sig_s,
+                               const int32_t* leaf_ptr, const void* surf, int n_eq, int nep,
+                               void* C, hipStream_t st);
+
+// out[perm[i] + r*ld] = near_scale * sum_{near j != i} sig_s[j] / |u_i - u_j + 2 d|
+//                     + far_scale  * sum_a E[(leaf*R+r)*nep + a] / |u_i - surf_a|   (if E != null)
+hipError_t launch_eval_targets(int elt, int R, int64_t n_leaf, const void* pts, const void* sig_s,
+                               const int32_t* leaf_ptr, const int32_t* near_ptr,
+                               const int32_t* near_leaf, const int32_t* near_code, const void* E,
+                               const void* surf, int n_eq, int nep, double near_scale,
+                               double far_scale, const int32_t* perm, void* out, int64_t ld,
+                               int nrhs, hipStream_t st);
+
+}  // namespace kifmm

@@ -1,0 +1,478 @@
+// Host-side plan construction: octree and lists (Sec. 2.1), FP64 operators
+// (Sec. 2.2, 3.1, 3.3, 4.1) and grouped-GEMM work schedules.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "linalg.h"
+
+namespace kifmm {
+
+namespace {
+
+constexpr double kFourPi = 12.566370614359172953850573533118;
+
+template <class F>
+void parallel_for(int64_t n, F&& f) {
+    unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 2 || hw == 1) {
+        for (int64_t i = 0; i < n; ++i) f(i);
+        return;
+    }
+    int nt = (int)std::min<int64_t>(hw, n);
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&, t] {
+            for (int64_t i = t; i < n; i += nt) f(i);
+        });
+    for (auto& x : th) x.join();
+}
+
+inline uint64_t spread3(uint64_t v) {
+    // spread the low 21 bits of v so that bit b lands on bit 3b
+    v &= 0x1fffff;
+    v = (v | (v << 32)) & 0x1f00000000ffffULL;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffULL;
+    v = (v | (v << 8)) & 0x100f00f00f00f00fULL;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ULL;
+    v = (v | (v << 2)) & 0x1249249249249249ULL;
+    return v;
+}
+
+inline uint64_t compact3(uint64_t v) {
+    v &= 0x1249249249249249ULL;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ULL;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00fULL;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffULL;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffULL;
+    v = (v ^ (v >> 32)) & 0x1fffff;
+    return v;
+}
+
+inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) {
+    return (spread3(x) << 2) | (spread3(y) << 1) | spread3(z);
+}
+
+inline void unmorton(uint64_t key, int64_t* c) {
+    c[0] = (int64_t)compact3(key >> 2);
+    c[1] = (int64_t)compact3(key >> 1);
+    c[2] = (int64_t)compact3(key);
+}
+
+// index of `key` in the sorted range [b, e) of `keys`, or -1
+inline int64_t find_key(const std::vector<uint64_t>& keys, int64_t b, int64_t e, uint64_t key) {
+    auto it = std::lower_bound(keys.begin() + b, keys.begin() + e, key);
+    if (it != keys.begin() + e && *it == key) return it - keys.begin();
+    return -1;
+}
+
+inline double kernel(const double* x, const double* y) {
+    double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+    double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+    return r > 0 ? 1.0 / (kFourPi * r) : 0.0;
+}
+
+// G(X, Y) for point lists X (m x 3) and Y (n x 3), row-major m x n
+std::vector<double> kernel_matrix(int m, const double* X, int n, const double* Y) {
+    std::vector<double> G((size_t)m * n);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) G[(size_t)i * n + j] = kernel(X + 3 * i, Y + 3 * j);
+    return G;
+}
+
+std::vector<double> transpose(int m, int n, const double* A) {
+    std::vector<double> B((size_t)m * n);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) B[(size_t)j * m + i] = A[(size_t)i * n + j];
+    return B;
+}
+
+}  // namespace
+
+int class_of_offset(int tx, int ty, int tz) {
+    if (std::max(std::abs(tx), std::max(std::abs(ty), std::abs(tz))) < 2) return -1;
+    if (std::abs(tx) > 3 || std::abs(ty) > 3 || std::abs(tz) > 3) return -1;
+    int id = 0;
+    for (int a = -3; a <= 3; ++a)
+        for (int b = -3; b <= 3; ++b)
+            for (int c = -3; c <= 3; ++c) {
+                if (std::max(std::abs(a), std::max(std::abs(b), std::abs(c))) < 2) continue;
+                if (a == tx && b == ty && c == tz) return id;
+                ++id;
+            }
+    return -1;
+}
+
+void offset_of_class(int cls, int* t) {
+    int id = 0;
+    for (int a = -3; a <= 3; ++a)
+        for (int b = -3; b <= 3; ++b)
+            for (int c = -3; c <= 3; ++c) {
+                if (std::max(std::abs(a), std::max(std::abs(b), std::abs(c))) < 2) continue;
+                if (id == cls) {
+                    t[0] = a; t[1] = b; t[2] = c;
+                    return;
+                }
+                ++id;
+            }
+    t[0] = t[1] = t[2] = 0;
+}
+
+HostTree build_host_tree(const double* pts, int64_t n, int leaf_size, int depth_override,
+                         int max_depth) {
+    if (n < 1) throw PlanError{-1, "n must be >= 1"};
+    if (leaf_size < 1) throw PlanError{-1, "leaf_size must be >= 1"};
+    if (max_depth < 0 || max_depth > MAX_LEVEL) throw PlanError{-1, "max_depth must be in [0, 20]"};
+    if (depth_override < 0 || depth_override > MAX_LEVEL) throw PlanError{-1, "depth must be in [0, 20]"};
+    if (n > (int64_t)INT32_MAX / 2) throw PlanError{-1, "n too large"};
+    HostTree t;
+    t.n = n;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) {
+            double v = pts[3 * i + a];
+            if (!std::isfinite(v)) throw PlanError{-4, "non-finite point coordinate at index " + std::to_string(i)};
+            lo[a] = std::min(lo[a], v);
+            hi[a] = std::max(hi[a], v);
+        }
+    double ext = 0;
+    for (int a = 0; a < 3; ++a) {
+        t.centre[a] = (lo[a] + hi[a]) / 2.0;
+        ext = std::max(ext, hi[a] - lo[a]);
+    }
+    t.r0 = ext > 0 ? ext / 2.0 * (1.0 + std::ldexp(1.0, -20)) : 1.0;
+    const double qmax = double((1 << QBITS) - 1);
+    std::vector<uint64_t> key(n);
+    std::vector<int64_t> q(3 * n);
+    for (int64_t i = 0; i < n; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            double base = t.centre[a] - t.r0;
+            double v = std::floor((pts[3 * i + a] - base) / (2.0 * t.r0) * double(1 << QBITS));
+            v = std::min(std::max(v, 0.0), qmax);
+            q[3 * i + a] = (int64_t)v;
+        }
+        key[i] = morton(q[3 * i], q[3 * i + 1], q[3 * i + 2]);
+    }
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    std::vector<uint64_t> skey(n);
+    for (int64_t i = 0; i < n; ++i) skey[i] = key[order[i]];
+
+    int L = depth_override;
+    if (L == 0 && depth_override == 0) {
+        L = max_depth;
+        for (int l = 0; l <= max_depth; ++l) {
+            int shift = 3 * (QBITS - l);
+            int64_t run = 1, worst = 1;
+            for (int64_t i = 1; i < n; ++i) {
+                if ((skey[i] >> shift) == (skey[i - 1] >> shift)) {
+                    ++run;
+                } else {
+                    run = 1;
+                }
+                worst = std::max(worst, run);
+            }
+            if (worst <= leaf_size) {
+                L = l;
+                break;
+            }
+        }
+    }
+    t.depth = L;
+    t.perm = order;
+
+    // per-level unique keys, leaves first
+    std::vector<std::vector<uint64_t>> lk(L + 1);
+    const int lshift = 3 * (QBITS - L);
+    t.leaf_ptr.clear();
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t k = skey[i] >> lshift;
+        if (lk[L].empty() || lk[L].back() != k) {
+            lk[L].push_back(k);
+            t.leaf_ptr.push_back((int32_t)i);
+        }
+    }
+    t.leaf_ptr.push_back((int32_t)n);
+    for (int l = L - 1; l >= 0; --l) {
+        for (uint64_t k : lk[l + 1]) {
+            uint64_t pk = k >> 3;
+            if (lk[l].empty() || lk[l].back() != pk) lk[l].push_back(pk);
+        }
+    }
+    t.level_begin.assign(L + 2, 0);
+    for (int l = 0; l <= L; ++l) t.level_begin[l + 1] = t.level_begin[l] + (int64_t)lk[l].size();
+    const int64_t nb = t.level_begin[L + 1];
+    t.box_key.resize(nb);
+    for (int l = 0; l <= L; ++l)
+        std::copy(lk[l].begin(), lk[l].end(), t.box_key.begin() + t.level_begin[l]);
+    t.box_parent.assign(nb, -1);
+    t.box_child.assign(8 * nb, -1);
+    for (int l = 1; l <= L; ++l) {
+        for (int64_t b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b) {
+            int64_t p = find_key(t.box_key, t.level_begin[l - 1], t.level_begin[l], t.box_key[b] >> 3);
+            t.box_parent[b] = (int32_t)p;
+            t.box_child[8 * p + (t.box_key[b] & 7)] = (int32_t)b;
+        }
+    }
+
+    // leaf-unit coordinates of the sorted points
+    const double rL = t.half_width(L);
+    t.u.resize(3 * n);
+    const int64_t nleaf = t.n_leaf();
+    for (int64_t e = 0; e < nleaf; ++e) {
+        int64_t c[3];
+        unmorton(t.box_key[t.level_begin[L] + e], c);
+        for (int32_t i = t.leaf_ptr[e]; i < t.leaf_ptr[e + 1]; ++i) {
+            for (int a = 0; a < 3; ++a) {
+                double centre = (t.centre[a] - t.r0) + (2.0 * double(c[a]) + 1.0) * rL;
+                t.u[3 * (int64_t)i + a] = (pts[3 * (int64_t)order[i] + a] - centre) / rL;
+            }
+        }
+    }
+    t.leaf_coords.resize(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) t.leaf_coords[3 * i + a] = (int32_t)(q[3 * i + a] >> (QBITS - L));
+
+    // near fields of the leaves
+    const int64_t side = int64_t(1) << L;
+    t.near_ptr.assign(nleaf + 1, 0);
+    {
+        std::vector<std::vector<int32_t>> nl(nleaf), nc(nleaf);
+        parallel_for(nleaf, [&](int64_t e) {
+            int64_t c[3];
+            unmorton(t.box_key[t.level_begin[L] + e], c);
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        int64_t b[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                        if (b[0] < 0 || b[1] < 0 || b[2] < 0 || b[0] >= side || b[1] >= side || b[2] >= side) continue;
+                        int64_t j = find_key(t.box_key, t.level_begin[L], t.level_begin[L + 1],
+                                             morton(b[0], b[1], b[2]));
+                        if (j < 0) continue;
+                        nl[e].push_back((int32_t)(j - t.level_begin[L]));
+                        // code of (target - source) = -d
+                        nc[e].push_back((1 - dx) * 9 + (1 - dy) * 3 + (1 - dz));
+                    }
+        });
+        for (int64_t e = 0; e < nleaf; ++e) t.near_ptr[e + 1] = t.near_ptr[e] + (int32_t)nl[e].size();
+        t.near_leaf.reserve(t.near_ptr[nleaf]);
+        t.near_code.reserve(t.near_ptr[nleaf]);
+        for (int64_t e = 0; e < nleaf; ++e) {
+            t.near_leaf.insert(t.near_leaf.end(), nl[e].begin(), nl[e].end());
+            t.near_code.insert(t.near_code.end(), nc[e].begin(), nc[e].end());
+        }
+    }
+
+    // interaction fields of every box at levels 2..L: children of the parent's
+    // near field that are not adjacent to the box
+    t.v_ptr.assign(nb + 1, 0);
+    {
+        std::vector<std::vector<int32_t>> vs(nb), vc(nb);
+        for (int l = 2; l <= L; ++l) {
+            const int64_t pside = int64_t(1) << (l - 1);
+            const int64_t b0 = t.level_begin[l], b1 = t.level_begin[l + 1];
+            parallel_for(b1 - b0, [&](int64_t off) {
+                const int64_t b = b0 + off;
+                int64_t c[3];
+                unmorton(t.box_key[b], c);
+                int64_t pc[3] = {c[0] >> 1, c[1] >> 1, c[2] >> 1};
+                for (int dx = -1; dx <= 1; ++dx)
+                    for (int dy = -1; dy <= 1; ++dy)
+                        for (int dz = -1; dz <= 1; ++dz) {
+                            int64_t pn[3] = {pc[0] + dx, pc[1] + dy, pc[2] + dz};
+                            if (pn[0] < 0 || pn[1] < 0 || pn[2] < 0 || pn[0] >= pside || pn[1] >= pside || pn[2] >= pside) continue;
+                            int64_t p = find_key(t.box_key, t.level_begin[l - 1], t.level_begin[l],
+                                                 morton(pn[0], pn[1], pn[2]));
+                            if (p < 0) continue;
+                            for (int o = 0; o < 8; ++o) {
+                                int32_t ch = t.box_child[8 * p + o];
+                                if (ch < 0) continue;
+                                int64_t cc[3] = {2 * pn[0] + ((o >> 2) & 1), 2 * pn[1] + ((o >> 1) & 1), 2 * pn[2] + (o & 1)};
+                                int tx = (int)(c[0] - cc[0]), ty = (int)(c[1] - cc[1]), tz = (int)(c[2] - cc[2]);
+                                if (std::max(std::abs(tx), std::max(std::abs(ty), std::abs(tz))) < 2) continue;
+                                vs[b].push_back(ch);
+                                vc[b].push_back(class_of_offset(tx, ty, tz));
+                            }
+                        }
+            });
+        }
+        for (int64_t b = 0; b < nb; ++b) t.v_ptr[b + 1] = t.v_ptr[b] + (int32_t)vs[b].size();
+        t.v_src.reserve(t.v_ptr[nb]);
+        t.v_cls.reserve(t.v_ptr[nb]);
+        for (int64_t b = 0; b < nb; ++b) {
+            t.v_src.insert(t.v_src.end(), vs[b].begin(), vs[b].end());
+            t.v_cls.insert(t.v_cls.end(), vc[b].begin(), vc[b].end());
+        }
+    }
+    return t;
+}
+
+HostOps build_host_ops(int p, double eps, int leaf_size, double cd, double rcond, bool dense) {
+    if (p < 2 || p > 16) throw PlanError{-1, "p must be in [2, 16]"};
+    if (!(eps >= 0.0 && eps < 1.0)) throw PlanError{-1, "eps must be in [0, 1)"};
+    if (!(cd >= 0.0) || !(rcond >= 0.0)) throw PlanError{-1, "cd and pinv_rcond must be >= 0"};
+    HostOps o;
+    o.p = p;
+    o.dense = dense;
+    o.eps = eps;
+    o.rcond = rcond;
+    o.d = cd / std::sqrt(double(leaf_size));
+    if (!(o.d <= 2.0 / 3.0)) throw PlanError{-1, "surface offset d = cd/sqrt(leaf_size) must be <= 2/3"};
+    // boundary nodes of the p^3 grid on [-1,1]^3, lexicographic
+    std::vector<double> g(p);
+    for (int i = 0; i < p; ++i) g[i] = -1.0 + 2.0 * double(i) / double(p - 1);
+    g[p - 1] = 1.0;
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j)
+            for (int k = 0; k < p; ++k)
+                if (std::min(i, std::min(j, k)) == 0 || std::max(i, std::max(j, k)) == p - 1) {
+                    o.E.push_back(g[i]);
+                    o.E.push_back(g[j]);
+                    o.E.push_back(g[k]);
+                }
+    const int ne = (int)o.E.size() / 3;
+    o.n_eq = ne;
+    std::vector<double> inner(3 * ne), outer(3 * ne);
+    for (int i = 0; i < 3 * ne; ++i) {
+        inner[i] = (1.0 + o.d) * o.E[i];
+        outer[i] = (3.0 - 2.0 * o.d) * o.E[i];
+    }
+    o.outer = outer;
+    // S2M / L2T check-to-equivalent pseudo-inverses (unit cube)
+    std::vector<double> Gup = kernel_matrix(ne, outer.data(), ne, inner.data());  // G(UC, UE)
+    std::vector<double> Gdn = kernel_matrix(ne, inner.data(), ne, outer.data());  // G(DC, DE)
+    std::vector<double> Pup = pinv(ne, Gup.data(), rcond);
+    std::vector<double> Pdn = pinv(ne, Gdn.data(), rcond);
+    // M2M and L2L for the 8 child octants (parent units)
+    std::vector<double> M8((size_t)8 * ne * ne), L8((size_t)8 * ne * ne);
+    parallel_for(8, [&](int64_t oc) {
+        double s[3] = {((oc >> 2) & 1) ? 1.0 : -1.0, ((oc >> 1) & 1) ? 1.0 : -1.0, (oc & 1) ? 1.0 : -1.0};
+        std::vector<double> child(3 * ne);
+        for (int i = 0; i < ne; ++i)
+            for (int a = 0; a < 3; ++a) child[3 * i + a] = 0.5 * (s[a] + inner[3 * i + a]);
+        std::vector<double> Gm = kernel_matrix(ne, outer.data(), ne, child.data());   // G(UC, child UE)
+        std::vector<double> Mo = matmul(ne, ne, ne, Pup.data(), Gm.data());
+        std::vector<double> Gl = kernel_matrix(ne, child.data(), ne, outer.data());   // G(child DC, DE)
+        std::vector<double> Lo = matmul(ne, ne, ne, Gl.data(), Pdn.data());
+        std::copy(Mo.begin(), Mo.end(), M8.begin() + oc * ne * ne);
+        std::copy(Lo.begin(), Lo.end(), L8.begin() + oc * ne * ne);
+    });
+    // M2L matrices K^(t) = G(DC + 2t, UE)
+    std::vector<double> K((size_t)NCLASS * ne * ne);
+    parallel_for(NCLASS, [&](int64_t c) {
+        int t[3];
+        offset_of_class((int)c, t);
+        std::vector<double> tgt(3 * ne);
+        for (int i = 0; i < ne; ++i)
+            for (int a = 0; a < 3; ++a) tgt[3 * i + a] = inner[3 * i + a] + 2.0 * t[a];
+        std::vector<double> Kc = kernel_matrix(ne, tgt.data(), ne, inner.data());
+        std::copy(Kc.begin(), Kc.end(), K.begin() + c * ne * ne);
+    });
+    o.sing.assign(ne, 0.0);
+    if (dense) {
+        o.k = ne;
+        o.U.assign((size_t)ne * ne, 0.0);
+        for (int i = 0; i < ne; ++i) o.U[(size_t)i * ne + i] = 1.0;
+        o.S = Pup;
+        o.T = Pdn;
+        o.M = std::move(M8);
+        o.L = std::move(L8);
+        o.K = std::move(K);
+        return o;
+    }
+    // stage-1 compression: U from the SVD of K_fat = [K^(1) ... K^(316)]
+    std::vector<double> Kfat((size_t)ne * NCLASS * ne);
+    for (int c = 0; c < NCLASS; ++c)
+        for (int i = 0; i < ne; ++i)
+            std::memcpy(&Kfat[(size_t)i * NCLASS * ne + (size_t)c * ne], &K[(size_t)c * ne * ne + (size_t)i * ne],
+                        sizeof(double) * ne);
+    std::vector<double> s, Ufull;
+    svd_wide_left(ne, (int64_t)NCLASS * ne, Kfat.data(), s, Ufull);
+    Kfat.clear();
+    Kfat.shrink_to_fit();
+    o.sing = s;
+    o.sigma0 = s[0];
+    int k = 0;
+    for (int i = 0; i < ne; ++i)
+        if (s[i] >= eps * s[0]) ++k;
+    if (k < 1) k = 1;
+    o.k = k;
+    o.U.resize((size_t)ne * k);
+    for (int i = 0; i < ne; ++i)
+        for (int j = 0; j < k; ++j) o.U[(size_t)i * k + j] = Ufull[(size_t)i * ne + j];
+    const double* U = o.U.data();
+    o.S = matmul_tn(k, ne, ne, U, Pup.data());         // U~^T P_up
+    o.T = matmul(ne, ne, k, Pdn.data(), U);            // P_dn U~
+    o.M.resize((size_t)8 * k * k);
+    o.L.resize((size_t)8 * k * k);
+    parallel_for(8, [&](int64_t oc) {
+        std::vector<double> MU = matmul(ne, ne, k, &M8[oc * ne * ne], U);
+        std::vector<double> Mr = matmul_tn(k, ne, k, U, MU.data());
+        std::vector<double> LU = matmul(ne, ne, k, &L8[oc * ne * ne], U);
+        std::vector<double> Lr = matmul_tn(k, ne, k, U, LU.data());
+        std::copy(Mr.begin(), Mr.end(), o.M.begin() + oc * k * k);
+        std::copy(Lr.begin(), Lr.end(), o.L.begin() + oc * k * k);
+    });
+    o.K.resize((size_t)NCLASS * k * k);
+    parallel_for(NCLASS, [&](int64_t c) {
+        std::vector<double> KU = matmul(ne, ne, k, &K[(size_t)c * ne * ne], U);
+        std::vector<double> Kr = matmul_tn(k, ne, k, U, KU.data());
+        std::copy(Kr.begin(), Kr.end(), o.K.begin() + c * k * k);
+    });
+    return o;
+}
+
+void gg_append(GGSched& s, int64_t tgt_row0, int64_t n_tgt, const int32_t* ptr, const int32_t* src,
+               const int32_t* cls, int tile, double scale) {
+    if (s.tile_chunk0.empty()) s.tile_chunk0.push_back(0);
+    std::vector<int32_t> cnt;
+    std::vector<int32_t> order;
+    for (int64_t t0 = 0; t0 < n_tgt; t0 += tile) {
+        const int64_t t1 = std::min<int64_t>(n_tgt, t0 + tile);
+        const int32_t pb = ptr[t0], pe = ptr[t1];
+        s.tile_tgt0.push_back((int32_t)(tgt_row0 + t0));
+        s.tile_ntgt.push_back((int32_t)(t1 - t0));
+        s.tile_scale.push_back(scale);
+        s.max_tile = std::max<int>(s.max_tile, (int)(t1 - t0));
+        // counting sort of the tile's pairs by class (stable in target order)
+        int maxc = 0;
+        for (int32_t q = pb; q < pe; ++q) maxc = std::max(maxc, cls[q] + 1);
+        cnt.assign(maxc + 1, 0);
+        for (int32_t q = pb; q < pe; ++q) cnt[cls[q] + 1]++;
+        for (int c = 0; c < maxc; ++c) cnt[c + 1] += cnt[c];
+        order.assign(pe - pb, 0);
+        std::vector<int32_t> pos(cnt.begin(), cnt.end());
+        std::vector<int32_t> col_of(pe - pb);
+        for (int64_t t = t0; t < t1; ++t)
+            for (int32_t q = ptr[t]; q < ptr[t + 1]; ++q) {
+                order[pos[cls[q]]++] = q;
+                col_of[q - pb] = (int32_t)(t - t0);
+            }
+        int64_t i = 0;
+        const int64_t np = pe - pb;
+        while (i < np) {
+            const int c = cls[order[i]];
+            s.chunk_cls.push_back(c);
+            for (int j = 0; j < s.cp; ++j) {
+                if (i < np && cls[order[i]] == c) {
+                    s.chunk_src.push_back(src[order[i]]);
+                    s.chunk_col.push_back(col_of[order[i] - pb]);
+                    ++i;
+                } else {
+                    s.chunk_src.push_back(-1);
+                    s.chunk_col.push_back(-1);
+                }
+            }
+        }
+        s.pairs += np;
+        s.tile_chunk0.push_back((int32_t)s.chunk_cls.size());
+    }
+}
+
+}  // namespace kifmm

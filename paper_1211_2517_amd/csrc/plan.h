@@ -1,0 +1,95 @@
+// Host-side plan: octree, near/interaction fields, FP64 operators and the
+// work schedules of the grouped GEMM kernel. Nothing here touches the GPU.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace kifmm {
+
+constexpr int QBITS = 21;     // integer coordinate bits per axis
+constexpr int NCLASS = 316;   // M2L offset classes (Sec. 3.1)
+constexpr int MAX_LEVEL = 20;
+
+struct PlanError {
+    int code;
+    std::string msg;
+};
+
+// Class id of an M2L offset t in [-3,3]^3 with max|t_a| >= 2 (lexicographic), else -1.
+int class_of_offset(int tx, int ty, int tz);
+// Inverse of class_of_offset.
+void offset_of_class(int c, int* t);
+
+struct HostTree {
+    int depth = 0;
+    int64_t n = 0;
+    double centre[3] = {0, 0, 0};
+    double r0 = 1.0;
+    std::vector<int32_t> perm;          // sorted position -> caller index
+    std::vector<int64_t> level_begin;   // depth+2 entries: global box index range of each level
+    std::vector<uint64_t> box_key;      // Morton key of each box at its own level
+    std::vector<int32_t> box_parent;    // global index of the parent, -1 for the root
+    std::vector<int32_t> box_child;     // 8 per box (octant 4*ox+2*oy+oz), -1 if empty
+    std::vector<int32_t> leaf_ptr;      // n_leaf+1 offsets into the sorted points
+    std::vector<double> u;              // sorted points in leaf units: (x - c_leaf)/r_L, 3 per point
+    std::vector<int32_t> near_ptr;      // CSR over leaves
+    std::vector<int32_t> near_leaf;     // source leaf (leaf index)
+    std::vector<int32_t> near_code;     // (dx+1)*9+(dy+1)*3+(dz+1), d = target - source cube
+    std::vector<int32_t> v_ptr;         // CSR over global boxes (levels 2..depth)
+    std::vector<int32_t> v_src;         // source box (global index)
+    std::vector<int32_t> v_cls;         // offset class of (target - source)
+    std::vector<int32_t> leaf_coords;   // per caller point: level-depth cube (3 ints)
+
+    int64_t n_box() const { return level_begin.back(); }
+    int64_t n_leaf() const { return level_begin[depth + 1] - level_begin[depth]; }
+    int64_t level_count(int l) const { return level_begin[l + 1] - level_begin[l]; }
+    double half_width(int l) const { return r0 / double(int64_t(1) << l); }
+};
+
+// Builds the tree; throws PlanError on invalid input.
+HostTree build_host_tree(const double* pts, int64_t n, int leaf_size, int depth_override,
+                         int max_depth);
+
+struct HostOps {
+    int p = 0, n_eq = 0, k = 0;
+    bool dense = false;
+    double d = 0, rcond = 0, eps = 0, sigma0 = 0;
+    std::vector<double> E;      // unit surface template (n_eq x 3)
+    std::vector<double> outer;  // (3-2d) E: upward check = downward equivalent surface
+    std::vector<double> sing;   // singular values of K_fat (n_eq; zeros in dense mode)
+    std::vector<double> U;      // n_eq x k
+    std::vector<double> S;      // k x n_eq
+    std::vector<double> T;      // n_eq x k
+    std::vector<double> M, L;   // 8 x k x k (octant 4*ox+2*oy+oz)
+    std::vector<double> K;      // 316 x k x k
+};
+
+HostOps build_host_ops(int p, double eps, int leaf_size, double cd, double rcond, bool dense);
+
+// Work schedule of the grouped gather GEMM Y[t] (+)= scale * sum A[cls] X[src].
+// Targets are split into tiles of consecutive rows; inside a tile the
+// (target, source, class) pairs are sorted by class and cut into chunks of at
+// most `cp` pairs of one class.
+struct GGSched {
+    int cp = 16;
+    int max_tile = 0;
+    std::vector<int32_t> tile_tgt0;    // first target row of the tile
+    std::vector<int32_t> tile_ntgt;    // targets in the tile
+    std::vector<int32_t> tile_chunk0;  // n_tiles + 1
+    std::vector<double> tile_scale;
+    std::vector<int32_t> chunk_cls;
+    std::vector<int32_t> chunk_src;    // n_chunks * cp (-1 = empty slot)
+    std::vector<int32_t> chunk_col;    // n_chunks * cp (target column in the tile, -1 = empty)
+    int64_t pairs = 0;
+    int n_tiles() const { return (int)tile_tgt0.size(); }
+    int n_chunks() const { return (int)chunk_cls.size(); }
+};
+
+// Append the targets [0, n_tgt) (rows tgt_row0 + i of Y) whose pairs are given
+// in CSR form (ptr over targets; src rows of X and class ids), in tiles of
+// `tile` targets with the given scale.
+void gg_append(GGSched& s, int64_t tgt_row0, int64_t n_tgt, const int32_t* ptr,
+               const int32_t* src, const int32_t* cls, int tile, double scale);
+
+}  // namespace kifmm

@@ -1,0 +1,282 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances:
+* FP64 device mode against the oracle in the same mode: 1e-10 relative L2
+  (both evaluate the same operators in double; they differ only by the
+  rounding of two independent SVD/pseudo-inverse routes and summation order).
+* FP32 device mode against the FP64 dense-M2L oracle: 1e-5 relative L2, the
+  bar set for this matvec. The SVD truncation at eps = 1e-6 contributes about
+  1e-6 of it and FP32 rounding the rest.
+"""
+import functools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "sphere1m_p6_samples.json")
+
+
+def _k():
+    import paper_1211_2517_amd as K
+    return K
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu_apply(x, s, p, eps, leaf, precision="fp32", dense=False, adjoint=False, **kw):
+    torch = _torch()
+    plan = _k().Plan(x, p=p, eps=eps, leaf_size=leaf, precision=precision, dense_m2l=dense, **kw)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    sd = torch.tensor(np.asarray(s), dtype=dt, device="cuda:0")
+    out = plan.apply_adjoint(sd) if adjoint else plan.apply(sd)
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy(), plan
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_ops(p, eps, leaf, mode):
+    return oracle.build_operators(p, eps, leaf, mode=mode)
+
+
+@functools.lru_cache(maxsize=None)
+def cube(n=4096):
+    x = workloads.uniform_cube(n, workloads.SEED_BASE)
+    s = workloads.uniform_density(n, workloads.SEED_BASE + 100)
+    return x, s
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_phi(kind, n, p, eps, leaf, mode):
+    x, s = cube(n) if kind == "cube" else sphere(n)
+    return oracle.fmm(x, s, p, eps, leaf, ops=oracle_ops(p, eps, leaf, mode))[0]
+
+
+@functools.lru_cache(maxsize=None)
+def sphere(n):
+    x = workloads.sphere_points(n, workloads.SEED_BASE + 1)
+    return x, workloads.sphere_density(x, workloads.SEED_BASE + 101)
+
+
+# ------------------------------------------------------------------ FP64 mode
+@pytest.mark.parametrize("mode", ["dense", "svd"])
+def test_fp64_matches_oracle_same_mode(mode):
+    x, s = cube()
+    want = oracle_phi("cube", 4096, 4, 1e-6, 64, mode)
+    got, _ = gpu_apply(x, s, 4, 1e-6, 64, precision="fp64", dense=(mode == "dense"))
+    assert rel(got, want) < 1e-10
+
+
+# ------------------------------------------------------------------ FP32 mode
+@pytest.mark.parametrize("p", [4, 6])
+def test_fp32_svd_vs_dense_oracle_cube(p):
+    x, s = cube()
+    want = oracle_phi("cube", 4096, p, 1e-6, 64, "dense")
+    got, plan = gpu_apply(x, s, p, 1e-6, 64)
+    e = rel(got, want)
+    print(f"p={p} k={plan.info()['k']} fp32-svd vs fp64-dense oracle: {e:.3e}")
+    assert e < 1e-5
+
+
+def test_fp32_dense_gpu_vs_dense_oracle_cube():
+    x, s = cube()
+    want = oracle_phi("cube", 4096, 6, 1e-6, 64, "dense")
+    got, _ = gpu_apply(x, s, 6, 1e-6, 64, dense=True)
+    assert rel(got, want) < 1e-5
+
+
+def test_fp32_sphere_many_tiles_ragged():
+    # 20000 points, leaf 32: depth 5, thousands of boxes, M2L tiles with a ragged tail
+    x, s = sphere(20000)
+    want = oracle_phi("sphere", 20000, 6, 1e-6, 32, "dense")
+    got, plan = gpu_apply(x, s, 6, 1e-6, 32, tile_targets=96)
+    info = plan.info()
+    assert info["depth"] >= 5 and info["n_box"] > 2000
+    assert rel(got, want) < 1e-5
+
+
+def test_full_size_sphere_sampled():
+    # 2**20 icosphere centroids, p=6, eps=1e-6, leaf 64 (the benchmark workload),
+    # checked at 256 sampled points against the oracle (tests/golden, written
+    # by tests/golden/make_sphere_samples.py from the oracle alone).
+    g = json.load(open(GOLDEN))
+    x, s = sphere(g["n"])
+    idx = np.asarray(g["sample"])
+    for dense in (False, True):
+        got, plan = gpu_apply(x, s, g["p"], g["eps"], g["leaf_size"], dense=dense)
+        assert plan.info()["depth"] == g["depth"]
+        e = rel(got[idx], g["phi_dense"])
+        print(f"dense_m2l={dense} sampled rel err vs fp64 dense oracle {e:.3e}; "
+              f"vs direct {rel(got[idx], g['phi_direct']):.3e}")
+        assert e < 1e-5
+
+
+# ----------------------------------------------------------------- adjoint
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-6)])
+def test_adjoint_dot_product(precision, tol):
+    torch = _torch()
+    x, s = cube()
+    g = workloads.uniform_density(4096, 77)
+    plan = _k().Plan(x, p=4, eps=1e-6, leaf_size=64, precision=precision)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    sd = torch.tensor(s, dtype=dt, device="cuda:0")
+    gd = torch.tensor(g, dtype=dt, device="cuda:0")
+    fs = plan.apply(sd).double().cpu().numpy()
+    ftg = plan.apply_adjoint(gd).double().cpu().numpy()
+    lhs, rhs = g @ fs, ftg @ s
+    assert abs(lhs - rhs) <= tol * np.linalg.norm(g) * np.linalg.norm(fs)
+
+
+def test_adjoint_equals_forward_fp64():
+    # With the paper's surfaces the FMM operator is symmetric, so the
+    # transposed passes must reproduce the forward passes to rounding.
+    x, s = cube()
+    fwd, _ = gpu_apply(x, s, 6, 1e-6, 64, precision="fp64")
+    adj, _ = gpu_apply(x, s, 6, 1e-6, 64, precision="fp64", adjoint=True)
+    assert rel(adj, fwd) < 1e-10
+
+
+def test_adjoint_vs_dense_direct_transpose_torus():
+    # F^T g against the dense K^T g (= K g, the kernel is symmetric) at N=16384.
+    x = workloads.torus_grid_centroids(128, 64)
+    g = workloads.uniform_density(x.shape[0], 5)
+    want = oracle.direct(x, g)
+    got, _ = gpu_apply(x, g, 6, 1e-6, 64, adjoint=True)
+    e = rel(got, want)
+    print(f"adjoint vs dense K^T g: {e:.3e}")
+    assert e < 1e-4
+
+
+def test_autograd_backward_is_adjoint_and_fd():
+    torch = _torch()
+    K = _k()
+    x = workloads.torus_grid_centroids(64, 32)
+    n = x.shape[0]
+    plan = K.Plan(x, p=6, eps=1e-6, leaf_size=64, precision="fp64")
+    rng = np.random.default_rng(3)
+    sig = torch.tensor(rng.uniform(-1, 1, n), dtype=torch.float64, device="cuda:0", requires_grad=True)
+    star = torch.tensor(rng.uniform(-1, 1, n), dtype=torch.float64, device="cuda:0")
+    b = plan.apply(star)
+
+    def loss_of(s):
+        r = K.KifmmMatvec.apply(plan, s) - b
+        return 0.5 * (r * r).sum()
+
+    loss = loss_of(sig)
+    loss.backward()
+    grad = sig.grad.detach()
+    want = plan.apply_adjoint(plan.apply(sig.detach()) - b)
+    assert torch.allclose(grad, want, rtol=0, atol=0)
+    h = 1e-3
+    for d in range(4):
+        v = torch.tensor(rng.normal(size=n), dtype=torch.float64, device="cuda:0")
+        v *= sig.detach().norm() / v.norm()
+        with torch.no_grad():
+            fd = (loss_of(sig.detach() + h * v) - loss_of(sig.detach() - h * v)) / (2 * h)
+        an = (grad * v).sum()
+        assert abs(float(fd - an)) <= 1e-8 * abs(float(an)) + 1e-12
+
+
+# ------------------------------------------------------------------ batching
+def test_batched_columns_match_single_applies():
+    torch = _torch()
+    K = _k()
+    x, _ = cube()
+    S = workloads.uniform_density(4096, 9, nrhs=3)
+    plan = K.Plan(x, p=4, eps=1e-6, leaf_size=64, max_nrhs=4)
+    single = K.Plan(x, p=4, eps=1e-6, leaf_size=64)
+    Sd = torch.tensor(S, dtype=torch.float32, device="cuda:0")
+    out = plan.apply_batched(Sd).cpu().numpy()
+    for j in range(3):
+        one = single.apply(Sd[:, j].contiguous()).cpu().numpy()
+        assert np.allclose(out[:, j], one, rtol=1e-6, atol=1e-6 * np.abs(one).max())
+        assert rel(out[:, j], oracle.fmm(x, S[:, j], 4, 1e-6, 64, ops=oracle_ops(4, 1e-6, 64, "dense"))[0]) < 1e-5
+
+
+# ------------------------------------------------------------- edge cases
+def test_single_point_and_pair():
+    got, _ = gpu_apply(np.array([[0.3, 0.1, -0.2]]), np.array([2.0]), 4, 1e-6, 64, precision="fp64")
+    assert got[0] == 0.0
+    x = np.array([[0.0, 0.0, 0.0], [0.0, 0.5, 0.0]])
+    got, _ = gpu_apply(x, np.array([1.0, -3.0]), 4, 1e-6, 64, precision="fp64")
+    f = 1.0 / (4 * math.pi * 0.5)
+    assert np.allclose(got, [-3.0 * f, f], rtol=1e-14)
+
+
+def test_one_leaf_equals_direct_fp32():
+    x = workloads.uniform_cube(60, 4)
+    s = workloads.uniform_density(60, 5)
+    got, plan = gpu_apply(x, s, 4, 1e-6, 64)
+    assert plan.info()["depth"] == 0
+    assert rel(got, oracle.direct(x, s)) < 1e-6
+
+
+def test_duplicates_and_clusters():
+    # exact duplicates contribute 0 on both sides; two far clusters exercise M2L alone
+    a = workloads.uniform_cube(1500, 6) * 0.01
+    b = a + np.array([1.0, 1.0, 1.0])
+    x = np.concatenate([a, b, a[:200]], axis=0)
+    s = workloads.uniform_density(x.shape[0], 7)
+    want = oracle.fmm(x, s, 6, 1e-6, 32, ops=oracle_ops(6, 1e-6, 32, "dense"))[0]
+    got, _ = gpu_apply(x, s, 6, 1e-6, 32)
+    assert rel(got, want) < 1e-5
+
+
+def test_bitwise_deterministic():
+    torch = _torch()
+    x, s = sphere(20000)
+    plan = _k().Plan(x, p=6, eps=1e-6, leaf_size=32)
+    sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
+    a = plan.apply(sd).clone()
+    b = plan.apply(sd).clone()
+    assert torch.equal(a, b)
+
+
+def test_group_graph_replays_match_eager():
+    torch = _torch()
+    K = _k()
+    sets = [workloads.sphere_points(3000, 1), workloads.cube_surface(5000, 2), workloads.torus_random(7000, 3)]
+    plans = [K.Plan(x, p=4, eps=1e-6, leaf_size=32) for x in sets]
+    sig = [torch.tensor(workloads.uniform_density(x.shape[0], i), dtype=torch.float32, device="cuda:0")
+           for i, x in enumerate(sets)]
+    eager = [p.apply(s).clone() for p, s in zip(plans, sig)]
+    outs = [torch.empty_like(s) for s in sig]
+    grp = K.Group(plans)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        grp.apply(sig, outs)
+        torch.cuda.synchronize()
+        for o, e in zip(outs, eager):
+            assert torch.equal(o, e), f"replay {rep}"
+        _ = [p.apply(s) for p, s in zip(plans, sig)]   # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_stage_profile_counts():
+    torch = _torch()
+    x, s = cube()
+    plan = _k().Plan(x, p=4, eps=1e-6, leaf_size=64)
+    sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
+    plan.profile(True)
+    for _ in range(3):
+        plan.apply(sd)
+    ms, calls = plan.profile_read()
+    assert calls == 3 and ms["m2l"] > 0 and ms["p2p"] > 0
+    plan.profile(False)

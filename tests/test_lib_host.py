@@ -1,0 +1,143 @@
+"""Host-side checks of the C-ABI library (CPU only, no device calls).
+
+The library is loaded and every symbol declared in include/kifmm.h must be
+exported. Host-only plans (opts.device = -1) build the tree, lists and FP64
+operators without touching a GPU; they are compared with the oracle, which
+computes the same quantities independently.
+"""
+import ctypes
+import functools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+import paper_1211_2517_amd as K
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "kifmm.h")
+
+
+def test_library_exports_every_declared_symbol():
+    lib = K.load_library()
+    text = open(HEADER).read()
+    declared = set(re.findall(r"\b(kifmm_[a-z_]+)\s*\(", text))
+    assert declared, "no declarations parsed"
+    assert declared == set(K.EXPORTED_SYMBOLS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+@functools.lru_cache(maxsize=None)
+def _host_plan(kind, n, p, eps, leaf, dense=False):
+    x = {"cube": workloads.uniform_cube, "sphere": workloads.sphere_points}[kind](n, 1211)
+    return x, K.Plan(x, p=p, eps=eps, leaf_size=leaf, device=-1, dense_m2l=dense)
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_ops(p, eps, leaf, mode):
+    return oracle.build_operators(p, eps, leaf, mode=mode)
+
+
+@pytest.mark.parametrize("kind,n,leaf", [("cube", 4096, 64), ("sphere", 20000, 32), ("cube", 50, 64)])
+def test_tree_identical_to_oracle(kind, n, leaf):
+    x, pl = _host_plan(kind, n, 4, 1e-6, leaf)
+    tr = oracle.build_tree(x, leaf)
+    info = pl.info()
+    assert info["depth"] == tr.depth
+    lc = pl.export_tree()
+    want = np.array(tr.leaf_of_point, dtype=np.int64).reshape(-1, 3)
+    assert np.array_equal(lc.astype(np.int64), want)
+    assert info["n_leaf"] == len(tr.leaf_points)
+    assert info["boxes_level"] == [len(tr.boxes[l]) for l in range(tr.depth + 1)]
+    vl = [sum(len(tr.interaction(l, b)) for b in tr.boxes[l]) if l >= 2 else 0 for l in range(tr.depth + 1)]
+    assert info["v_pairs_level"] == vl
+    near = sum(len(tr.near(tr.depth, b)) for b in tr.boxes[tr.depth])
+    assert info["near_pairs"] == near
+
+
+@pytest.mark.parametrize("p,eps", [(4, 1e-6), (6, 1e-6), (6, 1e-4)])
+def test_svd_operators_match_oracle(p, eps):
+    _, pl = _host_plan("cube", 4096, p, eps, 64)
+    ops = _oracle_ops(p, eps, 64, "svd")
+    k = ops.k
+    assert pl.info()["k"] == k
+    s = pl.export_operator(0)
+    assert np.allclose(s[:k], ops.sing[:k], rtol=1e-9, atol=0)
+    U = pl.export_operator(1).reshape(ops.n_eq, k)
+    assert np.allclose(U.T @ U, np.eye(k), atol=1e-12)
+    # singular vectors are unique up to sign: compare sign-free products
+    assert np.abs(U @ U.T - ops.U @ ops.U.T).max() < 1e-9
+    Kl = pl.export_operator(6).reshape(316, k, k)
+    scale = max(np.abs(v).max() for v in ops.K_full.values())
+    for i, t in enumerate(oracle.offset_classes()):
+        assert np.abs(U @ Kl[i] @ U.T - ops.U @ ops.K[t] @ ops.U.T).max() < 1e-9 * scale
+    S = pl.export_operator(2).reshape(k, ops.n_eq)
+    T = pl.export_operator(3).reshape(ops.n_eq, k)
+    ref = np.abs(ops.U @ ops.S).max()
+    assert np.abs(U @ S - ops.U @ ops.S).max() < 1e-7 * ref
+    assert np.abs(T @ U.T - ops.T @ ops.U.T).max() < 1e-7 * ref
+    M = pl.export_operator(4).reshape(8, k, k)
+    L = pl.export_operator(5).reshape(8, k, k)
+    for o in range(8):
+        sign = tuple(2.0 * ((o >> s) & 1) - 1.0 for s in (2, 1, 0))
+        assert np.abs(U @ M[o] @ U.T - ops.U @ ops.M[sign] @ ops.U.T).max() < 1e-8
+        assert np.abs(U @ L[o] @ U.T - ops.U @ ops.L[sign] @ ops.U.T).max() < 1e-8
+
+
+def test_dense_operators_match_oracle():
+    _, pl = _host_plan("cube", 4096, 4, 1e-6, 64, dense=True)
+    ops = _oracle_ops(4, 1e-6, 64, "dense")
+    n = ops.n_eq
+    assert pl.info()["k"] == n
+    Kl = pl.export_operator(6).reshape(316, n, n)
+    for i, t in enumerate(oracle.offset_classes()):
+        assert np.allclose(Kl[i], ops.K[t], rtol=1e-13, atol=1e-16)
+    S = pl.export_operator(2).reshape(n, n)
+    assert np.abs(S - ops.S).max() < 1e-8 * np.abs(ops.S).max()
+
+
+def test_single_leaf_depth_zero():
+    x, pl = _host_plan("cube", 50, 4, 1e-6, 64)
+    info = pl.info()
+    assert info["depth"] == 0 and info["n_leaf"] == 1 and info["v_pairs"] == 0
+
+
+def _err(fn):
+    with pytest.raises(K.KifmmError) as e:
+        fn()
+    return e.value.code
+
+
+def test_invalid_arguments_are_rejected():
+    x = workloads.uniform_cube(100, 1)
+    assert _err(lambda: K.Plan(x, p=1, device=-1)) == -1
+    assert _err(lambda: K.Plan(x, p=6, eps=1.0, device=-1)) == -1
+    assert _err(lambda: K.Plan(x, p=6, eps=-1e-3, device=-1)) == -1
+    assert _err(lambda: K.Plan(x, leaf_size=0, device=-1)) == -1
+    assert _err(lambda: K.Plan(x[:0], device=-1)) == -1
+    bad = x.copy()
+    bad[17, 1] = np.nan
+    assert _err(lambda: K.Plan(bad, device=-1)) == -4
+    bad[17, 1] = np.inf
+    assert _err(lambda: K.Plan(bad, device=-1)) == -4
+    assert _err(lambda: K.Plan(x, max_nrhs=17, device=-1)) == -1
+    assert _err(lambda: K.Plan(x, p=9, device=-1)) == -1     # n_eq 386 beyond the device kernels
+
+
+def test_host_only_plan_refuses_apply():
+    lib = K.load_library()
+    _, pl = _host_plan("cube", 4096, 4, 1e-6, 64)
+    rc = lib.kifmm_apply(pl._h, ctypes.c_void_p(16), ctypes.c_void_p(32), None)
+    assert rc == -5
+    assert b"host-only" in lib.kifmm_last_error()
+    lib.kifmm_destroy(None)       # NULL-safe
+    lib.kifmm_group_destroy(None)
+
+
+def test_duplicate_points_cap_depth():
+    x = np.repeat(workloads.uniform_cube(10, 2), 20, axis=0)   # 20 copies of 10 points
+    pl = K.Plan(x, p=4, eps=1e-6, leaf_size=8, device=-1, max_depth=6)
+    assert pl.info()["depth"] == 6
