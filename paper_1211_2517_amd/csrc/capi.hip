@@ -287,7 +287,12 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
     if (L < 2) return KIFMM_OK;
     const int64_t nleaf = t.n_leaf();
     const int64_t lb = t.level_begin[L];
-    const int leaf_tile = std::max(16, 128 / pl->R);
+    // tiles must keep their (rows x columns) accumulator within the LDS budget
+    auto fit = [&](int want, int rows) {
+        const int cap = (int)(gg_lds_limit() / ((size_t)(rows + 4) * pl->elt * pl->R));
+        return std::max(1, std::min(want, cap));
+    };
+    const int leaf_tile = fit(std::max(16, 128 / pl->R), std::max(pl->kp, pl->nep));
     {
         std::vector<int32_t> ptr(nleaf + 1), src(nleaf), cls(nleaf, 0);
         for (int64_t e = 0; e <= nleaf; ++e) ptr[e] = (int32_t)e;
@@ -296,7 +301,7 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
         for (int64_t e = 0; e < nleaf; ++e) src[e] = (int32_t)(lb + e);
         gg_append(pl->h_leafdown, 0, nleaf, ptr.data(), src.data(), cls.data(), leaf_tile, 1.0);
     }
-    const int updown_tile = std::max(16, 64 / pl->R);
+    const int updown_tile = fit(std::max(16, 64 / pl->R), pl->kp);
     for (int l = 2; l < L; ++l) {
         // targets at level l, sources their children at level l+1 (class = octant)
         const int64_t b0 = t.level_begin[l], nb = t.level_count(l);
@@ -329,7 +334,7 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
         // every box of levels 2..L gets a tile slot, so that M2L initialises its
         // local coefficients even when its interaction field is empty
         const int64_t b0 = t.level_begin[l], nb = t.level_count(l);
-        gg_append(pl->h_m2l, b0, nb, &t.v_ptr[b0], t.v_src.data(), t.v_cls.data(), m2l_tile,
+        gg_append(pl->h_m2l, b0, nb, &t.v_ptr[b0], t.v_src.data(), t.v_cls.data(), fit(m2l_tile, pl->kp),
                   1.0 / t.half_width(l));
     }
     return KIFMM_OK;

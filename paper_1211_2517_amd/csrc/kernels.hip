@@ -21,12 +21,16 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 struct Mfma;
 
+// Output row of accumulator element q held by lane group g (column = lane % 16):
+// the FP32 form stores 4 consecutive rows per lane group, the FP64 form
+// interleaves the lane groups row by row.
 template <>
 struct Mfma<float> {
     using V4 = f32x4;
     static __device__ __forceinline__ V4 step(float a, float b, V4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int q, int g) { return 4 * g + q; }
 };
 
 template <>
@@ -35,6 +39,7 @@ struct Mfma<double> {
     static __device__ __forceinline__ V4 step(double a, double b, V4 c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int q, int g) { return 4 * q + g; }
 };
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
@@ -76,7 +81,7 @@ constexpr int kMBW = 2;  // 16-row output blocks owned by one wave
 // waves touch the same LDS word in one step, so no atomics are needed).
 //
 // MFMA operand layout (v_mfma_*_16x16x4): lane l supplies A[l%16][kk] and
-// B[kk][l%16] of one K-step, and holds D[4*(l/16)+q][l%16], q = 0..3. The K
+// B[kk][l%16] of one K-step and holds D[Mfma<T>::row(q, l/16)][l%16]. The K
 // order is permuted so that both operands are read as 4-wide vectors: in
 // K-chunk t, lane group g = l/16 supplies indices 16t + 4g + e for the 4
 // consecutive MFMA steps e = 0..3.
@@ -161,11 +166,9 @@ __global__ void __launch_bounds__(1024) gg_kernel(GGParams p) {
 #pragma unroll
             for (int m = 0; m < kMBW; ++m) {
                 if (mb0 + m < p.MB) {
-                    T* dst = acc + (col * R + rj) * ldl + (mb0 + m) * 16 + 4 * grp;
-                    dst[0] += scale * d[m][0];
-                    dst[1] += scale * d[m][1];
-                    dst[2] += scale * d[m][2];
-                    dst[3] += scale * d[m][3];
+                    T* dst = acc + (col * R + rj) * ldl + (mb0 + m) * 16;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dst[M::row(q, grp)] += scale * d[m][q];
                 }
             }
         }

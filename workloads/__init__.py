@@ -137,6 +137,7 @@ def cube_surface(n: int, seed: int):
 
 
 def _torus_xyz(u, v, big_r, small_r):
+    u, v = np.broadcast_arrays(u, v)
     return np.stack([(big_r + small_r * np.cos(v)) * np.cos(u),
                      (big_r + small_r * np.cos(v)) * np.sin(u),
                      small_r * np.sin(v)], axis=-1)
