@@ -97,6 +97,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["svd", "dense64", "dense32"], default=None,
+                    help="time one plan only (profiling runs); prints no JSON line")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run one device-to-device copy of this many MB (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested): this build has no "
@@ -119,12 +124,24 @@ def main():
     ref = np.asarray(golden["phi_dense"])
     ref_direct = np.asarray(golden["phi_direct"])
 
+    if args.copy_calibration_mb:
+        nflt = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(nflt, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration_mb} MB done")
+        del src, dst
+
     res = {}
     # svd: the compressed path (FP32). dense64: uncompressed operators in FP64,
     # the dense-M2L matvec that reaches the same accuracy. dense32: uncompressed
     # in FP32 (same precision as svd; its rounding error is reported, it does
     # not reach the accuracy because the uncompressed translations amplify it).
     for name, dense, prec in (("svd", False, "fp32"), ("dense64", True, "fp64"), ("dense32", True, "fp32")):
+        if args.only and name != args.only:
+            continue
         log(f"plan {name}")
         plan = K.Plan(x, p=P, eps=EPS, leaf_size=LEAF, precision=prec, dense_m2l=dense)
         if prec == "fp64":
@@ -134,7 +151,8 @@ def main():
             sd_run, out_run = sd, out
         info = plan.info()
         log(f"{name}: depth {info['depth']} k {info['k']} v_pairs {info['v_pairs']} "
-            f"plan {info['plan_seconds']:.1f}s; timing {args.steps} steps")
+            f"plan {info['plan_seconds']:.1f}s, M2L tile <= {info['m2l_tile_targets']} targets; "
+            f"timing {args.steps} steps")
         ms, wall, stages = time_plan(plan, sd_run, out_run, args.steps, args.warmup)
         got = out_run.double().cpu().numpy()[idx]
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
@@ -143,6 +161,8 @@ def main():
         res[name] = dict(ms=ms, wall=wall, stages=stages, info=info, err=err, err_direct=err_direct)
         plan.close()
 
+    if args.only:
+        return
     svd = res["svd"]
     info = svd["info"]
     m2l_ms = svd["stages"]["m2l"]

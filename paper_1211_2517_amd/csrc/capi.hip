@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <tuple>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -47,6 +48,8 @@ struct kifmm_plan_s {
     int k = 0, kp = 0, nep = 0, R = 1, elt = 4;
     bool on_device = false;
     int device = 0;
+    int num_cu = 256;   // compute units of the device (MI355X: 256)
+    float tuned_ms = 0;  // M2L launch time of the autotuned shape (0 = not tuned)
     // host schedules
     GGSched h_leafup, h_leafdown, h_m2l;
     std::vector<GGSched> h_up, h_down;   // indexed by target level
@@ -105,6 +108,7 @@ struct Uploader {
     size_t limit;
     int err = KIFMM_OK;
     std::string msg;
+    std::vector<void*>* scratch = nullptr;   // when set, allocations go here instead of the plan
     void* alloc(size_t bytes) {
         if (err != KIFMM_OK) return nullptr;
         if (bytes == 0) bytes = 16;
@@ -121,8 +125,12 @@ struct Uploader {
             msg = std::string("hipMalloc failed: ") + hipGetErrorString(e);
             return nullptr;
         }
-        pl->allocs.push_back(p);
-        pl->device_bytes += bytes;
+        if (scratch) {
+            scratch->push_back(p);
+        } else {
+            pl->allocs.push_back(p);
+            pl->device_bytes += bytes;
+        }
         return p;
     }
     template <class V>
@@ -168,17 +176,20 @@ DevSched upload_sched(Uploader& up, const GGSched& s, int elt) {
     d.n_chunks = s.n_chunks();
     d.cp = s.cp;
     d.max_tile = s.max_tile;
+    d.variant = s.variant;
     if (d.n_tiles == 0) return d;
     d.tile_tgt0 = (const int32_t*)up.put(s.tile_tgt0);
     d.tile_ntgt = (const int32_t*)up.put(s.tile_ntgt);
     d.tile_chunk0 = (const int32_t*)up.put(s.tile_chunk0);
-    if (elt == 4) {
-        std::vector<float> f(s.tile_scale.begin(), s.tile_scale.end());
-        d.tile_scale = up.put(f);
-    } else {
-        d.tile_scale = up.put(s.tile_scale);
-    }
     d.chunk_cls = (const int32_t*)up.put(s.chunk_cls);
+    d.chunk_next = (const int32_t*)up.put(s.chunk_next);
+    d.chunk_nblk = (const int32_t*)up.put(s.chunk_nblk);
+    if (elt == 4) {
+        std::vector<float> f(s.chunk_scale.begin(), s.chunk_scale.end());
+        d.chunk_scale = up.put(f);
+    } else {
+        d.chunk_scale = up.put(s.chunk_scale);
+    }
     d.chunk_src = (const int32_t*)up.put(s.chunk_src);
     d.chunk_col = (const int32_t*)up.put(s.chunk_col);
     return d;
@@ -272,6 +283,56 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
     in.plan_seconds = seconds;
 }
 
+// Largest tile (targets) whose LDS accumulator fits one workgroup.
+int max_tile_for(const kifmm_plan_s* pl, int variant, int kdim) {
+    const size_t fixed = gg_lds_bytes(pl->elt, variant, kdim / 16, 0);
+    const size_t per_col = (gg_lds_bytes(pl->elt, variant, kdim / 16, 1) - fixed) * pl->R;
+    if (gg_lds_limit() <= fixed) return 1;
+    return std::max(1, (int)((gg_lds_limit() - fixed) / per_col));
+}
+
+int row_groups(int rows_pad, int variant) {
+    const int mbg = gg_variant_rows(variant) / 16;
+    return (rows_pad / 16 + mbg - 1) / mbg;
+}
+
+// M2L schedule over every box of levels 2..L (one contiguous target range);
+// tiles are cut at equal work (pairs + a per-target cost) into `n_tiles` tiles,
+// or uniformly into `tile` targets when tile > 0.
+GGSched build_m2l_sched(const kifmm_plan_s* pl, int variant, int n_tiles, int tile) {
+    const HostTree& t = pl->tree;
+    GGSched s;
+    s.cp = 32 / pl->R;
+    s.rhs = pl->R;
+    s.variant = variant;
+    const int L = t.depth;
+    if (L < 2) return s;
+    const int64_t b0 = t.level_begin[2], nb = t.n_box() - b0;
+    std::vector<int32_t> group(nb);
+    std::vector<double> scale(L - 1);
+    for (int l = 2; l <= L; ++l) {
+        scale[l - 2] = 1.0 / t.half_width(l);
+        for (int64_t b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b) group[b - b0] = l - 2;
+    }
+    const int cap = max_tile_for(pl, variant, pl->kp);
+    std::vector<int64_t> cuts = tile > 0 ? uniform_cuts(nb, std::min(tile, cap))
+                                         : balanced_cuts(nb, &t.v_ptr[b0], n_tiles, cap, 8.0);
+    gg_build(s, b0, nb, &t.v_ptr[b0], t.v_src.data(), t.v_cls.data(), group.data(), scale, cuts);
+    return s;
+}
+
+// Tiles for `variant` so that the launch fills the CUs in whole rounds.
+int m2l_tiles_for(const kifmm_plan_s* pl, int variant, int extra_rounds) {
+    const HostTree& t = pl->tree;
+    const int64_t nb = t.n_box() - t.level_begin[2];
+    const int n_rg = row_groups(pl->kp, variant);
+    const int slots = std::max(1, pl->num_cu / n_rg);
+    const int cap = max_tile_for(pl, variant, pl->kp);
+    int rounds = 1;
+    while ((int64_t)rounds * slots * cap < nb * 11 / 10) ++rounds;
+    return (rounds + extra_rounds) * slots;
+}
+
 int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
     const HostTree& t = pl->tree;
     const int L = t.depth;
@@ -280,28 +341,40 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
     pl->h_m2l = GGSched();
     pl->h_up.assign(L + 1, GGSched());
     pl->h_down.assign(L + 1, GGSched());
-    const int cp = 16 / pl->R;
-    pl->h_leafup.cp = pl->h_leafdown.cp = pl->h_m2l.cp = cp;
-    for (auto& s : pl->h_up) s.cp = cp;
-    for (auto& s : pl->h_down) s.cp = cp;
+    const int cp = 32 / pl->R;
+    for (GGSched* s : {&pl->h_leafup, &pl->h_leafdown, &pl->h_m2l}) {
+        s->cp = cp;
+        s->rhs = pl->R;
+    }
+    for (auto& s : pl->h_up) {
+        s.cp = cp;
+        s.rhs = pl->R;
+    }
+    for (auto& s : pl->h_down) {
+        s.cp = cp;
+        s.rhs = pl->R;
+    }
     if (L < 2) return KIFMM_OK;
     const int64_t nleaf = t.n_leaf();
     const int64_t lb = t.level_begin[L];
-    // tiles must keep their (rows x columns) accumulator within the LDS budget
-    auto fit = [&](int want, int rows) {
-        const int cap = (int)(gg_lds_limit() / ((size_t)(rows + 4) * pl->elt * pl->R));
-        return std::max(1, std::min(want, cap));
-    };
-    const int leaf_tile = fit(std::max(16, 128 / pl->R), std::max(pl->kp, pl->nep));
+    const std::vector<double> one{1.0}, inv4pi{1.0 / kFourPi};
     {
         std::vector<int32_t> ptr(nleaf + 1), src(nleaf), cls(nleaf, 0);
         for (int64_t e = 0; e <= nleaf; ++e) ptr[e] = (int32_t)e;
         for (int64_t e = 0; e < nleaf; ++e) src[e] = (int32_t)e;
-        gg_append(pl->h_leafup, lb, nleaf, ptr.data(), src.data(), cls.data(), leaf_tile, 1.0 / kFourPi);
+        const int tile_up = std::min(std::max(16, 128 / pl->R), max_tile_for(pl, 0, pl->nep));
+        gg_build(pl->h_leafup, lb, nleaf, ptr.data(), src.data(), cls.data(), nullptr, inv4pi,
+                 uniform_cuts(nleaf, tile_up));
         for (int64_t e = 0; e < nleaf; ++e) src[e] = (int32_t)(lb + e);
-        gg_append(pl->h_leafdown, 0, nleaf, ptr.data(), src.data(), cls.data(), leaf_tile, 1.0);
+        const int tile_dn = std::min(std::max(16, 128 / pl->R), max_tile_for(pl, 0, pl->kp));
+        gg_build(pl->h_leafdown, 0, nleaf, ptr.data(), src.data(), cls.data(), nullptr, one,
+                 uniform_cuts(nleaf, tile_dn));
     }
-    const int updown_tile = fit(std::max(16, 64 / pl->R), pl->kp);
+    // small levels get small tiles so that their launches still spread over the chip
+    auto level_tile = [&](int64_t nb) {
+        int64_t tl = std::max<int64_t>(16, std::min<int64_t>(64, nb / 256));
+        return (int)std::min<int64_t>(tl / pl->R + 1, max_tile_for(pl, 0, pl->kp));
+    };
     for (int l = 2; l < L; ++l) {
         // targets at level l, sources their children at level l+1 (class = octant)
         const int64_t b0 = t.level_begin[l], nb = t.level_count(l);
@@ -316,7 +389,8 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
             }
             ptr.push_back((int32_t)src.size());
         }
-        gg_append(pl->h_up[l], b0, nb, ptr.data(), src.data(), cls.data(), updown_tile, 1.0);
+        gg_build(pl->h_up[l], b0, nb, ptr.data(), src.data(), cls.data(), nullptr, one,
+                 uniform_cuts(nb, level_tile(nb)));
     }
     for (int l = 3; l <= L; ++l) {
         // targets at level l, source their parent at level l-1 (class = own octant)
@@ -328,24 +402,94 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
             cls[b] = (int32_t)(t.box_key[b0 + b] & 7);
         }
         ptr[nb] = (int32_t)nb;
-        gg_append(pl->h_down[l], b0, nb, ptr.data(), src.data(), cls.data(), updown_tile, 1.0);
+        gg_build(pl->h_down[l], b0, nb, ptr.data(), src.data(), cls.data(), nullptr, one,
+                 uniform_cuts(nb, level_tile(nb)));
     }
-    for (int l = 2; l <= L; ++l) {
-        // every box of levels 2..L gets a tile slot, so that M2L initialises its
-        // local coefficients even when its interaction field is empty
-        const int64_t b0 = t.level_begin[l], nb = t.level_count(l);
-        gg_append(pl->h_m2l, b0, nb, &t.v_ptr[b0], t.v_src.data(), t.v_cls.data(), fit(m2l_tile, pl->kp),
-                  1.0 / t.half_width(l));
-    }
+    // M2L: default shape (the device autotuner may replace it)
+    if (m2l_tile > 0)
+        pl->h_m2l = build_m2l_sched(pl, 0, 0, m2l_tile);
+    else
+        pl->h_m2l = build_m2l_sched(pl, 0, m2l_tiles_for(pl, 0, 0), 0);
     return KIFMM_OK;
 }
 
-int default_m2l_tile(const kifmm_plan_s* pl) {
-    if (pl->opts.tile_targets > 0) return pl->opts.tile_targets;
-    const size_t budget = gg_lds_limit();
-    int tile = (int)(budget / ((size_t)(pl->kp + 4) * pl->elt * pl->R));
-    tile = std::min(tile, 256);
-    return std::max(tile, 1);
+// M2L tile-shape autotuner: time the M2L launch for a few (row blocks per
+// workgroup, workgroup rounds) shapes on the device and keep the fastest.
+// Results are cached per (problem size, k, precision, nrhs width, CU count)
+// for the life of the process.
+struct TuneKey {
+    int64_t n, n_box, v_pairs;
+    int kp, elt, R, num_cu;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(n, n_box, v_pairs, kp, elt, R, num_cu) <
+               std::tie(o.n, o.n_box, o.v_pairs, o.kp, o.elt, o.R, o.num_cu);
+    }
+};
+std::map<TuneKey, std::pair<int, int>>& tune_cache() {
+    static std::map<TuneKey, std::pair<int, int>> c;
+    return c;
+}
+
+void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
+    const HostTree& t = pl->tree;
+    const int64_t nb = t.n_box() - t.level_begin[2];
+    const TuneKey key{t.n, t.n_box(), (int64_t)t.v_src.size(), pl->kp, pl->elt, pl->R, pl->num_cu};
+    std::vector<std::pair<int, int>> cands;   // (kernel shape, extra rounds)
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+        cands.push_back(it->second);
+    } else {
+        for (int v = 0; v < kGGVariants; ++v)
+            for (int r = 0; r < 3; ++r) cands.push_back({v, r});
+    }
+    if (cands.size() == 1) {
+        pl->h_m2l = build_m2l_sched(pl, cands[0].first, m2l_tiles_for(pl, cands[0].first, cands[0].second), 0);
+        pl->d_m2l = upload_sched(up, pl->h_m2l, pl->elt);
+        return;
+    }
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best_ms = 1e30f;
+    std::pair<int, int> best = {0, 0};
+    GGSched best_sched;
+    const int kp16 = pl->kp / 16;
+    for (auto c : cands) {
+        GGSched hs = build_m2l_sched(pl, c.first, m2l_tiles_for(pl, c.first, c.second), 0);
+        std::vector<void*> scratch;
+        Uploader tmp{pl, 0};
+        tmp.scratch = &scratch;
+        DevSched ds = upload_sched(tmp, hs, pl->elt);
+        float ms = 1e30f;
+        if (tmp.err == KIFMM_OK) {
+            bool ok = launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st) == hipSuccess;
+            for (int rep = 0; ok && rep < 3; ++rep) {
+                ok = hipEventRecord(e0, st) == hipSuccess &&
+                     launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st) == hipSuccess &&
+                     hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+                float one = 0.f;
+                if (ok && hipEventElapsedTime(&one, e0, e1) == hipSuccess) ms = std::min(ms, one);
+            }
+        }
+        (void)hipStreamSynchronize(st);
+        for (void* q : scratch) (void)hipFree(q);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+            best_sched = std::move(hs);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (best_ms < 1e29f) {
+        tune_cache()[key] = best;
+        pl->h_m2l = std::move(best_sched);
+        pl->tuned_ms = best_ms;
+    }
+    pl->d_m2l = upload_sched(up, pl->h_m2l, pl->elt);
 }
 
 int check_plan_for_apply(kifmm_plan_t plan) {
@@ -538,13 +682,18 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         delete pl;
         return fail(KIFMM_EINVAL, "n_eq too large for the device kernels (p <= 8 supported)");
     }
-    build_schedules(pl, default_m2l_tile(pl));
     if (o.device >= 0) {
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) {
             delete pl;
             return fail(KIFMM_EHIP, "HIP device " + std::to_string(o.device) + " not available");
         }
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, o.device) == hipSuccess && ncu > 0)
+            pl->num_cu = ncu;
+    }
+    build_schedules(pl, o.tile_targets);
+    if (o.device >= 0) {
         int cur = 0;
         hipGetDevice(&cur);
         hipSetDevice(o.device);
@@ -570,11 +719,13 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         }
         pl->d_leafup = upload_sched(up, pl->h_leafup, pl->elt);
         pl->d_leafdown = upload_sched(up, pl->h_leafdown, pl->elt);
-        pl->d_m2l = upload_sched(up, pl->h_m2l, pl->elt);
+        const bool tune = o.tile_targets == 0 && t.depth >= 2;
+        if (!tune) pl->d_m2l = upload_sched(up, pl->h_m2l, pl->elt);
         pl->d_up.resize(pl->h_up.size());
         pl->d_down.resize(pl->h_down.size());
         for (size_t l = 0; l < pl->h_up.size(); ++l) pl->d_up[l] = upload_sched(up, pl->h_up[l], pl->elt);
         for (size_t l = 0; l < pl->h_down.size(); ++l) pl->d_down[l] = upload_sched(up, pl->h_down[l], pl->elt);
+        if (up.err == KIFMM_OK && tune) autotune_m2l(pl, up);
         hipDeviceSynchronize();
         hipSetDevice(cur);
         if (up.err != KIFMM_OK) {

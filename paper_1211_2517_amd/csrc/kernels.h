@@ -12,11 +12,14 @@ struct DevSched {
     int n_chunks = 0;
     int cp = 16;
     int max_tile = 0;
+    int variant = 0;                    // kernel shape, see gg_variant_rows
     const int32_t* tile_tgt0 = nullptr;
     const int32_t* tile_ntgt = nullptr;
     const int32_t* tile_chunk0 = nullptr;
-    const void* tile_scale = nullptr;   // float or double per precision
     const int32_t* chunk_cls = nullptr;
+    const int32_t* chunk_next = nullptr;
+    const int32_t* chunk_nblk = nullptr;
+    const void* chunk_scale = nullptr;  // float or double per precision
     const int32_t* chunk_src = nullptr;
     const int32_t* chunk_col = nullptr;
 };
@@ -29,10 +32,16 @@ struct DevSched {
 hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, const void* X,
                      int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st);
 
+// Kernel shapes: 0 = 8 waves (128 output rows per workgroup), 1 = 4 waves
+// (64 rows); one 16-row block per wave. Chunks hold 32 / R pairs.
+constexpr int kGGVariants = 2;
+// Output rows per workgroup of a shape (0 for an unknown shape).
+int gg_variant_rows(int variant);
 // Largest dynamic LDS the grouped GEMM may use per workgroup (bytes).
 size_t gg_lds_limit();
-// Per-workgroup LDS bytes of a tile of `cols` columns with MB row blocks.
-size_t gg_lds_bytes(int elt, int MB, int cols);
+// Per-workgroup LDS bytes of a tile of `cols` accumulator columns with K
+// dimension KP16*16.
+size_t gg_lds_bytes(int elt, int variant, int KP16, int cols);
 
 // sig_s[i*R + r] = r < nrhs ? sigma[perm[i] + r*ld] : 0
 hipError_t launch_permute_in(int elt, int R, int64_t n, const int32_t* perm, const void* sigma,

@@ -62,122 +62,239 @@ struct GGParams {
     int R;
     int cp;
     int accumulate;
+    int n_tiles;
+    int n_rg;
     const int32_t* tile_tgt0;
     const int32_t* tile_ntgt;
     const int32_t* tile_chunk0;
-    const void* tile_scale;
     const int32_t* chunk_cls;
+    const int32_t* chunk_next;
+    const int32_t* chunk_nblk;
+    const void* chunk_scale;
     const int32_t* chunk_src;
     const int32_t* chunk_col;
 };
 
-constexpr int kMBW = 2;  // 16-row output blocks owned by one wave
+// Loads through the constant address space: with a wave-uniform index the
+// compiler emits scalar loads, which are counted apart from the vector loads
+// (lgkmcnt, not vmcnt) and so never force the vector-load queue to drain.
+template <typename T>
+__device__ __forceinline__ T uload(const void* base, int idx) {
+    typedef const T __attribute__((address_space(4))) CT;
+    return reinterpret_cast<CT*>(reinterpret_cast<uintptr_t>(base))[idx];
+}
 
-// One workgroup owns one tile of target rows; its (MB*16) x (ntgt*R)
-// accumulator lives in LDS. Wave w owns output row blocks [2w, 2w+2) and walks
-// every chunk of the tile: per class it keeps its rows of A in registers, per
-// chunk it gathers up to 16 columns of X, runs the 16x16x4 MFMA chain over the
-// K dimension and adds the result into its own LDS rows (no two lanes or
-// waves touch the same LDS word in one step, so no atomics are needed).
+// Grouped gather GEMM: Y[t] (+)= scale * sum_chunks A[cls] X[src].
+//
+// A workgroup owns one (tile, row group): the targets of the tile and WAVES
+// 16-row blocks of the output, one per wave. Its accumulator (rows x ntgt*R
+// columns) lives in LDS. The chunks of a tile are sorted by class; a chunk
+// holds up to 32 columns (two 16-column MFMA blocks, the second one only when
+// used) of one class. Per chunk the workgroup
+//   - stages the gathered source columns of X in an LDS buffer, loaded by all
+//     threads one chunk ahead (double buffer, one barrier per chunk);
+//   - each wave multiplies its 16 rows of A[cls], held in registers for the
+//     whole run of chunks of one class (the next class's rows are prefetched
+//     one chunk ahead of a class change), by the staged columns on 16x16x4
+//     MFMA and adds the result into its own LDS rows.
+// Chunk metadata that is uniform across a wave (class, next class, block
+// count, scale and the source index of each staged column) is read with
+// scalar loads; only the gathered data and the per-lane target column are
+// vector loads, issued so that every wait retires only what it needs.
+// Within a chunk the target columns are distinct and each wave owns its
+// rows, so no two lanes or waves update the same LDS word at the same time
+// and the summation order is fixed (results are bitwise reproducible).
 //
 // MFMA operand layout (v_mfma_*_16x16x4): lane l supplies A[l%16][kk] and
 // B[kk][l%16] of one K-step and holds D[Mfma<T>::row(q, l/16)][l%16]. The K
 // order is permuted so that both operands are read as 4-wide vectors: in
 // K-chunk t, lane group g = l/16 supplies indices 16t + 4g + e for the 4
 // consecutive MFMA steps e = 0..3.
-template <typename T, int KP16>
-__global__ void __launch_bounds__(1024) gg_kernel(GGParams p) {
+//
+// Block b maps to tile (b / (8*n_rg))*8 + b%8 and row group (b/8) % n_rg, so
+// the row groups of a tile run on the same XCD (blocks are dealt to the 8 XCDs
+// round-robin) and share its L2 for the gathered columns.
+template <typename T, int KP16, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) gg_kernel(GGParams p) {
     using M = Mfma<T>;
     using V4 = typename M::V4;
+    constexpr int NT = 64 * WAVES;
+    constexpr int KDIM = KP16 * 16;
+    constexpr int LDB = KDIM + 4;          // LDS stride of one staged column
+    constexpr int V4C = KDIM / 4;          // 4-vectors per column
+    constexpr int CPL = V4C >= 64 ? 1 : 64 / V4C;   // columns covered by one wave-wide load
+    constexpr int LPC = (V4C + 63) / 64;             // wave-wide loads per column (wide K)
+    constexpr int GRP = CPL * WAVES;                 // columns covered per load round by the workgroup
+    constexpr int NLD = ((32 + GRP - 1) / GRP) * LPC;   // loads per lane per chunk
+    const int b = blockIdx.x;
+    const int rg = (b >> 3) % p.n_rg;
+    const int tile = (b / (8 * p.n_rg)) * 8 + (b & 7);
+    if (tile >= p.n_tiles) return;
+
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* acc = reinterpret_cast<T*>(smem_raw);
-    const int tile = blockIdx.x;
+    T* bbuf = reinterpret_cast<T*>(smem_raw);   // [2][32][LDB]
+    T* acc = bbuf + 2 * 32 * LDB;               // [ncol][ldl]
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int rows = p.MB * 16;
-    const int ldl = rows + 4;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int mb_lo = rg * WAVES;
+    const int nmb = min(WAVES, p.MB - mb_lo);
+    const int rows = nmb * 16;
+    const int ldl = WAVES * 16 + 4;
     const int R = p.R;
-    const int t0 = p.tile_tgt0[tile];
-    const int ncol = p.tile_ntgt[tile] * R;
+    const int cp = p.cp;
+    const int t0 = uload<int32_t>(p.tile_tgt0, tile);
+    const int ncol = uload<int32_t>(p.tile_ntgt, tile) * R;
     const T* __restrict__ X = static_cast<const T*>(p.X);
     const T* __restrict__ A = static_cast<const T*>(p.A);
     T* __restrict__ Y = static_cast<T*>(p.Y);
 
     const int64_t ybase = (int64_t)t0 * R;
-    for (int idx = threadIdx.x; idx < ncol * rows; idx += blockDim.x) {
+    const int row0 = mb_lo * 16;
+    for (int idx = threadIdx.x; idx < ncol * rows; idx += NT) {
         const int col = idx / rows;
         const int row = idx - col * rows;
-        acc[col * ldl + row] = p.accumulate ? Y[(ybase + col) * p.ldy + row] : T(0);
+        acc[col * ldl + row] = p.accumulate ? Y[(ybase + col) * p.ldy + row0 + row] : T(0);
     }
-    __syncthreads();
 
+    const int cb = uload<int32_t>(p.tile_chunk0, tile);
+    const int ce = uload<int32_t>(p.tile_chunk0, tile + 1);
     const int j = lane & 15;
     const int grp = lane >> 4;
-    const int mb0 = wave * kMBW;
-    const T scale = static_cast<const T*>(p.tile_scale)[tile];
-    const int cb = p.tile_chunk0[tile];
-    const int ce = p.tile_chunk0[tile + 1];
-    const int pj = j / R;
-    const int rj = j - pj * R;
+    const bool wact = wave < nmb;
+    const T* arow = A + (int64_t)(row0 + (wact ? wave : 0) * 16 + j) * p.lda + 4 * grp;
 
-    V4 a[kMBW][KP16];
-    int cur = -1;
-    for (int ch = cb; ch < ce; ++ch) {
-        const int cls = p.chunk_cls[ch];
-        if (cls != cur) {
-            cur = cls;
-            const T* Ac = A + (int64_t)cls * p.a_stride;
+    // staging map: load i of this lane covers staged column sc[i] (0..31),
+    // 4-vector part sp[i] of it. In load i the wave covers the CPL columns
+    // scb[i] .. scb[i]+CPL-1 (lane / V4C picks one). Lanes beyond them repeat
+    // a valid (column, part), so every lane issues the same loads and stores
+    // (duplicates write identical values); no load is predicated.
+    int sc[NLD], sp[NLD], scb[NLD];
 #pragma unroll
-            for (int m = 0; m < kMBW; ++m) {
-                const int mb = mb0 + m;
-                const T* ar = Ac + (int64_t)(mb * 16 + j) * p.lda + 4 * grp;
+    for (int i = 0; i < NLD; ++i) {
+        const int unit = i / LPC;                       // which column round
+        const int sub = i - unit * LPC;                 // which 64-wide slice of a long column
+        scb[i] = (unit * WAVES + wave) * CPL;
+        const int q = CPL > 1 ? min(lane / V4C, CPL - 1) : 0;
+        sc[i] = min(scb[i] + q, 31);
+        sp[i] = min((CPL > 1 ? lane - q * V4C : lane) + sub * 64, V4C - 1);
+    }
+    V4 stg[NLD];
+    // Empty pair slots hold source -1 and load row 0 (a valid row): their
+    // products land only in output columns that are never stored. All source
+    // indices are fetched first (scalar loads), then all gathers are issued.
+    auto stage_load = [&](int ch) {
+        int src[NLD];
 #pragma unroll
-                for (int t = 0; t < KP16; ++t) {
-                    if (mb < p.MB)
-                        a[m][t] = *reinterpret_cast<const V4*>(ar + 16 * t);
-                    else
-                        a[m][t] = V4{0, 0, 0, 0};
-                }
+        for (int i = 0; i < NLD; ++i) {
+            int s = 0;
+#pragma unroll
+            for (int q = 0; q < CPL; ++q) {
+                const int c = min(scb[i] + q, 31);
+                const int sq = uload<int32_t>(p.chunk_src, ch * cp + c / R);
+                if (sc[i] == c) s = sq;
             }
+            src[i] = max(s, 0);
         }
-        const int src = p.chunk_src[ch * p.cp + pj];
-        const int col = p.chunk_col[ch * p.cp + pj];
-        V4 b[KP16];
-        if (src >= 0) {
-            const T* xs = X + ((int64_t)src * R + rj) * p.ldx + 4 * grp;
 #pragma unroll
-            for (int t = 0; t < KP16; ++t) b[t] = *reinterpret_cast<const V4*>(xs + 16 * t);
-        } else {
-#pragma unroll
-            for (int t = 0; t < KP16; ++t) b[t] = V4{0, 0, 0, 0};
+        for (int i = 0; i < NLD; ++i) {
+            const int c = sc[i];
+            const int pj = c / R;
+            stg[i] = *reinterpret_cast<const V4*>(X + ((int64_t)src[i] * R + (c - pj * R)) * p.ldx + 4 * sp[i]);
         }
-        V4 d[kMBW];
+    };
+    auto stage_store = [&](int buf) {
 #pragma unroll
-        for (int m = 0; m < kMBW; ++m) d[m] = V4{0, 0, 0, 0};
+        for (int i = 0; i < NLD; ++i) *reinterpret_cast<V4*>(bbuf + (buf * 32 + sc[i]) * LDB + 4 * sp[i]) = stg[i];
+    };
+    // A rows of the current class run and of the next one; the two register
+    // sets swap roles from run to run (the run loop below is unrolled by two),
+    // so a prefetch lands directly in the registers that will use it.
+    V4 a0[KP16];
+    V4 a1[KP16];
+    auto load_a = [&](V4 (&dst)[KP16], int cls) {
+        const T* ar = arow + (int64_t)cls * p.a_stride;
 #pragma unroll
-        for (int t = 0; t < KP16; ++t) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-#pragma unroll
-                for (int m = 0; m < kMBW; ++m) d[m] = M::step(a[m][t][e], b[t][e], d[m]);
-            }
-        }
-        if (col >= 0) {
-#pragma unroll
-            for (int m = 0; m < kMBW; ++m) {
-                if (mb0 + m < p.MB) {
-                    T* dst = acc + (col * R + rj) * ldl + (mb0 + m) * 16;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) dst[M::row(q, grp)] += scale * d[m][q];
-                }
-            }
-        }
+        for (int t = 0; t < KP16; ++t) dst[t] = *reinterpret_cast<const V4*>(ar + 16 * t);
+    };
+
+    const int pj16 = j / R;
+    const int rj = j - pj16 * R;
+    int col0 = -1, col1 = -1;   // target columns of the current chunk (both blocks)
+    if (cb < ce) {
+        load_a(a0, uload<int32_t>(p.chunk_cls, cb));
+        stage_load(cb);
+        stage_store(0);
+        col0 = p.chunk_col[cb * cp + pj16];
+        col1 = p.chunk_col[cb * cp + (16 / R) + pj16];
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < ncol * rows; idx += blockDim.x) {
+
+    // one chunk: stage chunk ch+1 (and its target columns) while the MFMAs of chunk ch run
+    auto step = [&](int ch, const V4 (&a)[KP16]) {
+        const int buf = (ch - cb) & 1;
+        // scalar metadata first: scalar and LDS loads share one counter, and
+        // scalar ones return out of order, so none may be pending at the MFMAs
+        const int nb = uload<int32_t>(p.chunk_nblk, ch);
+        const T scale = uload<T>(p.chunk_scale, ch);
+        const int chn = min(ch + 1, ce - 1);
+        const int ncol0 = p.chunk_col[chn * cp + pj16];
+        const int ncol1 = p.chunk_col[chn * cp + (16 / R) + pj16];
+        stage_load(chn);
+        if (wact) {
+#pragma unroll
+            for (int blk = 0; blk < 2; ++blk) {
+                if (blk < nb) {
+                    const T* bcol = bbuf + (buf * 32 + blk * 16 + j) * LDB + 4 * grp;
+                    V4 bv[KP16];
+#pragma unroll
+                    for (int t = 0; t < KP16; ++t) bv[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
+                    // issue every LDS read of the block before the first MFMA
+                    __builtin_amdgcn_sched_barrier(0);
+                    V4 d0 = V4{0, 0, 0, 0};
+                    V4 d1 = V4{0, 0, 0, 0};
+#pragma unroll
+                    for (int t = 0; t < KP16; ++t) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            if (t & 1)
+                                d1 = M::step(a[t][e], bv[t][e], d1);
+                            else
+                                d0 = M::step(a[t][e], bv[t][e], d0);
+                        }
+                    }
+                    const int col = blk ? col1 : col0;
+                    if (col >= 0) {
+                        T* dst = acc + (col * R + rj) * ldl + wave * 16;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dst[M::row(q, grp)] += scale * (d0[q] + d1[q]);
+                    }
+                }
+            }
+        }
+        stage_store(buf ^ 1);
+        col0 = ncol0;
+        col1 = ncol1;
+        __syncthreads();
+    };
+    // one class run: prefetch the next run's A rows, then its chunks
+    auto run = [&](int ch, const V4 (&a)[KP16], V4 (&nxt)[KP16]) {
+        const int cls = uload<int32_t>(p.chunk_cls, ch);
+        const int nx = uload<int32_t>(p.chunk_next, ch);
+        load_a(nxt, nx >= 0 ? nx : cls);   // unconditional, so every path issues the same loads
+        do {
+            step(ch, a);
+            ++ch;
+        } while (ch < ce && uload<int32_t>(p.chunk_cls, ch) == cls);
+        return ch;
+    };
+    for (int ch = cb; ch < ce;) {
+        ch = run(ch, a0, a1);
+        if (ch < ce) ch = run(ch, a1, a0);
+    }
+    for (int idx = threadIdx.x; idx < ncol * rows; idx += NT) {
         const int col = idx / rows;
         const int row = idx - col * rows;
-        Y[(ybase + col) * p.ldy + row] = acc[col * ldl + row];
+        Y[(ybase + col) * p.ldy + row0 + row] = acc[col * ldl + row];
     }
 }
 
@@ -300,25 +417,25 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     }
 }
 
-template <typename T, int KP16>
-hipError_t gg_launch_t(const GGParams& p, int n_tiles, int waves, size_t lds, hipStream_t st) {
+template <typename T, int KP16, int WAVES>
+hipError_t gg_launch_t(const GGParams& p, int blocks, size_t lds, hipStream_t st) {
     static size_t attr_set = 0;
     if (lds > 65536 && lds > attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gg_kernel<T, KP16>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = lds;
     }
-    hipLaunchKernelGGL((gg_kernel<T, KP16>), dim3(n_tiles), dim3(64 * waves), lds, st, p);
+    hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t gg_dispatch(int KP16, const GGParams& p, int n_tiles, int waves, size_t lds, hipStream_t st) {
+template <typename T, int WAVES>
+hipError_t gg_dispatch(int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st) {
     switch (KP16) {
 #define KIFMM_GG_CASE(K) \
     case K:              \
-        return gg_launch_t<T, K>(p, n_tiles, waves, lds, st);
+        return gg_launch_t<T, K, WAVES>(p, blocks, lds, st);
         KIFMM_GG_CASE(1) KIFMM_GG_CASE(2) KIFMM_GG_CASE(3) KIFMM_GG_CASE(4) KIFMM_GG_CASE(5)
         KIFMM_GG_CASE(6) KIFMM_GG_CASE(7) KIFMM_GG_CASE(8) KIFMM_GG_CASE(9) KIFMM_GG_CASE(10)
         KIFMM_GG_CASE(11) KIFMM_GG_CASE(12) KIFMM_GG_CASE(13) KIFMM_GG_CASE(14) KIFMM_GG_CASE(15)
@@ -329,11 +446,30 @@ hipError_t gg_dispatch(int KP16, const GGParams& p, int n_tiles, int waves, size
     }
 }
 
+template <typename T>
+hipError_t gg_variant(int variant, int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st) {
+    switch (variant) {
+        case 0: return gg_dispatch<T, 8>(KP16, p, blocks, lds, st);
+        case 1: return gg_dispatch<T, 4>(KP16, p, blocks, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+int gg_variant_rows(int variant) {
+    switch (variant) {
+        case 0: return 8 * 16;
+        case 1: return 4 * 16;
+        default: return 0;
+    }
+}
 
 size_t gg_lds_limit() { return 160 * 1024; }
 
-size_t gg_lds_bytes(int elt, int MB, int cols) { return (size_t)cols * (MB * 16 + 4) * elt; }
+size_t gg_lds_bytes(int elt, int variant, int KP16, int cols) {
+    return ((size_t)2 * 32 * (KP16 * 16 + 4) + (size_t)cols * (gg_variant_rows(variant) + 4)) * elt;
+}
 
 hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, const void* X,
                      int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st) {
@@ -350,18 +486,24 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
     p.R = R;
     p.cp = s.cp;
     p.accumulate = accumulate;
+    p.n_tiles = s.n_tiles;
+    const int mbg = gg_variant_rows(s.variant) / 16;
+    if (mbg == 0 || s.cp * R != 32) return hipErrorInvalidValue;
+    p.n_rg = (MB + mbg - 1) / mbg;
     p.tile_tgt0 = s.tile_tgt0;
     p.tile_ntgt = s.tile_ntgt;
     p.tile_chunk0 = s.tile_chunk0;
-    p.tile_scale = s.tile_scale;
     p.chunk_cls = s.chunk_cls;
+    p.chunk_next = s.chunk_next;
+    p.chunk_nblk = s.chunk_nblk;
+    p.chunk_scale = s.chunk_scale;
     p.chunk_src = s.chunk_src;
     p.chunk_col = s.chunk_col;
-    const int waves = (MB + kMBW - 1) / kMBW;
-    const size_t lds = gg_lds_bytes(elt, MB, s.max_tile * R);
-    if (lds > gg_lds_limit() || waves > 16) return hipErrorInvalidValue;
-    if (elt == 4) return gg_dispatch<float>(KP16, p, s.n_tiles, waves, lds, st);
-    return gg_dispatch<double>(KP16, p, s.n_tiles, waves, lds, st);
+    const size_t lds = gg_lds_bytes(elt, s.variant, KP16, s.max_tile * R);
+    if (lds > gg_lds_limit() || KP16 < 1 || KP16 > 19) return hipErrorInvalidValue;
+    const int blocks = (s.n_tiles + 7) / 8 * 8 * p.n_rg;
+    if (elt == 4) return gg_variant<float>(s.variant, KP16, p, blocks, lds, st);
+    return gg_variant<double>(s.variant, KP16, p, blocks, lds, st);
 }
 
 #define KIFMM_R_SWITCH(R, BODY)                      \

@@ -428,49 +428,86 @@ HostOps build_host_ops(int p, double eps, int leaf_size, double cd, double rcond
     return o;
 }
 
-void gg_append(GGSched& s, int64_t tgt_row0, int64_t n_tgt, const int32_t* ptr, const int32_t* src,
-               const int32_t* cls, int tile, double scale) {
+std::vector<int64_t> uniform_cuts(int64_t n_tgt, int tile) {
+    std::vector<int64_t> cuts;
+    for (int64_t t = 0; t < n_tgt; t += tile) cuts.push_back(t);
+    cuts.push_back(n_tgt);
+    return cuts;
+}
+
+std::vector<int64_t> balanced_cuts(int64_t n_tgt, const int32_t* ptr, int n_tiles, int max_tile,
+                                   double per_target) {
+    std::vector<int64_t> cuts{0};
+    if (n_tgt == 0) return cuts;
+    const double total = double(ptr[n_tgt] - ptr[0]) + per_target * double(n_tgt);
+    const double quota = total / std::max(1, n_tiles);
+    double acc = 0.0;
+    int64_t start = 0;
+    for (int64_t t = 0; t < n_tgt; ++t) {
+        acc += double(ptr[t + 1] - ptr[t]) + per_target;
+        const bool full = (t + 1 - start) >= max_tile;
+        if (t + 1 < n_tgt && (full || acc >= quota * double(cuts.size()))) {
+            cuts.push_back(t + 1);
+            start = t + 1;
+        }
+    }
+    cuts.push_back(n_tgt);
+    return cuts;
+}
+
+void gg_build(GGSched& s, int64_t tgt_row0, int64_t n_tgt, const int32_t* ptr, const int32_t* src,
+              const int32_t* cls, const int32_t* group, const std::vector<double>& group_scale,
+              const std::vector<int64_t>& cuts) {
     if (s.tile_chunk0.empty()) s.tile_chunk0.push_back(0);
-    std::vector<int32_t> cnt;
-    std::vector<int32_t> order;
-    for (int64_t t0 = 0; t0 < n_tgt; t0 += tile) {
-        const int64_t t1 = std::min<int64_t>(n_tgt, t0 + tile);
-        const int32_t pb = ptr[t0], pe = ptr[t1];
+    struct Item {
+        int64_t key;
+        int32_t q;
+        int32_t col;
+    };
+    std::vector<Item> items;
+    for (size_t c = 0; c + 1 < cuts.size(); ++c) {
+        const int64_t t0 = cuts[c], t1 = cuts[c + 1];
+        if (t1 <= t0) continue;
         s.tile_tgt0.push_back((int32_t)(tgt_row0 + t0));
         s.tile_ntgt.push_back((int32_t)(t1 - t0));
-        s.tile_scale.push_back(scale);
         s.max_tile = std::max<int>(s.max_tile, (int)(t1 - t0));
-        // counting sort of the tile's pairs by class (stable in target order)
-        int maxc = 0;
-        for (int32_t q = pb; q < pe; ++q) maxc = std::max(maxc, cls[q] + 1);
-        cnt.assign(maxc + 1, 0);
-        for (int32_t q = pb; q < pe; ++q) cnt[cls[q] + 1]++;
-        for (int c = 0; c < maxc; ++c) cnt[c + 1] += cnt[c];
-        order.assign(pe - pb, 0);
-        std::vector<int32_t> pos(cnt.begin(), cnt.end());
-        std::vector<int32_t> col_of(pe - pb);
-        for (int64_t t = t0; t < t1; ++t)
-            for (int32_t q = ptr[t]; q < ptr[t + 1]; ++q) {
-                order[pos[cls[q]]++] = q;
-                col_of[q - pb] = (int32_t)(t - t0);
-            }
-        int64_t i = 0;
-        const int64_t np = pe - pb;
-        while (i < np) {
-            const int c = cls[order[i]];
-            s.chunk_cls.push_back(c);
+        items.clear();
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t g = group ? group[t] : 0;
+            for (int32_t q = ptr[t]; q < ptr[t + 1]; ++q)
+                items.push_back({g * NCLASS * 8 + cls[q], q, (int32_t)(t - t0)});
+        }
+        std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.key < b.key; });
+        const size_t first_chunk = s.chunk_cls.size();
+        size_t i = 0;
+        while (i < items.size()) {
+            const int64_t key = items[i].key;
+            const int64_t g = key / (NCLASS * 8);
+            s.chunk_cls.push_back(cls[items[i].q]);
+            s.chunk_scale.push_back(group_scale[g]);
+            int used = 0;
             for (int j = 0; j < s.cp; ++j) {
-                if (i < np && cls[order[i]] == c) {
-                    s.chunk_src.push_back(src[order[i]]);
-                    s.chunk_col.push_back(col_of[order[i] - pb]);
+                if (i < items.size() && items[i].key == key) {
+                    s.chunk_src.push_back(src[items[i].q]);
+                    s.chunk_col.push_back(items[i].col);
                     ++i;
+                    ++used;
                 } else {
                     s.chunk_src.push_back(-1);
                     s.chunk_col.push_back(-1);
                 }
             }
+            s.chunk_nblk.push_back((used * s.rhs + 15) / 16);
         }
-        s.pairs += np;
+        // class of the next chunk with a different class, within this tile
+        const size_t last = s.chunk_cls.size();
+        s.chunk_next.resize(last, -1);
+        int next = -1;
+        for (size_t ch = last; ch-- > first_chunk;) {
+            s.chunk_next[ch] = next;
+            if (ch > first_chunk && s.chunk_cls[ch - 1] != s.chunk_cls[ch]) next = s.chunk_cls[ch];
+        }
+        s.pairs += (int64_t)items.size();
         s.tile_chunk0.push_back((int32_t)s.chunk_cls.size());
     }
 }

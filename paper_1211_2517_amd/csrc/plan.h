@@ -68,17 +68,22 @@ struct HostOps {
 HostOps build_host_ops(int p, double eps, int leaf_size, double cd, double rcond, bool dense);
 
 // Work schedule of the grouped gather GEMM Y[t] (+)= scale * sum A[cls] X[src].
+// `cp` pairs of one class form a chunk; `rhs` right-hand-side columns per pair.
 // Targets are split into tiles of consecutive rows; inside a tile the
-// (target, source, class) pairs are sorted by class and cut into chunks of at
-// most `cp` pairs of one class.
+// (target, source, class) pairs are sorted by (scale group, class) and cut
+// into chunks of at most `cp` pairs that share one class and one scale.
 struct GGSched {
-    int cp = 16;
+    int cp = 32;
+    int rhs = 1;
     int max_tile = 0;
+    int variant = 0;                   // grouped-GEMM kernel shape
     std::vector<int32_t> tile_tgt0;    // first target row of the tile
     std::vector<int32_t> tile_ntgt;    // targets in the tile
     std::vector<int32_t> tile_chunk0;  // n_tiles + 1
-    std::vector<double> tile_scale;
     std::vector<int32_t> chunk_cls;
+    std::vector<int32_t> chunk_next;   // class of the next chunk of the tile whose class differs, -1 if none
+    std::vector<int32_t> chunk_nblk;   // 16-column blocks holding data (ceil(pairs * R / 16))
+    std::vector<double> chunk_scale;
     std::vector<int32_t> chunk_src;    // n_chunks * cp (-1 = empty slot)
     std::vector<int32_t> chunk_col;    // n_chunks * cp (target column in the tile, -1 = empty)
     int64_t pairs = 0;
@@ -86,10 +91,19 @@ struct GGSched {
     int n_chunks() const { return (int)chunk_cls.size(); }
 };
 
-// Append the targets [0, n_tgt) (rows tgt_row0 + i of Y) whose pairs are given
-// in CSR form (ptr over targets; src rows of X and class ids), in tiles of
-// `tile` targets with the given scale.
-void gg_append(GGSched& s, int64_t tgt_row0, int64_t n_tgt, const int32_t* ptr,
-               const int32_t* src, const int32_t* cls, int tile, double scale);
+// Append the targets [0, n_tgt) (rows tgt_row0 + i of Y), whose pairs are
+// given in CSR form (ptr over targets, absolute indices into src/cls), cut
+// into tiles at `cuts` (strictly increasing, 0 ... n_tgt). Target i uses the
+// scale group_scale[group ? group[i] : 0].
+void gg_build(GGSched& s, int64_t tgt_row0, int64_t n_tgt, const int32_t* ptr, const int32_t* src,
+              const int32_t* cls, const int32_t* group, const std::vector<double>& group_scale,
+              const std::vector<int64_t>& cuts);
+
+// Tiles of `tile` consecutive targets.
+std::vector<int64_t> uniform_cuts(int64_t n_tgt, int tile);
+// About `n_tiles` tiles of equal cost (pairs + `per_target` per target), none
+// larger than `max_tile` targets.
+std::vector<int64_t> balanced_cuts(int64_t n_tgt, const int32_t* ptr, int n_tiles, int max_tile,
+                                   double per_target);
 
 }  // namespace kifmm
