@@ -109,7 +109,7 @@ int kifmm_opts_default(kifmm_opts_t* o);
 
 /* Build a plan (Alg. Step 1, Sec. 4.3): octree over the points (Sec. 2.1), near
  * and interaction fields, surfaces (Sec. 2.1 with d of Sec. 4.1), operators in
- * FP64 (S, M, K, L, T of eqs. (3)-(7); stage-1 SVD of Sec. 3.1 keeping singular
+ * FP64 (S, M, K, L, T of Sec. 2.2; stage-1 SVD of Sec. 3.1 keeping singular
  * values >= eps * Sigma_00; reduced operators of Sec. 3.3), the M2L work
  * schedule, and the upload of all of it to the device.
  *   points:    host, n x 3 row-major doubles (x0,y0,z0,x1,...); copied.

@@ -13,7 +13,7 @@ multipole method and its application to BEM"):
                   G(x,y) = 1/(4 pi |x-y|) of Sec. 4 (pairs at distance 0 add 0).
 * ``fmm``       - the KIFMM of Sec. 2 evaluated step by step as in the complete
                   algorithm of Sec. 4.3, either uncompressed (``mode="dense"``,
-                  M2L matrices K of eq. (5)) or with the stage-1 SVD compression
+                  M2L matrices K of Sec. 2.2) or with the stage-1 SVD compression
                   of Sec. 3.1 and the reduced upward/downward operators of
                   Sec. 3.3 (``mode="svd"``).
 

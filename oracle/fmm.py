@@ -57,9 +57,9 @@ def fmm(x: np.ndarray, sigma: np.ndarray, p: int, eps: float, leaf_size: int,
         rL = tree.half_width(L)
         for b, idx in tree.leaf_points.items():
             c = tree.box_centre(L, b)
-            check = kernel_matrix(c + rL * ops.UC, x[idx]) @ s[idx]   # S2M, eq. (3)
+            check = kernel_matrix(c + rL * ops.UC, x[idx]) @ s[idx]   # S2M, Sec. 2.2
             up[L][b] = rL * (ops.S @ check)
-        for level in range(L - 1, 1, -1):                               # M2M, eq. (4)
+        for level in range(L - 1, 1, -1):                               # M2M, Sec. 2.2
             for b in tree.boxes[level]:
                 acc = np.zeros((ops.k, nrhs))
                 for o in [(0, 0, 0), (0, 0, 1), (0, 1, 0), (0, 1, 1),
@@ -85,16 +85,16 @@ def fmm(x: np.ndarray, sigma: np.ndarray, p: int, eps: float, leaf_size: int,
         r = tree.half_width(level)
         for b in need[level]:
             acc = np.zeros((ops.k, nrhs))
-            if level > 2:                                               # L2L, eq. (6)
+            if level > 2:                                               # L2L, Sec. 2.2
                 parent = (b[0] >> 1, b[1] >> 1, b[2] >> 1)
                 o = (b[0] & 1, b[1] & 1, b[2] & 1)
                 acc += ops.L[_sign(o)] @ down[level - 1][parent]
-            for c in tree.interaction(level, b):                       # M2L, eq. (5)
+            for c in tree.interaction(level, b):                       # M2L, Sec. 2.2
                 t = (b[0] - c[0], b[1] - c[1], b[2] - c[2])
                 acc += (ops.K[t] @ up[level][c]) / r
             down[level][b] = acc
 
-    # ---- L2T (eq. (7)) and Step 4 S2T ---------------------------------------
+    # ---- L2T (Sec. 2.2) and Step 4 S2T ----------------------------------------
     phi = np.zeros((x.shape[0], nrhs))
     rL = tree.half_width(L)
     for b in leaves:

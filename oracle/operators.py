@@ -11,16 +11,16 @@ All operators are built for the cube of unit half-width centred at 0; the
 kernel 1/(4 pi r) is homogeneous of degree -1 (Sec. 3.1), which gives the
 level scalings used by the evaluation:
 
-* S2M (eq. (3)): q^u = r * P_up * (upward check potential), P_up the
+* S2M (Sec. 2.2): q^u = r * P_up * (upward check potential), P_up the
   pseudo-inverse of G(upward check, upward equivalent);
-* M2M (eq. (4)): M^o = P_up G(UC, (o + UE)/2), o in {-1,1}^3 the child offset;
-* M2L (eq. (5)): K^(t) = G(DC + 2t, UE), t the integer centre offset in units
+* M2M (Sec. 2.2): M^o = P_up G(UC, (o + UE)/2), o in {-1,1}^3 the child offset;
+* M2L (Sec. 2.2): K^(t) = G(DC + 2t, UE), t the integer centre offset in units
   of the cube width, scaled by 1/r at half-width r; the 316 offsets with
   max |t_a| in {2,3} are the classes;
-* L2L (eq. (6)): L^o = G((o + DC)/2, DE) P_dn, P_dn = pinv(G(DC, DE));
-* L2T (eq. (7)): e = r * P_dn * p^d, then the potential of e on DE.
+* L2L (Sec. 2.2): L^o = G((o + DC)/2, DE) P_dn, P_dn = pinv(G(DC, DE));
+* L2T (Sec. 2.2): e = r * P_dn * p^d, then the potential of e on DE.
 
-Stage-1 compression (Sec. 3.1, eqs. (9)-(13)): U from the SVD of
+Stage-1 compression (Sec. 3.1: the fat/thin SVDs and the compressed K~): U from the SVD of
 K_fat = [K^(1) ... K^(316)]; keep the columns whose singular value is at least
 eps * Sigma_00. Because the downward check and upward equivalent surfaces
 coincide, K^(-t) = K^(t)^T, so K_thin is a block permutation of K_fat^T and its

@@ -1,14 +1,14 @@
 // Device kernels of the KIFMM evaluation for gfx950 (CDNA4, wave64).
 //
 // gg_kernel      grouped gather GEMM on MFMA: the S2M/L2T reduced-operator
-//                products (Sec. 3.3), M2M and L2L (eqs. (4), (6)) and the
-//                compressed M2L (eq. (13) with the level scaling of Sec. 3.1).
+//                products (Sec. 3.3), M2M and L2L (Sec. 2.2 and their reduced forms) and the
+//                compressed M2L (Sec. 3.1, K~ applied with the homogeneous level scaling).
 // eval_surface   potential of the points of a leaf on the (3-2d) cube surface:
-//                the check potential of S2M (eq. (3)) and, in the adjoint,
+//                the check potential of S2M (Sec. 2.2) and, in the adjoint,
 //                the transpose of the L2T evaluation.
 // eval_targets   near-field direct sum of eq. (1) over the near field (S2T)
 //                plus the potential of the downward equivalent densities on
-//                the leaf's points (L2T, eq. (7)), scattered to caller order.
+//                the leaf's points (L2T, Sec. 2.2), scattered to caller order.
 #include "kernels.h"
 
 namespace kifmm {
