@@ -151,7 +151,8 @@ def main():
             sd_run, out_run = sd, out
         info = plan.info()
         log(f"{name}: depth {info['depth']} k {info['k']} v_pairs {info['v_pairs']} "
-            f"plan {info['plan_seconds']:.1f}s, M2L tile <= {info['m2l_tile_targets']} targets; "
+            f"plan {info['plan_seconds']:.1f}s, M2L tile <= {info['m2l_tile_targets']} targets, "
+            f"{info['m2l_tiles']} tiles, kernel shape {info['m2l_variant']}; "
             f"timing {args.steps} steps")
         ms, wall, stages = time_plan(plan, sd_run, out_run, args.steps, args.warmup)
         got = out_run.double().cpu().numpy()[idx]

@@ -72,6 +72,9 @@ typedef struct {
     size_t mem_limit;   /* fail with KIFMM_ENOMEM if the plan's device memory would exceed
                            this many bytes; 0 = no limit */
     int tile_targets;   /* target boxes per M2L work tile; 0 = autotune on the device */
+    int m2l_shape;      /* M2L kernel shape (see kifmm_info_t.m2l_variant); -1 = autotuned
+                           (default), 0..2 forces one shape (the tile count is still tuned
+                           unless tile_targets > 0) */
 } kifmm_opts_t;
 
 /* Per-stage counters; index with the KIFMM_STAGE_* values. */
@@ -102,6 +105,9 @@ typedef struct {
     int m2l_tile_targets;   /* tile size in use */
     double sigma0;          /* largest singular value of K_fat (svd mode), else 0 */
     double plan_seconds;    /* wall time of the plan call */
+    int m2l_variant;        /* M2L kernel shape in use: 0 = 8 waves x 16 rows per workgroup,
+                               1 = 4 waves x 16 rows, 2 = 4 waves x 16 rows at two workgroups per CU */
+    int m2l_tiles;          /* M2L target tiles (workgroups = tiles x row groups) */
 } kifmm_info_t;
 
 /* Fill `o` with the defaults listed above. Returns KIFMM_EINVAL if o is NULL. */

@@ -181,15 +181,20 @@ DevSched upload_sched(Uploader& up, const GGSched& s, int elt) {
     d.tile_tgt0 = (const int32_t*)up.put(s.tile_tgt0);
     d.tile_ntgt = (const int32_t*)up.put(s.tile_ntgt);
     d.tile_chunk0 = (const int32_t*)up.put(s.tile_chunk0);
-    d.chunk_cls = (const int32_t*)up.put(s.chunk_cls);
-    d.chunk_next = (const int32_t*)up.put(s.chunk_next);
-    d.chunk_nblk = (const int32_t*)up.put(s.chunk_nblk);
-    if (elt == 4) {
-        std::vector<float> f(s.chunk_scale.begin(), s.chunk_scale.end());
-        d.chunk_scale = up.put(f);
-    } else {
-        d.chunk_scale = up.put(s.chunk_scale);
+    for (int32_t v : s.chunk_src) d.max_src = std::max(d.max_src, v);
+    for (int32_t v : s.chunk_cls) d.max_cls = std::max(d.max_cls, v);
+    std::vector<int32_t> meta((size_t)4 * d.n_chunks, 0);
+    for (int c = 0; c < d.n_chunks; ++c) {
+        meta[4 * c] = s.chunk_cls[c];
+        meta[4 * c + 1] = s.chunk_nblk[c];
+        if (elt == 4) {
+            const float f = (float)s.chunk_scale[c];
+            std::memcpy(&meta[4 * c + 2], &f, sizeof f);
+        } else {
+            std::memcpy(&meta[4 * c + 2], &s.chunk_scale[c], sizeof(double));
+        }
     }
+    d.chunk_meta = (const int32_t*)up.put(meta);
     d.chunk_src = (const int32_t*)up.put(s.chunk_src);
     d.chunk_col = (const int32_t*)up.put(s.chunk_col);
     return d;
@@ -281,14 +286,17 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
     in.m2l_tile_targets = pl->h_m2l.max_tile;
     in.sigma0 = pl->ops.sigma0;
     in.plan_seconds = seconds;
+    in.m2l_variant = pl->h_m2l.variant;
+    in.m2l_tiles = pl->h_m2l.n_tiles();
 }
 
-// Largest tile (targets) whose LDS accumulator fits one workgroup.
+// Largest tile (targets) whose LDS accumulator (plus the R spare columns of
+// empty slots) fits one workgroup of the shape.
 int max_tile_for(const kifmm_plan_s* pl, int variant, int kdim) {
-    const size_t fixed = gg_lds_bytes(pl->elt, variant, kdim / 16, 0);
-    const size_t per_col = (gg_lds_bytes(pl->elt, variant, kdim / 16, 1) - fixed) * pl->R;
-    if (gg_lds_limit() <= fixed) return 1;
-    return std::max(1, (int)((gg_lds_limit() - fixed) / per_col));
+    const size_t fixed = gg_lds_bytes(pl->elt, variant, kdim / 16, pl->R);
+    const size_t per_col = (gg_lds_bytes(pl->elt, variant, kdim / 16, 1) - gg_lds_bytes(pl->elt, variant, kdim / 16, 0)) * pl->R;
+    if (gg_lds_limit(variant) <= fixed + per_col) return 1;
+    return std::max(1, (int)((gg_lds_limit(variant) - fixed) / per_col));
 }
 
 int row_groups(int rows_pad, int variant) {
@@ -326,14 +334,14 @@ int m2l_tiles_for(const kifmm_plan_s* pl, int variant, int extra_rounds) {
     const HostTree& t = pl->tree;
     const int64_t nb = t.n_box() - t.level_begin[2];
     const int n_rg = row_groups(pl->kp, variant);
-    const int slots = std::max(1, pl->num_cu / n_rg);
+    const int slots = std::max(1, pl->num_cu * gg_variant_wgs_per_cu(variant) / n_rg);
     const int cap = max_tile_for(pl, variant, pl->kp);
     int rounds = 1;
     while ((int64_t)rounds * slots * cap < nb * 11 / 10) ++rounds;
     return (rounds + extra_rounds) * slots;
 }
 
-int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
+int build_schedules(kifmm_plan_s* pl, int m2l_tile, int m2l_shape) {
     const HostTree& t = pl->tree;
     const int L = t.depth;
     pl->h_leafup = GGSched();
@@ -407,9 +415,9 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
     }
     // M2L: default shape (the device autotuner may replace it)
     if (m2l_tile > 0)
-        pl->h_m2l = build_m2l_sched(pl, 0, 0, m2l_tile);
+        pl->h_m2l = build_m2l_sched(pl, m2l_shape, 0, m2l_tile);
     else
-        pl->h_m2l = build_m2l_sched(pl, 0, m2l_tiles_for(pl, 0, 0), 0);
+        pl->h_m2l = build_m2l_sched(pl, m2l_shape, m2l_tiles_for(pl, m2l_shape, 0), 0);
     return KIFMM_OK;
 }
 
@@ -419,10 +427,10 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile) {
 // for the life of the process.
 struct TuneKey {
     int64_t n, n_box, v_pairs;
-    int kp, elt, R, num_cu;
+    int kp, elt, R, num_cu, shape;
     bool operator<(const TuneKey& o) const {
-        return std::tie(n, n_box, v_pairs, kp, elt, R, num_cu) <
-               std::tie(o.n, o.n_box, o.v_pairs, o.kp, o.elt, o.R, o.num_cu);
+        return std::tie(n, n_box, v_pairs, kp, elt, R, num_cu, shape) <
+               std::tie(o.n, o.n_box, o.v_pairs, o.kp, o.elt, o.R, o.num_cu, o.shape);
     }
 };
 std::map<TuneKey, std::pair<int, int>>& tune_cache() {
@@ -432,15 +440,16 @@ std::map<TuneKey, std::pair<int, int>>& tune_cache() {
 
 void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
     const HostTree& t = pl->tree;
-    const int64_t nb = t.n_box() - t.level_begin[2];
-    const TuneKey key{t.n, t.n_box(), (int64_t)t.v_src.size(), pl->kp, pl->elt, pl->R, pl->num_cu};
+    const int shape = pl->opts.m2l_shape;
+    const TuneKey key{t.n, t.n_box(), (int64_t)t.v_src.size(), pl->kp, pl->elt, pl->R, pl->num_cu, shape};
     std::vector<std::pair<int, int>> cands;   // (kernel shape, extra rounds)
     auto it = tune_cache().find(key);
     if (it != tune_cache().end()) {
         cands.push_back(it->second);
     } else {
         for (int v = 0; v < kGGVariants; ++v)
-            for (int r = 0; r < 3; ++r) cands.push_back({v, r});
+            if (shape < 0 || v == shape)
+                for (int r = 0; r < 3; ++r) cands.push_back({v, r});
     }
     if (cands.size() == 1) {
         pl->h_m2l = build_m2l_sched(pl, cands[0].first, m2l_tiles_for(pl, cands[0].first, cands[0].second), 0);
@@ -631,6 +640,7 @@ int kifmm_opts_default(kifmm_opts_t* o) {
     o->device = 0;
     o->mem_limit = 0;
     o->tile_targets = 0;
+    o->m2l_shape = -1;
     return KIFMM_OK;
 }
 
@@ -653,6 +663,8 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     if (o.max_nrhs < 1 || o.max_nrhs > 16) return fail(KIFMM_EINVAL, "max_nrhs must be in [1, 16]");
     if (o.tile_targets < 0 || o.tile_targets > 4096) return fail(KIFMM_EINVAL, "tile_targets must be in [0, 4096]");
     if (o.device < -1) return fail(KIFMM_EINVAL, "device must be >= -1");
+    if (o.m2l_shape < -1 || o.m2l_shape >= kGGVariants)
+        return fail(KIFMM_EINVAL, "m2l_shape must be -1 or in [0, " + std::to_string(kGGVariants - 1) + "]");
     const auto t0 = std::chrono::steady_clock::now();
     kifmm_plan_s* pl = new (std::nothrow) kifmm_plan_s();
     if (!pl) return fail(KIFMM_ENOMEM, "host allocation failed");
@@ -692,7 +704,7 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, o.device) == hipSuccess && ncu > 0)
             pl->num_cu = ncu;
     }
-    build_schedules(pl, o.tile_targets);
+    build_schedules(pl, o.tile_targets, std::max(o.m2l_shape, 0));
     if (o.device >= 0) {
         int cur = 0;
         hipGetDevice(&cur);

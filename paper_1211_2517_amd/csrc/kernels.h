@@ -13,13 +13,14 @@ struct DevSched {
     int cp = 16;
     int max_tile = 0;
     int variant = 0;                    // kernel shape, see gg_variant_rows
+    int max_src = 0;                    // largest source row index in the chunks
+    int max_cls = 0;                    // largest class in the chunks
     const int32_t* tile_tgt0 = nullptr;
     const int32_t* tile_ntgt = nullptr;
     const int32_t* tile_chunk0 = nullptr;
-    const int32_t* chunk_cls = nullptr;
-    const int32_t* chunk_next = nullptr;
-    const int32_t* chunk_nblk = nullptr;
-    const void* chunk_scale = nullptr;  // float or double per precision
+    // per chunk 4 words: class, 16-column blocks holding data, scale (float
+    // bits in word 2, or the low and high words of a double in words 2 and 3)
+    const int32_t* chunk_meta = nullptr;
     const int32_t* chunk_src = nullptr;
     const int32_t* chunk_col = nullptr;
 };
@@ -32,15 +33,21 @@ struct DevSched {
 hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, const void* X,
                      int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st);
 
-// Kernel shapes: 0 = 8 waves (128 output rows per workgroup), 1 = 4 waves
-// (64 rows); one 16-row block per wave. Chunks hold 32 / R pairs.
-constexpr int kGGVariants = 2;
+// Kernel shapes (one 16-row block per wave; chunks hold 32 / R pairs):
+//   0 = 8 waves (128 output rows per workgroup), all of a CU's LDS;
+//   1 = 4 waves (64 rows), all of a CU's LDS;
+//   2 = 4 waves (64 rows), half of a CU's LDS, so two workgroups share a CU.
+constexpr int kGGVariants = 3;
 // Output rows per workgroup of a shape (0 for an unknown shape).
 int gg_variant_rows(int variant);
-// Largest dynamic LDS the grouped GEMM may use per workgroup (bytes).
-size_t gg_lds_limit();
-// Per-workgroup LDS bytes of a tile of `cols` accumulator columns with K
-// dimension KP16*16.
+// Workgroups of a shape that run on one CU at a time.
+int gg_variant_wgs_per_cu(int variant);
+// Largest dynamic LDS a workgroup of the shape may use (bytes).
+size_t gg_lds_limit(int variant);
+// LDS staging buffers (2, or 1 when two would take over half the budget).
+int gg_nbuf(int elt, int variant, int KP16);
+// Per-workgroup LDS bytes with `cols` accumulator columns (spare columns
+// included) and K dimension KP16*16.
 size_t gg_lds_bytes(int elt, int variant, int KP16, int cols);
 
 // sig_s[i*R + r] = r < nrhs ? sigma[perm[i] + r*ld] : 0

@@ -64,24 +64,62 @@ struct GGParams {
     int accumulate;
     int n_tiles;
     int n_rg;
+    int nbuf;        // LDS staging buffers (2: double buffer; 1: wide K in FP64)
+    int trash_col;   // first of R accumulator columns that take the products of empty slots
+    // extents (bytes) of the buffer resources: loads past them return zero
+    uint32_t x_bytes, a_bytes, meta_bytes, list_bytes;
     const int32_t* tile_tgt0;
     const int32_t* tile_ntgt;
     const int32_t* tile_chunk0;
-    const int32_t* chunk_cls;
-    const int32_t* chunk_next;
-    const int32_t* chunk_nblk;
-    const void* chunk_scale;
+    const int32_t* chunk_meta;   // per chunk: class, 16-column blocks, scale (bits, 1 or 2 words)
     const int32_t* chunk_src;
     const int32_t* chunk_col;
 };
 
 // Loads through the constant address space: with a wave-uniform index the
-// compiler emits scalar loads, which are counted apart from the vector loads
-// (lgkmcnt, not vmcnt) and so never force the vector-load queue to drain.
+// compiler emits scalar loads. Used only outside the chunk loop.
 template <typename T>
 __device__ __forceinline__ T uload(const void* base, int idx) {
     typedef const T __attribute__((address_space(4))) CT;
     return reinterpret_cast<CT*>(reinterpret_cast<uintptr_t>(base))[idx];
+}
+
+// Word 3 of a raw buffer resource (32-bit data format; offsets are checked
+// against the record count, out-of-range loads return zero).
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+
+// 4-vector load through a buffer resource at byte offset voff + soff.
+template <typename T>
+__device__ __forceinline__ typename Mfma<T>::V4 bload4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ f32x4 bload4<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ f64x4 bload4<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    typedef int i32x8 __attribute__((ext_vector_type(8)));
+    const i32x4 lo = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    const i32x4 hi = __builtin_bit_cast(i32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0));
+    const i32x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(f64x4, v);
+}
+
+__device__ __forceinline__ int bload1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T meta_scale(int lo, int hi);
+template <>
+__device__ __forceinline__ float meta_scale<float>(int lo, int) { return __int_as_float(lo); }
+template <>
+__device__ __forceinline__ double meta_scale<double>(int lo, int hi) {
+    return __hiloint2double(hi, lo);
 }
 
 // Grouped gather GEMM: Y[t] (+)= scale * sum_chunks A[cls] X[src].
@@ -90,20 +128,26 @@ __device__ __forceinline__ T uload(const void* base, int idx) {
 // 16-row blocks of the output, one per wave. Its accumulator (rows x ntgt*R
 // columns) lives in LDS. The chunks of a tile are sorted by class; a chunk
 // holds up to 32 columns (two 16-column MFMA blocks, the second one only when
-// used) of one class. Per chunk the workgroup
-//   - stages the gathered source columns of X in an LDS buffer, loaded by all
-//     threads one chunk ahead (double buffer, one barrier per chunk);
-//   - each wave multiplies its 16 rows of A[cls], held in registers for the
-//     whole run of chunks of one class (the next class's rows are prefetched
-//     one chunk ahead of a class change), by the staged columns on 16x16x4
-//     MFMA and adds the result into its own LDS rows.
-// Chunk metadata that is uniform across a wave (class, next class, block
-// count, scale and the source index of each staged column) is read with
-// scalar loads; only the gathered data and the per-lane target column are
-// vector loads, issued so that every wait retires only what it needs.
-// Within a chunk the target columns are distinct and each wave owns its
-// rows, so no two lanes or waves update the same LDS word at the same time
-// and the summation order is fixed (results are bitwise reproducible).
+// used) of one class. The chunk loop is a software pipeline; while the MFMAs of
+// chunk c run, the workgroup has in flight
+//   - the gathered source columns of chunks c+1 and c+2 (all threads, into two
+//     register sets; chunk c+1's are stored to the other LDS staging buffer
+//     after the MFMAs, so a gather has two chunks' time to arrive),
+//   - the A rows of chunk c+1 for each wave (second register set; a copy of
+//     the current set when the class does not change),
+//   - the target columns of chunk c+1, the metadata of chunk c+2 and the
+//     source rows of chunk c+3.
+// Every load of the loop is a buffer load with a lane offset fixed for the
+// kernel and a scalar offset per chunk (little address arithmetic), issued
+// in the same order each iteration, so the waits retire exactly the loads
+// that are needed next; the loop has no scalar loads, whose out-of-order
+// returns would share the LDS counter and stall the MFMAs' operand reads.
+// One barrier per chunk.
+// Empty slots of a chunk gather row 0 (a valid row) and add their products
+// into R spare accumulator columns that are never stored. Within a chunk the
+// real target columns are distinct and each wave owns its rows, so no two
+// lanes or waves update the same live LDS word at the same time and the
+// summation order is fixed (results are bitwise reproducible).
 //
 // MFMA operand layout (v_mfma_*_16x16x4): lane l supplies A[l%16][kk] and
 // B[kk][l%16] of one K-step and holds D[Mfma<T>::row(q, l/16)][l%16]. The K
@@ -115,27 +159,30 @@ __device__ __forceinline__ T uload(const void* base, int idx) {
 // the row groups of a tile run on the same XCD (blocks are dealt to the 8 XCDs
 // round-robin) and share its L2 for the gathered columns.
 template <typename T, int KP16, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) gg_kernel(GGParams p) {
+__global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
     using M = Mfma<T>;
     using V4 = typename M::V4;
     constexpr int NT = 64 * WAVES;
     constexpr int KDIM = KP16 * 16;
     constexpr int LDB = KDIM + 4;          // LDS stride of one staged column
-    constexpr int V4C = KDIM / 4;          // 4-vectors per column
-    constexpr int CPL = V4C >= 64 ? 1 : 64 / V4C;   // columns covered by one wave-wide load
-    constexpr int LPC = (V4C + 63) / 64;             // wave-wide loads per column (wide K)
-    constexpr int GRP = CPL * WAVES;                 // columns covered per load round by the workgroup
-    constexpr int NLD = ((32 + GRP - 1) / GRP) * LPC;   // loads per lane per chunk
+    constexpr int V4C = KDIM / 4;          // 4-vectors per staged column
+    constexpr int NSV = 32 * V4C;          // 4-vectors staged per chunk
+    constexpr int NLD = (NSV + NT - 1) / NT;
+    // second A register set and both blocks' B operands read ahead, where the
+    // registers allow it (two waves per SIMD: 256 per lane)
+    constexpr bool ADBL = KP16 * sizeof(T) <= 64;
+    constexpr bool PRE2 = KP16 * sizeof(T) <= 32;
     const int b = blockIdx.x;
     const int rg = (b >> 3) % p.n_rg;
     const int tile = (b / (8 * p.n_rg)) * 8 + (b & 7);
     if (tile >= p.n_tiles) return;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* bbuf = reinterpret_cast<T*>(smem_raw);   // [2][32][LDB]
-    T* acc = bbuf + 2 * 32 * LDB;               // [ncol][ldl]
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    T* bbuf = reinterpret_cast<T*>(smem_raw);   // [nbuf][32][LDB]
+    T* acc = bbuf + p.nbuf * 32 * LDB;          // [ncol + R][ldl]
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int mb_lo = rg * WAVES;
     const int nmb = min(WAVES, p.MB - mb_lo);
     const int rows = nmb * 16;
@@ -144,154 +191,253 @@ __global__ void __launch_bounds__(64 * WAVES) gg_kernel(GGParams p) {
     const int cp = p.cp;
     const int t0 = uload<int32_t>(p.tile_tgt0, tile);
     const int ncol = uload<int32_t>(p.tile_ntgt, tile) * R;
-    const T* __restrict__ X = static_cast<const T*>(p.X);
-    const T* __restrict__ A = static_cast<const T*>(p.A);
+    const int cb = uload<int32_t>(p.tile_chunk0, tile);
+    const int ce = uload<int32_t>(p.tile_chunk0, tile + 1);
     T* __restrict__ Y = static_cast<T*>(p.Y);
 
     const int64_t ybase = (int64_t)t0 * R;
     const int row0 = mb_lo * 16;
-    for (int idx = threadIdx.x; idx < ncol * rows; idx += NT) {
+    for (int idx = tid; idx < ncol * rows; idx += NT) {
         const int col = idx / rows;
         const int row = idx - col * rows;
         acc[col * ldl + row] = p.accumulate ? Y[(ybase + col) * p.ldy + row0 + row] : T(0);
     }
+    if (cb >= ce) {
+        __syncthreads();
+        for (int idx = tid; idx < ncol * rows; idx += NT) {
+            const int col = idx / rows;
+            Y[(ybase + col) * p.ldy + row0 + idx - col * rows] = acc[col * ldl + idx - col * rows];
+        }
+        return;
+    }
 
-    const int cb = uload<int32_t>(p.tile_chunk0, tile);
-    const int ce = uload<int32_t>(p.tile_chunk0, tile + 1);
     const int j = lane & 15;
     const int grp = lane >> 4;
     const bool wact = wave < nmb;
-    const T* arow = A + (int64_t)(row0 + (wact ? wave : 0) * 16 + j) * p.lda + 4 * grp;
+    // buffer resources: every load of the chunk loop takes a 32-bit lane
+    // offset that is fixed for the kernel plus a scalar offset per chunk
+    const __amdgpu_buffer_rsrc_t rx = make_rsrc(p.X, p.x_bytes);
+    const __amdgpu_buffer_rsrc_t ra = make_rsrc(p.A, p.a_bytes);
+    const __amdgpu_buffer_rsrc_t rm = make_rsrc(p.chunk_meta, p.meta_bytes);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(p.chunk_src, p.list_bytes);
+    const __amdgpu_buffer_rsrc_t rc = make_rsrc(p.chunk_col, p.list_bytes);
+    const uint32_t aoff = (uint32_t)(((row0 + (wact ? wave : 0) * 16 + j) * p.lda + 4 * grp) * (int)sizeof(T));
+    const uint32_t a_cls_bytes = (uint32_t)(p.a_stride * (int64_t)sizeof(T));
+    const uint32_t xrow_bytes = (uint32_t)(R * p.ldx * (int)sizeof(T));
 
-    // staging map: load i of this lane covers staged column sc[i] (0..31),
-    // 4-vector part sp[i] of it. In load i the wave covers the CPL columns
-    // scb[i] .. scb[i]+CPL-1 (lane / V4C picks one). Lanes beyond them repeat
-    // a valid (column, part), so every lane issues the same loads and stores
-    // (duplicates write identical values); no load is predicated.
-    int sc[NLD], sp[NLD], scb[NLD];
+    // staging map: 4-vector f = i*NT + tid of the chunk is part f % V4C of
+    // staged column f / V4C (pair f / V4C / R, right-hand side f / V4C % R).
+    // Threads past the end repeat the last 4-vector (identical stores).
+    int spair[NLD], soff[NLD];
+    uint32_t xoff[NLD];
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
-        const int unit = i / LPC;                       // which column round
-        const int sub = i - unit * LPC;                 // which 64-wide slice of a long column
-        scb[i] = (unit * WAVES + wave) * CPL;
-        const int q = CPL > 1 ? min(lane / V4C, CPL - 1) : 0;
-        sc[i] = min(scb[i] + q, 31);
-        sp[i] = min((CPL > 1 ? lane - q * V4C : lane) + sub * 64, V4C - 1);
+        const int f = min(i * NT + tid, NSV - 1);
+        const int c = f / V4C;
+        spair[i] = c / R;
+        const int rhs = c - spair[i] * R;
+        const int part = 4 * (f - c * V4C);
+        soff[i] = c * LDB + part;
+        xoff[i] = (uint32_t)((rhs * p.ldx + part) * (int)sizeof(T));
     }
-    V4 stg[NLD];
-    // Empty pair slots hold source -1 and load row 0 (a valid row): their
-    // products land only in output columns that are never stored. All source
-    // indices are fetched first (scalar loads), then all gathers are issued.
-    auto stage_load = [&](int ch) {
-        int src[NLD];
-#pragma unroll
-        for (int i = 0; i < NLD; ++i) {
-            int s = 0;
-#pragma unroll
-            for (int q = 0; q < CPL; ++q) {
-                const int c = min(scb[i] + q, 31);
-                const int sq = uload<int32_t>(p.chunk_src, ch * cp + c / R);
-                if (sc[i] == c) s = sq;
-            }
-            src[i] = max(s, 0);
-        }
-#pragma unroll
-        for (int i = 0; i < NLD; ++i) {
-            const int c = sc[i];
-            const int pj = c / R;
-            stg[i] = *reinterpret_cast<const V4*>(X + ((int64_t)src[i] * R + (c - pj * R)) * p.ldx + 4 * sp[i]);
-        }
-    };
-    auto stage_store = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < NLD; ++i) *reinterpret_cast<V4*>(bbuf + (buf * 32 + sc[i]) * LDB + 4 * sp[i]) = stg[i];
-    };
-    // A rows of the current class run and of the next one; the two register
-    // sets swap roles from run to run (the run loop below is unrolled by two),
-    // so a prefetch lands directly in the registers that will use it.
-    V4 a0[KP16];
-    V4 a1[KP16];
-    auto load_a = [&](V4 (&dst)[KP16], int cls) {
-        const T* ar = arow + (int64_t)cls * p.a_stride;
-#pragma unroll
-        for (int t = 0; t < KP16; ++t) dst[t] = *reinterpret_cast<const V4*>(ar + 16 * t);
-    };
-
     const int pj16 = j / R;
     const int rj = j - pj16 * R;
-    int col0 = -1, col1 = -1;   // target columns of the current chunk (both blocks)
-    if (cb < ce) {
-        load_a(a0, uload<int32_t>(p.chunk_cls, cb));
-        stage_load(cb);
-        stage_store(0);
-        col0 = p.chunk_col[cb * cp + pj16];
-        col1 = p.chunk_col[cb * cp + (16 / R) + pj16];
-    }
-    __syncthreads();
+    const int colb1 = 16 / R;   // pair index of the first column of block 1
 
-    // one chunk: stage chunk ch+1 (and its target columns) while the MFMAs of chunk ch run
-    auto step = [&](int ch, const V4 (&a)[KP16]) {
-        const int buf = (ch - cb) & 1;
-        // scalar metadata first: scalar and LDS loads share one counter, and
-        // scalar ones return out of order, so none may be pending at the MFMAs
-        const int nb = uload<int32_t>(p.chunk_nblk, ch);
-        const T scale = uload<T>(p.chunk_scale, ch);
-        const int chn = min(ch + 1, ce - 1);
-        const int ncol0 = p.chunk_col[chn * cp + pj16];
-        const int ncol1 = p.chunk_col[chn * cp + (16 / R) + pj16];
-        stage_load(chn);
-        if (wact) {
+    // pipeline state entering the iteration of chunk c: the class, block count
+    // and scale of chunks c and c+1, the target columns of chunk c, the source
+    // rows of chunk c+2 and the gathered columns of chunk c+1 (in flight)
+    int cls_c, nb_c, cls_n, nb_n;
+    T sc_c, sc_n;
+    int col0_c, col1_c;         // target columns of this lane in chunk c (blocks 0 and 1)
+    int src_q[NLD];             // source rows of chunk c+2
+    V4 g0[NLD], g1[NLD];        // gathered columns, alternating by chunk parity
+    V4 a0[KP16];
+    V4 a1[ADBL ? KP16 : 1];
+
+    // metadata of a chunk: lanes 0..3 load its four words (a vector load), then
+    // they are broadcast to scalars once the loads have drained
+    auto load_meta = [&](int ch) { return bload1(rm, 4 * (lane & 3), 16 * ch); };
+    auto unpack_meta = [&](int v, int& cls, int& nb, T& sc) {
+        cls = __builtin_amdgcn_readlane(v, 0);
+        nb = __builtin_amdgcn_readlane(v, 1);
+        sc = meta_scale<T>(__builtin_amdgcn_readlane(v, 2), __builtin_amdgcn_readlane(v, 3));
+    };
+    auto load_src = [&](int ch, int (&dst)[NLD]) {
 #pragma unroll
-            for (int blk = 0; blk < 2; ++blk) {
-                if (blk < nb) {
-                    const T* bcol = bbuf + (buf * 32 + blk * 16 + j) * LDB + 4 * grp;
-                    V4 bv[KP16];
+        for (int i = 0; i < NLD; ++i) dst[i] = bload1(rs, 4 * spair[i], 4 * ch * cp);
+    };
+    auto gather = [&](V4 (&dst)[NLD], const int (&src)[NLD]) {
 #pragma unroll
-                    for (int t = 0; t < KP16; ++t) bv[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
-                    // issue every LDS read of the block before the first MFMA
-                    __builtin_amdgcn_sched_barrier(0);
-                    V4 d0 = V4{0, 0, 0, 0};
-                    V4 d1 = V4{0, 0, 0, 0};
+        for (int i = 0; i < NLD; ++i) {
+            const uint32_t s = (uint32_t)max(src[i], 0);
+            dst[i] = bload4<T>(rx, (uint32_t)__umul24(s, xrow_bytes) + xoff[i], 0);
+        }
+    };
+    auto stage_store = [&](int buf, const V4 (&v)[NLD]) {
 #pragma unroll
-                    for (int t = 0; t < KP16; ++t) {
+        for (int i = 0; i < NLD; ++i) *reinterpret_cast<V4*>(bbuf + buf * 32 * LDB + soff[i]) = v[i];
+    };
+    auto load_a = [&](V4 (&dst)[KP16], int cls) {
+        const uint32_t so = (uint32_t)cls * a_cls_bytes;
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            if (t & 1)
-                                d1 = M::step(a[t][e], bv[t][e], d1);
-                            else
-                                d0 = M::step(a[t][e], bv[t][e], d0);
-                        }
-                    }
-                    const int col = blk ? col1 : col0;
-                    if (col >= 0) {
-                        T* dst = acc + (col * R + rj) * ldl + wave * 16;
+        for (int t = 0; t < KP16; ++t) dst[t] = bload4<T>(ra, aoff + 16 * t * (int)sizeof(T), so);
+    };
+    auto tcol = [&](int ch, int& c0, int& c1) {
+        c0 = bload1(rc, 4 * pj16, 4 * ch * cp);
+        c1 = bload1(rc, 4 * (colb1 + pj16), 4 * ch * cp);
+    };
+    // acc[col] += scale * v over this wave's 16 rows; empty slots go to the spare columns
+    auto acc_ptr = [&](int col) {
+        return acc + ((col >= 0 ? col : p.trash_col) * R + rj) * ldl + wave * 16;
+    };
+
+    // acc[col][rows of this wave] += scale * (u + v), read-modify-write of one
+    // lane's 4 accumulator elements
+    auto acc_add = [&](T* ptr, const V4& u, const V4& v, T scale) {
+        if constexpr (sizeof(T) == 4) {
+            V4* q4 = reinterpret_cast<V4*>(ptr + 4 * grp);   // rows 4*grp .. 4*grp+3
+            const V4 o = *q4;
+            V4 r;
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) dst[M::row(q, grp)] += scale * (d0[q] + d1[q]);
-                    }
+            for (int q = 0; q < 4; ++q) r[q] = __builtin_fmaf(scale, u[q] + v[q], o[q]);
+            *q4 = r;
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ptr[M::row(q, grp)] = __builtin_fma(scale, u[q] + v[q], ptr[M::row(q, grp)]);
+        }
+    };
+
+    // MFMAs of one chunk whose B operands sit in LDS buffer `buf`
+    auto mfma_chunk = [&](int buf, const V4 (&a)[KP16]) {
+        if (!wact) return;
+        const T* bcol = bbuf + (buf * 32 + j) * LDB + 4 * grp;
+        const T scale = sc_c;
+        if (PRE2 && nb_c > 1) {
+            V4 b0[KP16], b1[KP16];
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) b0[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) b1[t] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * t);
+            __builtin_amdgcn_sched_barrier(0);
+            V4 d[4] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}, V4{0, 0, 0, 0}, V4{0, 0, 0, 0}};
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    d[t & 1] = M::step(a[t][e], b0[t][e], d[t & 1]);
+                    d[2 + (t & 1)] = M::step(a[t][e], b1[t][e], d[2 + (t & 1)]);
                 }
             }
+            acc_add(acc_ptr(col0_c), d[0], d[1], scale);
+            acc_add(acc_ptr(col1_c), d[2], d[3], scale);
+        } else if (PRE2) {
+            V4 b0[KP16];
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) b0[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
+            __builtin_amdgcn_sched_barrier(0);
+            V4 d0 = V4{0, 0, 0, 0};
+            V4 d1 = V4{0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (t & 1)
+                        d1 = M::step(a[t][e], b0[t][e], d1);
+                    else
+                        d0 = M::step(a[t][e], b0[t][e], d0);
+                }
+            }
+            acc_add(acc_ptr(col0_c), d0, d1, scale);
+        } else {
+            for (int blk = 0; blk < nb_c; ++blk) {
+                V4 d0 = V4{0, 0, 0, 0};
+                V4 d1 = V4{0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < KP16; ++t) {
+                    const V4 bv = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (t & 1)
+                            d1 = M::step(a[t][e], bv[e], d1);
+                        else
+                            d0 = M::step(a[t][e], bv[e], d0);
+                    }
+                }
+                acc_add(acc_ptr(blk ? col1_c : col0_c), d0, d1, scale);
+            }
         }
-        stage_store(buf ^ 1);
-        col0 = ncol0;
-        col1 = ncol1;
+    };
+
+    // The loop starts two chunks early, at c = cb-2: those two iterations
+    // only fill the pipeline (chunk indices are clamped into the tile, their
+    // MFMAs are skipped), so every load of the loop is issued by the same code
+    // in the same order, and the wait counts are the same on every iteration.
+    // A clamped chunk index past the last chunk only repeats valid loads.
+    // cls_c = -1 forces the first A load.
+    auto clampc = [&](int ch) { return min(max(ch, cb), ce - 1); };
+    unpack_meta(load_meta(cb), cls_n, nb_n, sc_n);
+    cls_c = -1;
+    nb_c = 0;
+    sc_c = T(0);
+    col0_c = col1_c = -1;
+    load_src(cb, src_q);
+    // drain the prologue's loads (s_waitcnt vmcnt(0)), so that the wait
+    // counts computed for the loop follow its steady state only
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+
+    // one iteration: chunk ch with its A rows in `a`; `an` receives chunk
+    // ch+1's rows, `gi` holds chunk ch+1's gathered columns (in flight) and
+    // `go` receives chunk ch+2's
+    auto step = [&](int ch, int buf, V4 (&a)[KP16], V4 (&an)[KP16], V4 (&gi)[NLD], V4 (&go)[NLD]) {
+        // A rows first, so that the wait at the end of the iteration leaves
+        // only this iteration's metadata and gathers in flight
+        if (ADBL) {
+            if (cls_n != cls_c) {
+                load_a(an, cls_n);
+            } else {
+#pragma unroll
+                for (int t = 0; t < KP16; ++t) an[t] = a[t];
+            }
+        }
+        int src3[NLD];
+        load_src(clampc(ch + 3), src3);
+        const int m2 = load_meta(clampc(ch + 2));
+        int n0, n1;
+        tcol(clampc(ch + 1), n0, n1);
+        gather(go, src_q);
+        // with one staging buffer every chunk uses buffer 0, and the store of
+        // the next chunk waits until all waves have read the current one
+        const bool one = p.nbuf == 1;
+        if (ch >= cb && ch < ce) mfma_chunk(one ? 0 : buf, a);
+        if (one) __syncthreads();
+        stage_store(one ? 0 : buf ^ 1, gi);
+        if (!ADBL && cls_n != cls_c) load_a(a, cls_n);
+        cls_c = cls_n;
+        nb_c = nb_n;
+        sc_c = sc_n;
+        unpack_meta(m2, cls_n, nb_n, sc_n);
+        col0_c = n0;
+        col1_c = n1;
+#pragma unroll
+        for (int i = 0; i < NLD; ++i) src_q[i] = src3[i];
         __syncthreads();
     };
-    // one class run: prefetch the next run's A rows, then its chunks
-    auto run = [&](int ch, const V4 (&a)[KP16], V4 (&nxt)[KP16]) {
-        const int cls = uload<int32_t>(p.chunk_cls, ch);
-        const int nx = uload<int32_t>(p.chunk_next, ch);
-        load_a(nxt, nx >= 0 ? nx : cls);   // unconditional, so every path issues the same loads
-        do {
-            step(ch, a);
-            ++ch;
-        } while (ch < ce && uload<int32_t>(p.chunk_cls, ch) == cls);
-        return ch;
-    };
-    for (int ch = cb; ch < ce;) {
-        ch = run(ch, a0, a1);
-        if (ch < ce) ch = run(ch, a1, a0);
+    // both iterations of the unrolled pair always run (one past the last
+    // chunk when the count is odd; its MFMAs are skipped), so the loop has a
+    // single back edge and the wait counts stay exact
+    if constexpr (ADBL) {
+        for (int ch = cb - 2; ch < ce; ch += 2) {
+            step(ch, 0, a0, a1, g1, g0);
+            step(ch + 1, 1, a1, a0, g0, g1);
+        }
+    } else {
+        for (int ch = cb - 2; ch < ce; ch += 2) {
+            step(ch, 0, a0, a0, g1, g0);
+            step(ch + 1, 1, a0, a0, g0, g1);
+        }
     }
-    for (int idx = threadIdx.x; idx < ncol * rows; idx += NT) {
+    for (int idx = tid; idx < ncol * rows; idx += NT) {
         const int col = idx / rows;
         const int row = idx - col * rows;
         Y[(ybase + col) * p.ldy + row0 + row] = acc[col * ldl + row];
@@ -450,7 +596,8 @@ template <typename T>
 hipError_t gg_variant(int variant, int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st) {
     switch (variant) {
         case 0: return gg_dispatch<T, 8>(KP16, p, blocks, lds, st);
-        case 1: return gg_dispatch<T, 4>(KP16, p, blocks, lds, st);
+        case 1:
+        case 2: return gg_dispatch<T, 4>(KP16, p, blocks, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -460,15 +607,24 @@ hipError_t gg_variant(int variant, int KP16, const GGParams& p, int blocks, size
 int gg_variant_rows(int variant) {
     switch (variant) {
         case 0: return 8 * 16;
-        case 1: return 4 * 16;
+        case 1:
+        case 2: return 4 * 16;
         default: return 0;
     }
 }
 
-size_t gg_lds_limit() { return 160 * 1024; }
+int gg_variant_wgs_per_cu(int variant) { return variant == 2 ? 2 : 1; }
+
+size_t gg_lds_limit(int variant) { return (160 * 1024) / gg_variant_wgs_per_cu(variant); }
+
+int gg_nbuf(int elt, int variant, int KP16) {
+    const size_t stage = (size_t)32 * (KP16 * 16 + 4) * elt;
+    return 2 * stage <= gg_lds_limit(variant) / 2 ? 2 : 1;
+}
 
 size_t gg_lds_bytes(int elt, int variant, int KP16, int cols) {
-    return ((size_t)2 * 32 * (KP16 * 16 + 4) + (size_t)cols * (gg_variant_rows(variant) + 4)) * elt;
+    return ((size_t)gg_nbuf(elt, variant, KP16) * 32 * (KP16 * 16 + 4) +
+            (size_t)cols * (gg_variant_rows(variant) + 4)) * elt;
 }
 
 hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, const void* X,
@@ -488,19 +644,31 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
     p.accumulate = accumulate;
     p.n_tiles = s.n_tiles;
     const int mbg = gg_variant_rows(s.variant) / 16;
-    if (mbg == 0 || s.cp * R != 32) return hipErrorInvalidValue;
+    if (mbg == 0 || s.cp * R != 32 || s.max_tile < 1) return hipErrorInvalidValue;
     p.n_rg = (MB + mbg - 1) / mbg;
+    p.nbuf = gg_nbuf(elt, s.variant, KP16);
+    p.trash_col = s.max_tile;
     p.tile_tgt0 = s.tile_tgt0;
     p.tile_ntgt = s.tile_ntgt;
     p.tile_chunk0 = s.tile_chunk0;
-    p.chunk_cls = s.chunk_cls;
-    p.chunk_next = s.chunk_next;
-    p.chunk_nblk = s.chunk_nblk;
-    p.chunk_scale = s.chunk_scale;
+    p.chunk_meta = s.chunk_meta;
     p.chunk_src = s.chunk_src;
     p.chunk_col = s.chunk_col;
-    const size_t lds = gg_lds_bytes(elt, s.variant, KP16, s.max_tile * R);
-    if (lds > gg_lds_limit() || KP16 < 1 || KP16 > 19) return hipErrorInvalidValue;
+    // buffer extents: rows of X up to the largest source row of the schedule,
+    // classes of A up to the largest class; each must fit 32-bit offsets
+    const int64_t xb = (int64_t)(s.max_src + 1) * R * ldx * elt;
+    const int64_t ab = (int64_t)(s.max_cls + 1) * p.a_stride * elt;
+    const int64_t lb = (int64_t)s.n_chunks * s.cp * 4;
+    const int64_t lim = (int64_t)1 << 31;
+    if (xb >= lim || ab >= lim || lb >= lim || (int64_t)R * ldx * elt >= (1 << 24) || s.max_src >= (1 << 24))
+        return hipErrorInvalidValue;
+    p.x_bytes = (uint32_t)xb;
+    p.a_bytes = (uint32_t)ab;
+    p.meta_bytes = (uint32_t)((int64_t)s.n_chunks * 16);
+    p.list_bytes = (uint32_t)lb;
+    // accumulator columns: the largest tile plus the spare columns of empty slots
+    const size_t lds = gg_lds_bytes(elt, s.variant, KP16, (s.max_tile + 1) * R);
+    if (lds > gg_lds_limit(s.variant) || KP16 < 1 || KP16 > 19) return hipErrorInvalidValue;
     const int blocks = (s.n_tiles + 7) / 8 * 8 * p.n_rg;
     if (elt == 4) return gg_variant<float>(s.variant, KP16, p, blocks, lds, st);
     return gg_variant<double>(s.variant, KP16, p, blocks, lds, st);
