@@ -73,8 +73,9 @@ typedef struct {
                            this many bytes; 0 = no limit */
     int tile_targets;   /* target boxes per M2L work tile; 0 = autotune on the device */
     int m2l_shape;      /* M2L kernel shape (see kifmm_info_t.m2l_variant); -1 = autotuned
-                           (default), 0..2 forces one shape (the tile count is still tuned
-                           unless tile_targets > 0) */
+                           (default), 0..3 forces one shape (the tile count is still tuned
+                           unless tile_targets > 0); KIFMM_EINVAL if the shape does not
+                           exist in the requested precision */
 } kifmm_opts_t;
 
 /* Per-stage counters; index with the KIFMM_STAGE_* values. */
@@ -106,7 +107,8 @@ typedef struct {
     double sigma0;          /* largest singular value of K_fat (svd mode), else 0 */
     double plan_seconds;    /* wall time of the plan call */
     int m2l_variant;        /* M2L kernel shape in use: 0 = 8 waves x 16 rows per workgroup,
-                               1 = 4 waves x 16 rows, 2 = 4 waves x 16 rows at two workgroups per CU */
+                               1 = 4 waves x 16 rows, 2 = 4 waves x 16 rows at two workgroups per CU,
+                               3 = 4 waves x 32 rows (FP32 only) */
     int m2l_tiles;          /* M2L target tiles (workgroups = tiles x row groups) */
 } kifmm_info_t;
 

@@ -448,7 +448,7 @@ void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
         cands.push_back(it->second);
     } else {
         for (int v = 0; v < kGGVariants; ++v)
-            if (shape < 0 || v == shape)
+            if ((shape < 0 || v == shape) && gg_variant_supported(v, pl->elt))
                 for (int r = 0; r < 3; ++r) cands.push_back({v, r});
     }
     if (cands.size() == 1) {
@@ -473,10 +473,10 @@ void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
         DevSched ds = upload_sched(tmp, hs, pl->elt);
         float ms = 1e30f;
         if (tmp.err == KIFMM_OK) {
-            bool ok = launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st) == hipSuccess;
+            bool ok = launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->k, pl->k, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st) == hipSuccess;
             for (int rep = 0; ok && rep < 3; ++rep) {
                 ok = hipEventRecord(e0, st) == hipSuccess &&
-                     launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st) == hipSuccess &&
+                     launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->k, pl->k, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st) == hipSuccess &&
                      hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
                 float one = 0.f;
                 if (ok && hipEventElapsedTime(&one, e0, e1) == hipSuccess) ms = std::min(ms, one);
@@ -547,7 +547,7 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
         // upward (forward) / L2T^T (adjoint): surface evaluation and the leaf GEMM
         KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->surf, pl->ops.n_eq, nep,
                                       pl->C, st));
-        KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->C, nep,
+        KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->k, pl->ops.n_eq, pl->C, nep,
                             adjoint ? pl->P : pl->Q, kp, R, 0, st));
     }
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 1));
@@ -555,38 +555,38 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
     if (far) {
         if (!adjoint) {
             for (int l = L - 1; l >= 2; --l)   // M2M
-                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->Mt, MBk, KPk, pl->Q, kp, pl->Q, kp, R, 0, st));
+                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->Mt, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->Q, kp, R, 0, st));
         } else {
             for (int l = L - 1; l >= 2; --l)   // L2L^T: parents at l from children at l+1
-                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->LtT, MBk, KPk, pl->P, kp, pl->P, kp, R, 0, st));
+                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->LtT, MBk, KPk, pl->k, pl->k, pl->P, kp, pl->P, kp, R, 0, st));
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 0));
     if (far) {
         if (!adjoint)
-            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->Q, kp, pl->P, kp, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->P, kp, R, 0, st));
         else
-            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->KtT, MBk, KPk, pl->P, kp, pl->Q, kp, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->KtT, MBk, KPk, pl->k, pl->k, pl->P, kp, pl->Q, kp, R, 0, st));
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 0));
     if (far) {
         if (!adjoint) {
             for (int l = 3; l <= L; ++l)       // L2L
-                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->Lt, MBk, KPk, pl->P, kp, pl->P, kp, R, 1, st));
+                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->Lt, MBk, KPk, pl->k, pl->k, pl->P, kp, pl->P, kp, R, 1, st));
         } else {
             for (int l = 3; l <= L; ++l)       // M2M^T: children at l from parents at l-1
-                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->MtT, MBk, KPk, pl->Q, kp, pl->Q, kp, R, 1, st));
+                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->MtT, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->Q, kp, R, 1, st));
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_L2P, 0));
     if (far) {
         if (!adjoint)
-            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, pl->P, kp, pl->E, nep, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, pl->ops.n_eq, pl->k, pl->P, kp, pl->E, nep, R, 0, st));
         else
-            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, pl->Q, kp, pl->E, nep, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, pl->ops.n_eq, pl->k, pl->Q, kp, pl->E, nep, R, 0, st));
     }
     KIFMM_HIP(mark(KIFMM_STAGE_L2P, 1));
     const double rL = t.half_width(L);
@@ -665,6 +665,8 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     if (o.device < -1) return fail(KIFMM_EINVAL, "device must be >= -1");
     if (o.m2l_shape < -1 || o.m2l_shape >= kGGVariants)
         return fail(KIFMM_EINVAL, "m2l_shape must be -1 or in [0, " + std::to_string(kGGVariants - 1) + "]");
+    if (o.m2l_shape >= 0 && !gg_variant_supported(o.m2l_shape, o.precision == KIFMM_FP64 ? 8 : 4))
+        return fail(KIFMM_EINVAL, "m2l_shape " + std::to_string(o.m2l_shape) + " is not available in this precision");
     const auto t0 = std::chrono::steady_clock::now();
     kifmm_plan_s* pl = new (std::nothrow) kifmm_plan_s();
     if (!pl) return fail(KIFMM_ENOMEM, "host allocation failed");

@@ -26,18 +26,23 @@ struct DevSched {
 };
 
 // Y[tgt] (+)= scale * sum_chunks A[cls] X[src] for every tile of `s`.
-//  A: per-class (MB*16) x (KP16*16) row-major blocks (zero padded);
-//  X rows of length ldx (>= KP16*16), Y rows of length ldy (>= MB*16);
-//  row of (box b, right-hand side r) is b*R + r.
+//  A: per-class (MB*16) x (KP16*16) row-major blocks, of which the leading
+//  a_rows x a_cols hold data and the rest is zero (the padding is not read);
+//  X rows of length ldx (>= KP16*16, zero past a_cols), Y rows of length
+//  ldy (>= MB*16); row of (box b, right-hand side r) is b*R + r.
 // elt = 4 (FP32 MFMA) or 8 (FP64 MFMA). Returns a hipError_t.
-hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, const void* X,
-                     int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st);
+hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, int a_rows, int a_cols,
+                     const void* X, int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st);
 
 // Kernel shapes (one 16-row block per wave; chunks hold 32 / R pairs):
 //   0 = 8 waves (128 output rows per workgroup), all of a CU's LDS;
 //   1 = 4 waves (64 rows), all of a CU's LDS;
-//   2 = 4 waves (64 rows), half of a CU's LDS, so two workgroups share a CU.
-constexpr int kGGVariants = 3;
+//   2 = 4 waves (64 rows), half of a CU's LDS, so two workgroups share a CU;
+//   3 = 4 waves with two 16-row blocks each (128 rows), all of a CU's LDS,
+//       one wave per SIMD (FP32 only).
+constexpr int kGGVariants = 4;
+// Whether shape `variant` exists for element size `elt` (4 or 8 bytes).
+bool gg_variant_supported(int variant, int elt);
 // Output rows per workgroup of a shape (0 for an unknown shape).
 int gg_variant_rows(int variant);
 // Workgroups of a shape that run on one CU at a time.

@@ -54,6 +54,7 @@ struct GGParams {
     const void* A;
     int64_t a_stride;
     int lda;
+    int a_rows, a_cols;   // rows and columns of A that hold data (the rest is zero)
     const void* X;
     int ldx;
     void* Y;
@@ -84,6 +85,10 @@ __device__ __forceinline__ T uload(const void* base, int idx) {
     return reinterpret_cast<CT*>(reinterpret_cast<uintptr_t>(base))[idx];
 }
 
+// A lane offset at or past every buffer extent: the load returns zero and
+// makes no memory request (used for zero padding and empty slots).
+constexpr uint32_t kOffNone = 0x80000000u;
+
 // Word 3 of a raw buffer resource (32-bit data format; offsets are checked
 // against the record count, out-of-range loads return zero).
 constexpr int kRsrcWord3 = 0x00020000;
@@ -113,6 +118,25 @@ __device__ __forceinline__ int bload1(__amdgpu_buffer_rsrc_t r, uint32_t voff, u
     return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
 }
 
+// Scheduling pattern for an MFMA sequence of N K-chunks: DS0 LDS reads first,
+// then per K-chunk MF MFMAs, DS LDS reads (operands of a later K-chunk; none
+// in the last LA chunks) and LD vector-memory reads, so that loads issued
+// inside the sequence stay spread over it instead of leaving in one burst.
+template <int N, int LA, int MF, int DS, int LD>
+__device__ __forceinline__ void sched_chain() {
+    if constexpr (N > 0) {
+        __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);
+        if constexpr (N > LA) __builtin_amdgcn_sched_group_barrier(0x100, DS, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, LD, 0);
+        sched_chain<N - 1, LA, MF, DS, LD>();
+    }
+}
+template <int N, int LA, int MF, int DS, int LD>
+__device__ __forceinline__ void sched_interleave() {
+    __builtin_amdgcn_sched_group_barrier(0x100, DS * LA, 0);
+    sched_chain<N, LA, MF, DS, LD>();
+}
+
 template <typename T>
 __device__ __forceinline__ T meta_scale(int lo, int hi);
 template <>
@@ -124,19 +148,20 @@ __device__ __forceinline__ double meta_scale<double>(int lo, int hi) {
 
 // Grouped gather GEMM: Y[t] (+)= scale * sum_chunks A[cls] X[src].
 //
-// A workgroup owns one (tile, row group): the targets of the tile and WAVES
-// 16-row blocks of the output, one per wave. Its accumulator (rows x ntgt*R
-// columns) lives in LDS. The chunks of a tile are sorted by class; a chunk
+// A workgroup owns one (tile, row group): the targets of the tile and
+// WAVES*MBW 16-row blocks of the output, MBW per wave. Its accumulator (rows x
+// ntgt*R columns) lives in LDS. The chunks of a tile are sorted by class; a chunk
 // holds up to 32 columns (two 16-column MFMA blocks, the second one only when
 // used) of one class. The chunk loop is a software pipeline; while the MFMAs of
 // chunk c run, the workgroup has in flight
 //   - the gathered source columns of chunks c+1 and c+2 (all threads, into two
 //     register sets; chunk c+1's are stored to the other LDS staging buffer
 //     after the MFMAs, so a gather has two chunks' time to arrive),
-//   - the A rows of chunk c+1 for each wave (second register set; a copy of
-//     the current set when the class does not change),
-//   - the target columns of chunk c+1, the metadata of chunk c+2 and the
-//     source rows of chunk c+3.
+//   - the A rows of chunk c+1 for each wave (second register set),
+//   - the target columns of chunk c+1, the metadata of chunk c+3 and the
+//     source rows of chunk c+4.
+// A value is first needed one iteration after the one that loads it (A rows,
+// target columns, source rows) or two (gathers, metadata).
 // Every load of the loop is a buffer load with a lane offset fixed for the
 // kernel and a scalar offset per chunk (little address arithmetic), issued
 // in the same order each iteration, so the waits retire exactly the loads
@@ -158,8 +183,8 @@ __device__ __forceinline__ double meta_scale<double>(int lo, int hi) {
 // Block b maps to tile (b / (8*n_rg))*8 + b%8 and row group (b/8) % n_rg, so
 // the row groups of a tile run on the same XCD (blocks are dealt to the 8 XCDs
 // round-robin) and share its L2 for the gathered columns.
-template <typename T, int KP16, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
+template <typename T, int KP16, int WAVES, int MBW>
+__global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGParams p) {
     using M = Mfma<T>;
     using V4 = typename M::V4;
     constexpr int NT = 64 * WAVES;
@@ -169,7 +194,8 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
     constexpr int NSV = 32 * V4C;          // 4-vectors staged per chunk
     constexpr int NLD = (NSV + NT - 1) / NT;
     // second A register set and both blocks' B operands read ahead, where the
-    // registers allow it (two waves per SIMD: 256 per lane)
+    // registers allow it (256 per lane at two waves per SIMD, MBW = 1; 512 at
+    // one wave per SIMD, MBW = 2)
     constexpr bool ADBL = KP16 * sizeof(T) <= 64;
     constexpr bool PRE2 = KP16 * sizeof(T) <= 32;
     const int b = blockIdx.x;
@@ -183,10 +209,10 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int mb_lo = rg * WAVES;
-    const int nmb = min(WAVES, p.MB - mb_lo);
+    const int mb_lo = rg * WAVES * MBW;
+    const int nmb = min(WAVES * MBW, p.MB - mb_lo);
     const int rows = nmb * 16;
-    const int ldl = WAVES * 16 + 4;
+    const int ldl = WAVES * MBW * 16 + 4;
     const int R = p.R;
     const int cp = p.cp;
     const int t0 = uload<int32_t>(p.tile_tgt0, tile);
@@ -213,7 +239,10 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
 
     const int j = lane & 15;
     const int grp = lane >> 4;
-    const bool wact = wave < nmb;
+    // a wave works when its first row block holds output rows; a second row
+    // block past the last one reads a valid row of A and accumulates into LDS
+    // rows that are never stored
+    const bool wact = wave * MBW < nmb;
     // buffer resources: every load of the chunk loop takes a 32-bit lane
     // offset that is fixed for the kernel plus a scalar offset per chunk
     const __amdgpu_buffer_rsrc_t rx = make_rsrc(p.X, p.x_bytes);
@@ -221,7 +250,17 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
     const __amdgpu_buffer_rsrc_t rm = make_rsrc(p.chunk_meta, p.meta_bytes);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(p.chunk_src, p.list_bytes);
     const __amdgpu_buffer_rsrc_t rc = make_rsrc(p.chunk_col, p.list_bytes);
-    const uint32_t aoff = (uint32_t)(((row0 + (wact ? wave : 0) * 16 + j) * p.lda + 4 * grp) * (int)sizeof(T));
+    // A loads skip the zero padding: rows past a_rows, and the 4-wide K pieces
+    // past a_cols (only the last K-chunk can hold those)
+    uint32_t aoff[MBW], aofl[MBW];
+#pragma unroll
+    for (int m = 0; m < MBW; ++m) {
+        const int blk = min(wave * MBW + m, nmb - 1);
+        const int row = row0 + blk * 16 + j;
+        aoff[m] = row < p.a_rows ? (uint32_t)((row * p.lda + 4 * grp) * (int)sizeof(T)) : kOffNone;
+        aofl[m] = (row < p.a_rows && 16 * (KP16 - 1) + 4 * grp < p.a_cols)
+                      ? aoff[m] + 16 * (KP16 - 1) * (int)sizeof(T) : kOffNone;
+    }
     const uint32_t a_cls_bytes = (uint32_t)(p.a_stride * (int64_t)sizeof(T));
     const uint32_t xrow_bytes = (uint32_t)(R * p.ldx * (int)sizeof(T));
 
@@ -230,6 +269,7 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
     // Threads past the end repeat the last 4-vector (identical stores).
     int spair[NLD], soff[NLD];
     uint32_t xoff[NLD];
+    bool xpad[NLD];     // 4-vector entirely in the zero padding past a_cols
 #pragma unroll
     for (int i = 0; i < NLD; ++i) {
         const int f = min(i * NT + tid, NSV - 1);
@@ -239,21 +279,24 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
         const int part = 4 * (f - c * V4C);
         soff[i] = c * LDB + part;
         xoff[i] = (uint32_t)((rhs * p.ldx + part) * (int)sizeof(T));
+        xpad[i] = part >= p.a_cols;
     }
     const int pj16 = j / R;
     const int rj = j - pj16 * R;
     const int colb1 = 16 / R;   // pair index of the first column of block 1
 
     // pipeline state entering the iteration of chunk c: the class, block count
-    // and scale of chunks c and c+1, the target columns of chunk c, the source
-    // rows of chunk c+2 and the gathered columns of chunk c+1 (in flight)
-    int cls_c, nb_c, cls_n, nb_n;
+    // and scale of chunks c and c+1, the metadata word of chunk c+2 (loaded),
+    // the target columns of chunk c, the source rows of chunks c+2 and c+3 and
+    // the gathered columns of chunk c+1 (in flight)
+    int cls_c, nb_c, cls_n, nb_n, m_q;
     T sc_c, sc_n;
     int col0_c, col1_c;         // target columns of this lane in chunk c (blocks 0 and 1)
     int src_q[NLD];             // source rows of chunk c+2
+    int src_q2[NLD];            // source rows of chunk c+3
     V4 g0[NLD], g1[NLD];        // gathered columns, alternating by chunk parity
-    V4 a0[KP16];
-    V4 a1[ADBL ? KP16 : 1];
+    V4 a0[MBW][KP16];
+    V4 a1[ADBL ? MBW : 1][KP16];
 
     // metadata of a chunk: lanes 0..3 load its four words (a vector load), then
     // they are broadcast to scalars once the loads have drained
@@ -270,26 +313,31 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
     auto gather = [&](V4 (&dst)[NLD], const int (&src)[NLD]) {
 #pragma unroll
         for (int i = 0; i < NLD; ++i) {
-            const uint32_t s = (uint32_t)max(src[i], 0);
-            dst[i] = bload4<T>(rx, (uint32_t)__umul24(s, xrow_bytes) + xoff[i], 0);
+            const uint32_t off = (src[i] < 0 || xpad[i]) ? kOffNone
+                                                         : (uint32_t)__umul24((uint32_t)src[i], xrow_bytes) + xoff[i];
+            dst[i] = bload4<T>(rx, off, 0);
         }
     };
     auto stage_store = [&](int buf, const V4 (&v)[NLD]) {
 #pragma unroll
         for (int i = 0; i < NLD; ++i) *reinterpret_cast<V4*>(bbuf + buf * 32 * LDB + soff[i]) = v[i];
     };
-    auto load_a = [&](V4 (&dst)[KP16], int cls) {
+    auto load_a = [&](V4 (&dst)[MBW][KP16], int cls) {
         const uint32_t so = (uint32_t)cls * a_cls_bytes;
 #pragma unroll
-        for (int t = 0; t < KP16; ++t) dst[t] = bload4<T>(ra, aoff + 16 * t * (int)sizeof(T), so);
+        for (int m = 0; m < MBW; ++m) {
+#pragma unroll
+            for (int t = 0; t < KP16 - 1; ++t) dst[m][t] = bload4<T>(ra, aoff[m] + 16 * t * (int)sizeof(T), so);
+            dst[m][KP16 - 1] = bload4<T>(ra, aofl[m], so);
+        }
     };
     auto tcol = [&](int ch, int& c0, int& c1) {
         c0 = bload1(rc, 4 * pj16, 4 * ch * cp);
         c1 = bload1(rc, 4 * (colb1 + pj16), 4 * ch * cp);
     };
-    // acc[col] += scale * v over this wave's 16 rows; empty slots go to the spare columns
+    // accumulator column `col` at this wave's rows; empty slots go to the spare columns
     auto acc_ptr = [&](int col) {
-        return acc + ((col >= 0 ? col : p.trash_col) * R + rj) * ldl + wave * 16;
+        return acc + ((col >= 0 ? col : p.trash_col) * R + rj) * ldl + wave * MBW * 16;
     };
 
     // acc[col][rows of this wave] += scale * (u + v), read-modify-write of one
@@ -308,63 +356,103 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
         }
     };
 
-    // MFMAs of one chunk whose B operands sit in LDS buffer `buf`
-    auto mfma_chunk = [&](int buf, const V4 (&a)[KP16]) {
-        if (!wact) return;
+    // MFMAs of one chunk whose B operands sit in LDS buffer `buf`; for each of
+    // the wave's MBW row blocks and each 16-column block two accumulation
+    // chains over K (even and odd K-chunks)
+    // MFMAs of one chunk whose B operands sit in LDS buffer `buf`: for each of
+    // the wave's MBW row blocks and each 16-column block, two accumulation
+    // chains over K (even and odd K-chunks).
+    //
+    // PRE2 shapes issue their memory traffic inside the MFMA sequence, in
+    // program order between fences (sched_barrier), so that the loads of all
+    // waves reach the memory pipelines spread over the MFMAs instead of in one
+    // burst after the barrier: the LDS operands LA K-chunks ahead of their use,
+    // and after K-chunk t the call hook(t) (the A rows of the next chunk and
+    // this iteration's other loads). Other shapes call hook(t) for every t
+    // before the MFMAs.
+    constexpr int LA = 2;
+    auto mfma_chunk = [&](int buf, const V4 (&a)[MBW][KP16], auto&& hook) {
         const T* bcol = bbuf + (buf * 32 + j) * LDB + 4 * grp;
         const T scale = sc_c;
+        T* p0 = acc_ptr(col0_c);
         if (PRE2 && nb_c > 1) {
             V4 b0[KP16], b1[KP16];
 #pragma unroll
-            for (int t = 0; t < KP16; ++t) b0[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
+            for (int t = 0; t < LA && t < KP16; ++t) {
+                b0[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
+                b1[t] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * t);
+            }
+            V4 d[MBW][4];
 #pragma unroll
-            for (int t = 0; t < KP16; ++t) b1[t] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * t);
-            __builtin_amdgcn_sched_barrier(0);
-            V4 d[4] = {V4{0, 0, 0, 0}, V4{0, 0, 0, 0}, V4{0, 0, 0, 0}, V4{0, 0, 0, 0}};
+            for (int m = 0; m < MBW; ++m)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) d[m][q] = V4{0, 0, 0, 0};
 #pragma unroll
             for (int t = 0; t < KP16; ++t) {
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    d[t & 1] = M::step(a[t][e], b0[t][e], d[t & 1]);
-                    d[2 + (t & 1)] = M::step(a[t][e], b1[t][e], d[2 + (t & 1)]);
+#pragma unroll
+                    for (int m = 0; m < MBW; ++m) {
+                        d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
+                        d[m][2 + (t & 1)] = M::step(a[m][t][e], b1[t][e], d[m][2 + (t & 1)]);
+                    }
                 }
+                __builtin_amdgcn_sched_barrier(0);
+                if (t + LA < KP16) {
+                    b0[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * (t + LA));
+                    b1[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * (t + LA));
+                }
+                hook(t);
             }
-            acc_add(acc_ptr(col0_c), d[0], d[1], scale);
-            acc_add(acc_ptr(col1_c), d[2], d[3], scale);
+            __builtin_amdgcn_sched_barrier(0);
+            T* p1 = acc_ptr(col1_c);
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) {
+                acc_add(p0 + 16 * m, d[m][0], d[m][1], scale);
+                acc_add(p1 + 16 * m, d[m][2], d[m][3], scale);
+            }
         } else if (PRE2) {
             V4 b0[KP16];
 #pragma unroll
-            for (int t = 0; t < KP16; ++t) b0[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
-            __builtin_amdgcn_sched_barrier(0);
-            V4 d0 = V4{0, 0, 0, 0};
-            V4 d1 = V4{0, 0, 0, 0};
+            for (int t = 0; t < LA && t < KP16; ++t) b0[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
+            V4 d[MBW][2];
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) d[m][0] = d[m][1] = V4{0, 0, 0, 0};
 #pragma unroll
             for (int t = 0; t < KP16; ++t) {
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    if (t & 1)
-                        d1 = M::step(a[t][e], b0[t][e], d1);
-                    else
-                        d0 = M::step(a[t][e], b0[t][e], d0);
+#pragma unroll
+                    for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
                 }
+                __builtin_amdgcn_sched_barrier(0);
+                if (t + LA < KP16) b0[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * (t + LA));
+                hook(t);
             }
-            acc_add(acc_ptr(col0_c), d0, d1, scale);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int m = 0; m < MBW; ++m) acc_add(p0 + 16 * m, d[m][0], d[m][1], scale);
         } else {
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) hook(t);
             for (int blk = 0; blk < nb_c; ++blk) {
-                V4 d0 = V4{0, 0, 0, 0};
-                V4 d1 = V4{0, 0, 0, 0};
+                V4 d[MBW][2];
+#pragma unroll
+                for (int m = 0; m < MBW; ++m) d[m][0] = d[m][1] = V4{0, 0, 0, 0};
 #pragma unroll
                 for (int t = 0; t < KP16; ++t) {
                     const V4 bv = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        if (t & 1)
-                            d1 = M::step(a[t][e], bv[e], d1);
-                        else
-                            d0 = M::step(a[t][e], bv[e], d0);
+#pragma unroll
+                        for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], bv[e], d[m][t & 1]);
                     }
                 }
-                acc_add(acc_ptr(blk ? col1_c : col0_c), d0, d1, scale);
+                T* pp = blk ? acc_ptr(col1_c) : p0;
+#pragma unroll
+                for (int m = 0; m < MBW; ++m) acc_add(pp + 16 * m, d[m][0], d[m][1], scale);
             }
         }
     };
@@ -374,14 +462,15 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
     // MFMAs are skipped), so every load of the loop is issued by the same code
     // in the same order, and the wait counts are the same on every iteration.
     // A clamped chunk index past the last chunk only repeats valid loads.
-    // cls_c = -1 forces the first A load.
     auto clampc = [&](int ch) { return min(max(ch, cb), ce - 1); };
     unpack_meta(load_meta(cb), cls_n, nb_n, sc_n);
+    m_q = load_meta(cb);
     cls_c = -1;
     nb_c = 0;
     sc_c = T(0);
     col0_c = col1_c = -1;
     load_src(cb, src_q);
+    load_src(clampc(cb + 1), src_q2);
     // drain the prologue's loads (s_waitcnt vmcnt(0)), so that the wait
     // counts computed for the loop follow its steady state only
     __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -389,38 +478,59 @@ __global__ void __launch_bounds__(64 * WAVES, 2) gg_kernel(GGParams p) {
     // one iteration: chunk ch with its A rows in `a`; `an` receives chunk
     // ch+1's rows, `gi` holds chunk ch+1's gathered columns (in flight) and
     // `go` receives chunk ch+2's
-    auto step = [&](int ch, int buf, V4 (&a)[KP16], V4 (&an)[KP16], V4 (&gi)[NLD], V4 (&go)[NLD]) {
-        // A rows first, so that the wait at the end of the iteration leaves
-        // only this iteration's metadata and gathers in flight
-        if (ADBL) {
-            if (cls_n != cls_c) {
-                load_a(an, cls_n);
-            } else {
+    auto step = [&](int ch, int buf, V4 (&a)[MBW][KP16], V4 (&an)[MBW][KP16], V4 (&gi)[NLD], V4 (&go)[NLD]) {
+        // Every iteration issues the same loads in the same order (the A rows
+        // of the next chunk are loaded even when its class is unchanged; they
+        // then come from L2): vmcnt retires loads in issue order, so with a
+        // fixed sequence each wait covers exactly the loads it needs, while a
+        // data-dependent load count would make the compiler's waits drain
+        // loads issued in the same iteration. The order is: the A rows of chunk
+        // c+1, K-chunk by K-chunk (hook(t), spread over the MFMAs; needed by
+        // the next iteration's MFMAs), then the gathers of chunk c+2 (stored at
+        // the end of the next iteration) and the indices consumed one or two
+        // iterations later. So no wait ever retires a load of its own iteration
+        // that it does not need, and waiting for the last A rows does not
+        // retire the gathers.
+        int src4[NLD];
+        int m3, n0, n1;
+        auto hook = [&](int t) {
+            if (ADBL) {
+                const uint32_t so = (uint32_t)cls_n * a_cls_bytes;
 #pragma unroll
-                for (int t = 0; t < KP16; ++t) an[t] = a[t];
+                for (int m = 0; m < MBW; ++m)
+                    an[m][t] = bload4<T>(ra, t == KP16 - 1 ? aofl[m] : aoff[m] + 16 * t * (int)sizeof(T), so);
             }
-        }
-        int src3[NLD];
-        load_src(clampc(ch + 3), src3);
-        const int m2 = load_meta(clampc(ch + 2));
-        int n0, n1;
-        tcol(clampc(ch + 1), n0, n1);
-        gather(go, src_q);
+            if (t == KP16 - 1) {
+                gather(go, src_q);
+                load_src(clampc(ch + 4), src4);
+                m3 = load_meta(clampc(ch + 3));
+                tcol(clampc(ch + 1), n0, n1);
+            }
+        };
         // with one staging buffer every chunk uses buffer 0, and the store of
         // the next chunk waits until all waves have read the current one
         const bool one = p.nbuf == 1;
-        if (ch >= cb && ch < ce) mfma_chunk(one ? 0 : buf, a);
+        if (wact && ch >= cb && ch < ce) {
+            mfma_chunk(one ? 0 : buf, a, hook);
+        } else {
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) hook(t);
+        }
         if (one) __syncthreads();
         stage_store(one ? 0 : buf ^ 1, gi);
         if (!ADBL && cls_n != cls_c) load_a(a, cls_n);
         cls_c = cls_n;
         nb_c = nb_n;
         sc_c = sc_n;
-        unpack_meta(m2, cls_n, nb_n, sc_n);
+        unpack_meta(m_q, cls_n, nb_n, sc_n);
+        m_q = m3;
         col0_c = n0;
         col1_c = n1;
 #pragma unroll
-        for (int i = 0; i < NLD; ++i) src_q[i] = src3[i];
+        for (int i = 0; i < NLD; ++i) {
+            src_q[i] = src_q2[i];
+            src_q2[i] = src4[i];
+        }
         __syncthreads();
     };
     // both iterations of the unrolled pair always run (one past the last
@@ -563,25 +673,25 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     }
 }
 
-template <typename T, int KP16, int WAVES>
+template <typename T, int KP16, int WAVES, int MBW>
 hipError_t gg_launch_t(const GGParams& p, int blocks, size_t lds, hipStream_t st) {
     static size_t attr_set = 0;
     if (lds > 65536 && lds > attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES, MBW>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = lds;
     }
-    hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
+    hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES, MBW>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
     return hipGetLastError();
 }
 
-template <typename T, int WAVES>
+template <typename T, int WAVES, int MBW>
 hipError_t gg_dispatch(int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st) {
     switch (KP16) {
 #define KIFMM_GG_CASE(K) \
     case K:              \
-        return gg_launch_t<T, K, WAVES>(p, blocks, lds, st);
+        return gg_launch_t<T, K, WAVES, MBW>(p, blocks, lds, st);
         KIFMM_GG_CASE(1) KIFMM_GG_CASE(2) KIFMM_GG_CASE(3) KIFMM_GG_CASE(4) KIFMM_GG_CASE(5)
         KIFMM_GG_CASE(6) KIFMM_GG_CASE(7) KIFMM_GG_CASE(8) KIFMM_GG_CASE(9) KIFMM_GG_CASE(10)
         KIFMM_GG_CASE(11) KIFMM_GG_CASE(12) KIFMM_GG_CASE(13) KIFMM_GG_CASE(14) KIFMM_GG_CASE(15)
@@ -595,9 +705,13 @@ hipError_t gg_dispatch(int KP16, const GGParams& p, int blocks, size_t lds, hipS
 template <typename T>
 hipError_t gg_variant(int variant, int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st) {
     switch (variant) {
-        case 0: return gg_dispatch<T, 8>(KP16, p, blocks, lds, st);
+        case 0: return gg_dispatch<T, 8, 1>(KP16, p, blocks, lds, st);
         case 1:
-        case 2: return gg_dispatch<T, 4>(KP16, p, blocks, lds, st);
+        case 2: return gg_dispatch<T, 4, 1>(KP16, p, blocks, lds, st);
+        case 3:
+            // two row blocks per wave: FP32 only (the FP64 registers would spill)
+            if constexpr (sizeof(T) == 4) return gg_dispatch<T, 4, 2>(KP16, p, blocks, lds, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -609,8 +723,13 @@ int gg_variant_rows(int variant) {
         case 0: return 8 * 16;
         case 1:
         case 2: return 4 * 16;
+        case 3: return 4 * 2 * 16;
         default: return 0;
     }
+}
+
+bool gg_variant_supported(int variant, int elt) {
+    return variant >= 0 && variant < kGGVariants && (variant != 3 || elt == 4);
 }
 
 int gg_variant_wgs_per_cu(int variant) { return variant == 2 ? 2 : 1; }
@@ -627,13 +746,16 @@ size_t gg_lds_bytes(int elt, int variant, int KP16, int cols) {
             (size_t)cols * (gg_variant_rows(variant) + 4)) * elt;
 }
 
-hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, const void* X,
-                     int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st) {
+hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, int a_rows, int a_cols,
+                     const void* X, int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st) {
     if (s.n_tiles == 0) return hipSuccess;
+    if (a_rows < 1 || a_rows > MB * 16 || a_cols < 1 || a_cols > KP16 * 16) return hipErrorInvalidValue;
     GGParams p;
     p.A = A;
     p.a_stride = (int64_t)MB * 16 * KP16 * 16;
     p.lda = KP16 * 16;
+    p.a_rows = a_rows;
+    p.a_cols = a_cols;
     p.X = X;
     p.ldx = ldx;
     p.Y = Y;
@@ -644,7 +766,7 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
     p.accumulate = accumulate;
     p.n_tiles = s.n_tiles;
     const int mbg = gg_variant_rows(s.variant) / 16;
-    if (mbg == 0 || s.cp * R != 32 || s.max_tile < 1) return hipErrorInvalidValue;
+    if (!gg_variant_supported(s.variant, elt) || s.cp * R != 32 || s.max_tile < 1) return hipErrorInvalidValue;
     p.n_rg = (MB + mbg - 1) / mbg;
     p.nbuf = gg_nbuf(elt, s.variant, KP16);
     p.trash_col = s.max_tile;
