@@ -69,6 +69,10 @@ struct kifmm_plan_s {
     void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
     std::vector<void*> allocs;
     size_t device_bytes = 0;
+    // the near field runs on a stream of its own, forked from and joined back
+    // into the caller's stream, so that it overlaps the far-field passes
+    hipStream_t near_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     kifmm_info_t info{};
     // stage profiling
     bool profiling = false;
@@ -91,6 +95,14 @@ struct kifmm_group_s {
 };
 
 namespace {
+
+void release_streams(kifmm_plan_s* pl) {
+    if (pl->near_stream) (void)hipStreamDestroy(pl->near_stream);
+    if (pl->ev_fork) (void)hipEventDestroy(pl->ev_fork);
+    if (pl->ev_join) (void)hipEventDestroy(pl->ev_join);
+    pl->near_stream = nullptr;
+    pl->ev_fork = pl->ev_join = nullptr;
+}
 
 void release_device(kifmm_plan_s* pl) {
     if (!pl->allocs.empty()) {
@@ -370,18 +382,24 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile, int m2l_shape) {
         std::vector<int32_t> ptr(nleaf + 1), src(nleaf), cls(nleaf, 0);
         for (int64_t e = 0; e <= nleaf; ++e) ptr[e] = (int32_t)e;
         for (int64_t e = 0; e < nleaf; ++e) src[e] = (int32_t)e;
-        const int tile_up = std::min(std::max(16, 128 / pl->R), max_tile_for(pl, 0, pl->nep));
+        const int per_cu = (int)((nleaf + pl->num_cu - 1) / pl->num_cu);
+        const int tile_up = std::min(std::max(16 / pl->R + 1, per_cu), max_tile_for(pl, 0, pl->nep));
         gg_build(pl->h_leafup, lb, nleaf, ptr.data(), src.data(), cls.data(), nullptr, inv4pi,
                  uniform_cuts(nleaf, tile_up));
         for (int64_t e = 0; e < nleaf; ++e) src[e] = (int32_t)(lb + e);
-        const int tile_dn = std::min(std::max(16, 128 / pl->R), max_tile_for(pl, 0, pl->kp));
+        const int tile_dn = std::min(std::max(16 / pl->R + 1, per_cu), max_tile_for(pl, 0, pl->kp));
         gg_build(pl->h_leafdown, 0, nleaf, ptr.data(), src.data(), cls.data(), nullptr, one,
                  uniform_cuts(nleaf, tile_dn));
     }
     // small levels get small tiles so that their launches still spread over the chip
+    // tiles of a per-level launch: about one workgroup per CU for the large
+    // levels (a workgroup's fixed costs - pipeline fill, accumulator load and
+    // store - then amortise over many chunks), small ones for small levels so
+    // that they still spread over the chip
     auto level_tile = [&](int64_t nb) {
-        int64_t tl = std::max<int64_t>(16, std::min<int64_t>(64, nb / 256));
-        return (int)std::min<int64_t>(tl / pl->R + 1, max_tile_for(pl, 0, pl->kp));
+        const int64_t per_cu = (nb + pl->num_cu - 1) / pl->num_cu;
+        const int64_t tl = std::max<int64_t>(16 / pl->R + 1, per_cu);
+        return (int)std::min<int64_t>(tl, max_tile_for(pl, 0, pl->kp));
     };
     for (int l = 2; l < L; ++l) {
         // targets at level l, sources their children at level l+1 (class = octant)
@@ -542,6 +560,27 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
     KIFMM_HIP(launch_permute_in(elt, R, t.n, pl->perm, in, ld, nrhs, pl->sig_s, st));
     KIFMM_HIP(mark(KIFMM_STAGE_PERM, 1));
     const bool far = L >= 2;
+    const double rL = t.half_width(L);
+    // The near field (S2T) runs on the plan's own stream, concurrent with the
+    // far-field passes, and the far-field evaluation waits for it. Under
+    // stream capture everything stays on the capturing stream instead (near
+    // and far fields in one kernel at the end): the fork and join events are
+    // also recorded by eager applies, and an event recorded during a capture
+    // must not be reused outside it.
+    hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+    KIFMM_HIP(hipStreamIsCapturing(st, &cap_status));
+    const bool fork = far && cap_status == hipStreamCaptureStatusNone;
+    if (fork) {
+        hipStream_t ns = pl->near_stream;
+        KIFMM_HIP(hipEventRecord(pl->ev_fork, st));
+        KIFMM_HIP(hipStreamWaitEvent(ns, pl->ev_fork, 0));
+        if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P], ns));
+        KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->near_ptr,
+                                      pl->near_leaf, pl->near_code, nullptr, pl->surf, pl->ops.n_eq, nep,
+                                      1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, ns));
+        if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P + 1], ns));
+        KIFMM_HIP(hipEventRecord(pl->ev_join, ns));
+    }
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 0));
     if (far) {
         // upward (forward) / L2T^T (adjoint): surface evaluation and the leaf GEMM
@@ -587,14 +626,24 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
             KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, pl->ops.n_eq, pl->k, pl->P, kp, pl->E, nep, R, 0, st));
         else
             KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, pl->ops.n_eq, pl->k, pl->Q, kp, pl->E, nep, R, 0, st));
+        if (fork) {
+            // far field at the points (L2T), added to the near field
+            KIFMM_HIP(hipStreamWaitEvent(st, pl->ev_join, 0));
+            KIFMM_HIP(launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->near_ptr,
+                                          pl->near_leaf, pl->near_code, pl->E, pl->surf, pl->ops.n_eq, nep,
+                                          1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
+        }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_L2P, 1));
-    const double rL = t.half_width(L);
-    KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
-    KIFMM_HIP(launch_eval_targets(elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->near_ptr, pl->near_leaf,
-                                  pl->near_code, far ? pl->E : nullptr, pl->surf, pl->ops.n_eq, nep,
-                                  1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
-    KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
+    if (!fork) {
+        // near field and (when there is one) far field in one kernel
+        KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
+        KIFMM_HIP(launch_eval_targets(3, elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->near_ptr,
+                                      pl->near_leaf, pl->near_code, far ? pl->E : nullptr, pl->surf,
+                                      pl->ops.n_eq, nep, 1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out,
+                                      ld, nrhs, st));
+        KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
+    }
     if (cur != pl->device) KIFMM_HIP(hipSetDevice(cur));
     return KIFMM_OK;
 }
@@ -740,11 +789,19 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         for (size_t l = 0; l < pl->h_up.size(); ++l) pl->d_up[l] = upload_sched(up, pl->h_up[l], pl->elt);
         for (size_t l = 0; l < pl->h_down.size(); ++l) pl->d_down[l] = upload_sched(up, pl->h_down[l], pl->elt);
         if (up.err == KIFMM_OK && tune) autotune_m2l(pl, up);
+        if (up.err == KIFMM_OK &&
+            (hipStreamCreateWithFlags(&pl->near_stream, hipStreamNonBlocking) != hipSuccess ||
+             hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
+             hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming) != hipSuccess)) {
+            up.err = KIFMM_EHIP;
+            up.msg = "creating the near-field stream or its events failed";
+        }
         hipDeviceSynchronize();
         hipSetDevice(cur);
         if (up.err != KIFMM_OK) {
             int code = up.err;
             std::string msg = up.msg;
+            release_streams(pl);
             release_device(pl);
             delete pl;
             return fail(code, msg);
@@ -846,6 +903,7 @@ void kifmm_destroy(kifmm_plan_t plan) {
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(plan->device);
         destroy_profile_events(plan);
+        release_streams(plan);
         (void)hipSetDevice(cur);
     }
     release_device(plan);

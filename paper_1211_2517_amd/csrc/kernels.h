@@ -64,9 +64,12 @@ hipError_t launch_eval_surface(int elt, int R, int64_t n_leaf, const void* pts, 
                                const int32_t* leaf_ptr, const void* surf, int n_eq, int nep,
                                void* C, hipStream_t st);
 
-// out[perm[i] + r*ld] = near_scale * sum_{near j != i} sig_s[j] / |u_i - u_j + 2 d|
-//                     + far_scale  * sum_a E[(leaf*R+r)*nep + a] / |u_i - surf_a|   (if E != null)
-hipError_t launch_eval_targets(int elt, int R, int64_t n_leaf, const void* pts, const void* sig_s,
+// Evaluation at the points of every leaf (i in the leaf, caller index perm[i]):
+//   near(i) = near_scale * sum_{near j != i} sig_s[j] / |u_i - u_j + 2 d|
+//   far(i)  = far_scale  * sum_a E[(leaf*R+r)*nep + a] / |u_i - surf_a|
+// mode 1: out[perm[i] + r*ld] = near(i); mode 2: out[...] += far(i) (E must
+// not be null); mode 3: out[...] = near(i) + far(i) (far omitted if E is null).
+hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const void* pts, const void* sig_s,
                                const int32_t* leaf_ptr, const int32_t* near_ptr,
                                const int32_t* near_leaf, const int32_t* near_code, const void* E,
                                const void* surf, int n_eq, int nep, double near_scale,

@@ -11,6 +11,12 @@
 //                the leaf's points (L2T, Sec. 2.2), scattered to caller order.
 #include "kernels.h"
 
+#ifndef GG_XCD_RUN
+#define GG_XCD_RUN 1
+#endif
+#ifndef GG_LA
+#define GG_LA 2
+#endif
 namespace kifmm {
 
 namespace {
@@ -65,6 +71,7 @@ struct GGParams {
     int accumulate;
     int n_tiles;
     int n_rg;
+    int xcd_run;     // consecutive tiles given to one XCD
     int nbuf;        // LDS staging buffers (2: double buffer; 1: wide K in FP64)
     int trash_col;   // first of R accumulator columns that take the products of empty slots
     // extents (bytes) of the buffer resources: loads past them return zero
@@ -180,9 +187,12 @@ __device__ __forceinline__ double meta_scale<double>(int lo, int hi) {
 // K-chunk t, lane group g = l/16 supplies indices 16t + 4g + e for the 4
 // consecutive MFMA steps e = 0..3.
 //
-// Block b maps to tile (b / (8*n_rg))*8 + b%8 and row group (b/8) % n_rg, so
-// the row groups of a tile run on the same XCD (blocks are dealt to the 8 XCDs
-// round-robin) and share its L2 for the gathered columns.
+// Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// Runs of xcd_run consecutive tiles go to one XCD, with the row groups of a
+// tile next to each other: for k = b/8 and q = k/n_rg, block b is row group
+// k % n_rg of tile ((q / xcd_run)*8 + b%8)*xcd_run + q % xcd_run. Tiles are
+// Morton-ordered ranges of targets, so the row groups of a tile, and
+// neighbouring tiles of a run, share their source columns in one L2.
 template <typename T, int KP16, int WAVES, int MBW>
 __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGParams p) {
     using M = Mfma<T>;
@@ -199,8 +209,10 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     constexpr bool ADBL = KP16 * sizeof(T) <= 64;
     constexpr bool PRE2 = KP16 * sizeof(T) <= 32;
     const int b = blockIdx.x;
-    const int rg = (b >> 3) % p.n_rg;
-    const int tile = (b / (8 * p.n_rg)) * 8 + (b & 7);
+    const int kx = b >> 3;
+    const int rg = kx % p.n_rg;
+    const int q = kx / p.n_rg;
+    const int tile = ((q / p.xcd_run) * 8 + (b & 7)) * p.xcd_run + q % p.xcd_run;
     if (tile >= p.n_tiles) return;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -370,7 +382,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     // and after K-chunk t the call hook(t) (the A rows of the next chunk and
     // this iteration's other loads). Other shapes call hook(t) for every t
     // before the MFMAs.
-    constexpr int LA = 2;
+    constexpr int LA = GG_LA;
     auto mfma_chunk = [&](int buf, const V4 (&a)[MBW][KP16], auto&& hook) {
         const T* bcol = bbuf + (buf * 32 + j) * LDB + 4 * grp;
         const T scale = sc_c;
@@ -565,55 +577,116 @@ __global__ void __launch_bounds__(256) permute_in_kernel(int64_t n, const int32_
     for (int r = 0; r < R; ++r) sig_s[i * R + r] = r < nrhs ? sigma[src + r * ld] : T(0);
 }
 
-// one wave per leaf; lanes run over the surface points
+// Check potential of a leaf's points on its (3-2d) surface: one wave per
+// leaf, lanes over the surface points. The wave stages the leaf's points as
+// (x, y, z, sigma) 4-vectors in LDS (sigmas of further right-hand sides in a
+// second array), in batches of at most CAP points, so each interaction reads
+// one broadcast LDS vector.
 template <typename T, int R>
 __global__ void __launch_bounds__(256) eval_surface_kernel(int64_t n_leaf, const P4<T>* __restrict__ pts,
                                                            const T* __restrict__ sig,
                                                            const int32_t* __restrict__ leaf_ptr,
                                                            const T* __restrict__ surf, int n_eq,
                                                            int nep, T* __restrict__ C) {
-    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    constexpr int WPB = 4;
+    constexpr int CAP = 64;
+    __shared__ P4<T> sp[WPB][CAP];
+    __shared__ T ss[WPB][R > 1 ? CAP * R : 1];
+    const int wave = threadIdx.x >> 6;
+    const int64_t leaf = (int64_t)blockIdx.x * WPB + wave;
     if (leaf >= n_leaf) return;
     const int lane = threadIdx.x & 63;
+    P4<T>* st = sp[wave];
+    T* sst = ss[wave];
     const int p0 = leaf_ptr[leaf];
     const int p1 = leaf_ptr[leaf + 1];
-    for (int a0 = 0; a0 < nep; a0 += 64) {
-        const int a = a0 + lane;
+    constexpr int NA = (19 * 16 + 63) / 64;   // surface points per lane, at most
+    T sx[NA], sy[NA], sz[NA];
+    T acc[NA][R];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int a = k * 64 + lane;
         const bool valid = a < n_eq;
-        T sx = 0, sy = 0, sz = 0;
-        if (valid) {
-            sx = surf[3 * a];
-            sy = surf[3 * a + 1];
-            sz = surf[3 * a + 2];
+        sx[k] = valid ? surf[3 * a] : T(0);
+        sy[k] = valid ? surf[3 * a + 1] : T(0);
+        sz[k] = valid ? surf[3 * a + 2] : T(0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[k][r] = 0;
+    }
+    const int na = (nep + 63) / 64;
+    for (int base = p0; base < p1; base += CAP) {
+        const int cnt = min(CAP, p1 - base);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const P4<T> v = pts[base + lane];
+            T w0 = T(0);
+            if constexpr (R == 1) {
+                w0 = sig[base + lane];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) sst[lane * R + r] = sig[(int64_t)(base + lane) * R + r];
+            }
+            st[lane] = P4<T>{v.x, v.y, v.z, w0};
         }
-        T acc[R];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+        for (int jj = 0; jj < cnt; ++jj) {
+            const P4<T> f = st[jj];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = 0;
-        for (int jj = p0; jj < p1; ++jj) {
-            const P4<T> q = pts[jj];
-            const T dx = sx - q.x, dy = sy - q.y, dz = sz - q.z;
-            const T rinv = rsq(dx * dx + dy * dy + dz * dz);
+            for (int k = 0; k < NA; ++k) {
+                if (k < na) {
+                    const T dx = sx[k] - f.x, dy = sy[k] - f.y, dz = sz[k] - f.z;
+                    const T rinv = rsq(dx * dx + dy * dy + dz * dz);
+                    if constexpr (R == 1) {
+                        acc[k][0] += f.w * rinv;
+                    } else {
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += sig[(int64_t)jj * R + r] * rinv;
+                        for (int r = 0; r < R; ++r) acc[k][r] += sst[jj * R + r] * rinv;
+                    }
+                }
+            }
         }
-        if (a < nep) {
+    }
 #pragma unroll
-            for (int r = 0; r < R; ++r) C[(leaf * R + r) * nep + a] = valid ? acc[r] : T(0);
+    for (int k = 0; k < NA; ++k) {
+        const int a = k * 64 + lane;
+        if (k < na && a < nep) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) C[(leaf * R + r) * nep + a] = a < n_eq ? acc[k][r] : T(0);
         }
     }
 }
 
-// one wave per target leaf; `lpt` lanes per target split the sources
-template <typename T, int R>
+// Near field (S2T, MODE bit 1) and far field (L2T, MODE bit 2) at the points
+// of a target leaf: one wave per target leaf, `lpt` lanes per target splitting
+// the sources. MODE 1 writes the near field, MODE 2 adds the far field to
+// what is there, MODE 3 writes both.
+// The wave stages the points of its near-field leaves in its own LDS slots
+// as 4-vectors (x, y, z in target-leaf units, sigma for one right-hand side;
+// the sigmas of several right-hand sides sit in a second array), so each
+// interaction reads one broadcast LDS vector; batches of at most CAP points
+// are staged and consumed in turn. For the far field the wave stages the
+// leaf's downward equivalent surface as (x, y, z, E) vectors the same way
+// (one right-hand side), or reads E from global memory (several).
+template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(256) eval_targets_kernel(
     int64_t n_leaf, const P4<T>* __restrict__ pts, const T* __restrict__ sig,
     const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ near_ptr,
     const int32_t* __restrict__ near_leaf, const int32_t* __restrict__ near_code,
     const T* __restrict__ E, const T* __restrict__ surf, int n_eq, int nep, T near_scale,
     T far_scale, const int32_t* __restrict__ perm, T* __restrict__ out, int64_t ld, int nrhs) {
-    const int64_t leaf = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (leaf >= n_leaf) return;
+    constexpr int WPB = 4;
+    constexpr int CAP = (R >= 8 ? 64 : R >= 2 ? 128 : 256) / (int)(sizeof(T) / 4);
+    constexpr int MAXEQ = 19 * 16;
+    __shared__ P4<T> sp[(MODE & 1) ? WPB : 1][(MODE & 1) ? CAP : 1];
+    __shared__ T ss[(MODE & 1) ? WPB : 1][(MODE & 1) && R > 1 ? CAP * R : 1];
+    __shared__ P4<T> fs[(MODE & 2) && R == 1 ? WPB : 1][(MODE & 2) && R == 1 ? MAXEQ : 1];
+    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    const int64_t leaf = (int64_t)blockIdx.x * WPB + wave;
+    if (leaf >= n_leaf) return;
+    P4<T>* st = sp[(MODE & 1) ? wave : 0];
+    T* sst = ss[(MODE & 1) ? wave : 0];
     const int p0 = leaf_ptr[leaf];
     const int ne = leaf_ptr[leaf + 1] - p0;
     int lpt = 64;
@@ -622,6 +695,13 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     const int sub = lane & (lpt - 1);
     const int q0 = near_ptr[leaf];
     const int q1 = near_ptr[leaf + 1];
+    const bool far_on = (MODE & 2) && E != nullptr;
+    if constexpr ((MODE & 2) && R == 1) {
+        if (far_on) {
+            for (int a = lane; a < n_eq; a += 64)
+                fs[wave][a] = P4<T>{surf[3 * a], surf[3 * a + 1], surf[3 * a + 2], E[leaf * nep + a]};
+        }
+    }
     for (int tb = 0; tb < ne; tb += tpr) {
         const int tl = tb + lane / lpt;
         const bool valid = tl < ne;
@@ -630,31 +710,73 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
         T acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0;
-        for (int q = q0; q < q1; ++q) {
-            const int nb = near_leaf[q];
-            const int code = near_code[q];
-            const T wx = ui.x + T(2 * (code / 9 - 1));
-            const T wy = ui.y + T(2 * ((code / 3) % 3 - 1));
-            const T wz = ui.z + T(2 * (code % 3 - 1));
-            const int b1 = leaf_ptr[nb + 1];
-            for (int jj = leaf_ptr[nb] + sub; jj < b1; jj += lpt) {
-                const P4<T> s = pts[jj];
-                const T dx = wx - s.x, dy = wy - s.y, dz = wz - s.z;
+        // consume the staged batch of n points
+        auto consume = [&](int n) {
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+            for (int jj = sub; jj < n; jj += lpt) {
+                const P4<T> f = st[jj];
+                const T dx = ui.x - f.x, dy = ui.y - f.y, dz = ui.z - f.z;
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 const T rinv = r2 > T(0) ? rsq(r2) : T(0);
+                if constexpr (R == 1) {
+                    acc[0] += f.w * rinv;
+                } else {
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[r] += sig[(int64_t)jj * R + r] * rinv;
+                    for (int r = 0; r < R; ++r) acc[r] += sst[jj * R + r] * rinv;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        };
+        int n_st = 0;
+        for (int q = (MODE & 1) ? q0 : q1; q < q1; ++q) {
+            const int nb = near_leaf[q];
+            const int code = near_code[q];
+            // source shifted into target-leaf units: s - 2 d, d = target - source cube
+            const T shx = T(2 * (code / 9 - 1)), shy = T(2 * ((code / 3) % 3 - 1)), shz = T(2 * (code % 3 - 1));
+            const int b0 = leaf_ptr[nb];
+            const int c = leaf_ptr[nb + 1] - b0;
+            for (int base = 0; base < c; base += 64) {
+                const int cnt = min(64, c - base);
+                if (n_st + cnt > CAP) {
+                    consume(n_st);
+                    n_st = 0;
+                }
+                if (lane < cnt) {
+                    const int jj = b0 + base + lane;
+                    const P4<T> sv = pts[jj];
+                    T w0 = T(0);
+                    if constexpr (R == 1) {
+                        w0 = sig[jj];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) sst[(n_st + lane) * R + r] = sig[(int64_t)jj * R + r];
+                    }
+                    st[n_st + lane] = P4<T>{sv.x - shx, sv.y - shy, sv.z - shz, w0};
+                }
+                n_st += cnt;
             }
         }
+        if (n_st > 0) consume(n_st);
         T far[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) far[r] = 0;
-        if (E != nullptr) {
-            for (int a = sub; a < n_eq; a += lpt) {
-                const T dx = ui.x - surf[3 * a], dy = ui.y - surf[3 * a + 1], dz = ui.z - surf[3 * a + 2];
-                const T rinv = rsq(dx * dx + dy * dy + dz * dz);
+        if (far_on) {
+            if constexpr ((MODE & 2) && R == 1) {
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+                for (int a = sub; a < n_eq; a += lpt) {
+                    const P4<T> f = fs[wave][a];
+                    const T dx = ui.x - f.x, dy = ui.y - f.y, dz = ui.z - f.z;
+                    far[0] += f.w * rsq(dx * dx + dy * dy + dz * dz);
+                }
+            } else {
+                for (int a = sub; a < n_eq; a += lpt) {
+                    const T dx = ui.x - surf[3 * a], dy = ui.y - surf[3 * a + 1], dz = ui.z - surf[3 * a + 2];
+                    const T rinv = rsq(dx * dx + dy * dy + dz * dz);
 #pragma unroll
-                for (int r = 0; r < R; ++r) far[r] += E[(leaf * R + r) * nep + a] * rinv;
+                    for (int r = 0; r < R; ++r) far[r] += E[(leaf * R + r) * nep + a] * rinv;
+                }
             }
         }
         for (int off = lpt >> 1; off > 0; off >>= 1) {
@@ -667,8 +789,16 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
         if (valid && sub == 0) {
             const int64_t dst = perm[i];
 #pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (r < nrhs) out[dst + r * ld] = near_scale * acc[r] + far_scale * far[r];
+            for (int r = 0; r < R; ++r) {
+                if (r < nrhs) {
+                    if constexpr (MODE == 1)
+                        out[dst + r * ld] = near_scale * acc[r];
+                    else if constexpr (MODE == 2)
+                        out[dst + r * ld] += far_scale * far[r];
+                    else
+                        out[dst + r * ld] = near_scale * acc[r] + far_scale * far[r];
+                }
+            }
         }
     }
 }
@@ -791,7 +921,8 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
     // accumulator columns: the largest tile plus the spare columns of empty slots
     const size_t lds = gg_lds_bytes(elt, s.variant, KP16, (s.max_tile + 1) * R);
     if (lds > gg_lds_limit(s.variant) || KP16 < 1 || KP16 > 19) return hipErrorInvalidValue;
-    const int blocks = (s.n_tiles + 7) / 8 * 8 * p.n_rg;
+    p.xcd_run = GG_XCD_RUN;
+    const int blocks = (s.n_tiles + 8 * p.xcd_run - 1) / (8 * p.xcd_run) * 8 * p.xcd_run * p.n_rg;
     if (elt == 4) return gg_variant<float>(s.variant, KP16, p, blocks, lds, st);
     return gg_variant<double>(s.variant, KP16, p, blocks, lds, st);
 }
@@ -836,25 +967,25 @@ hipError_t launch_eval_surface(int elt, int R, int64_t n_leaf, const void* pts, 
     return hipGetLastError();
 }
 
-hipError_t launch_eval_targets(int elt, int R, int64_t n_leaf, const void* pts, const void* sig_s,
+hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const void* pts, const void* sig_s,
                                const int32_t* leaf_ptr, const int32_t* near_ptr, const int32_t* near_leaf,
                                const int32_t* near_code, const void* E, const void* surf, int n_eq, int nep,
                                double near_scale, double far_scale, const int32_t* perm, void* out,
                                int64_t ld, int nrhs, hipStream_t st) {
     if (n_leaf == 0) return hipSuccess;
+    if (mode < 1 || mode > 3 || (mode == 2 && E == nullptr)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n_leaf + 3) / 4));
+#define KIFMM_EVT(TT, M)                                                                                  \
+    KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_targets_kernel<TT, RR, M>), grid, dim3(256), 0, st, n_leaf, \
+                                         (const P4<TT>*)pts, (const TT*)sig_s, leaf_ptr, near_ptr, near_leaf, \
+                                         near_code, (const TT*)E, (const TT*)surf, n_eq, nep, (TT)near_scale, \
+                                         (TT)far_scale, perm, (TT*)out, ld, nrhs))
     if (elt == 4) {
-        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_targets_kernel<float, RR>), grid, dim3(256), 0, st, n_leaf,
-                                             (const P4<float>*)pts, (const float*)sig_s, leaf_ptr, near_ptr,
-                                             near_leaf, near_code, (const float*)E, (const float*)surf, n_eq,
-                                             nep, (float)near_scale, (float)far_scale, perm, (float*)out, ld,
-                                             nrhs))
+        if (mode == 1) { KIFMM_EVT(float, 1) } else if (mode == 2) { KIFMM_EVT(float, 2) } else { KIFMM_EVT(float, 3) }
     } else {
-        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_targets_kernel<double, RR>), grid, dim3(256), 0, st, n_leaf,
-                                             (const P4<double>*)pts, (const double*)sig_s, leaf_ptr, near_ptr,
-                                             near_leaf, near_code, (const double*)E, (const double*)surf, n_eq,
-                                             nep, near_scale, far_scale, perm, (double*)out, ld, nrhs))
+        if (mode == 1) { KIFMM_EVT(double, 1) } else if (mode == 2) { KIFMM_EVT(double, 2) } else { KIFMM_EVT(double, 3) }
     }
+#undef KIFMM_EVT
     return hipGetLastError();
 }
 
