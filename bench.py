@@ -97,7 +97,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["svd", "dense64", "dense32"], default=None,
+    ap.add_argument("--only", choices=["svd", "dense64", "dense32", "svd_bf16x3"], default=None,
                     help="time one plan only (profiling runs); prints no JSON line")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MB (a kernel of known "
@@ -139,7 +139,9 @@ def main():
     # the dense-M2L matvec that reaches the same accuracy. dense32: uncompressed
     # in FP32 (same precision as svd; its rounding error is reported, it does
     # not reach the accuracy because the uncompressed translations amplify it).
-    for name, dense, prec in (("svd", False, "fp32"), ("dense64", True, "fp64"), ("dense32", True, "fp32")):
+    # svd_bf16x3: the compressed path with the split-BF16 M2L (precision mode).
+    for name, dense, prec in (("svd", False, "fp32"), ("dense64", True, "fp64"), ("dense32", True, "fp32"),
+                              ("svd_bf16x3", False, "bf16x3")):
         if args.only and name != args.only:
             continue
         log(f"plan {name}")
@@ -196,6 +198,9 @@ def main():
                            "m2l_mfma_util": round(dense_m2l / PEAK_FP32_MFMA_TFLOPS, 4),
                            "stage_ms": {k: round(v, 4) for k, v in d32["stages"].items()}},
         "m2l_speedup_vs_dense_m2l_fp32": round(d32["stages"]["m2l"] / m2l_ms, 3),
+        "svd_bf16x3": {"ms_per_step": round(res["svd_bf16x3"]["ms"], 4),
+                       "err_vs_fp64_dense_oracle": res["svd_bf16x3"]["err"],
+                       "m2l_ms": round(res["svd_bf16x3"]["stages"]["m2l"], 4)},
         "m2l_mfma_util": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
         "stage_ms": {k: round(v, 4) for k, v in svd["stages"].items()},
         "err_vs_fp64_dense_oracle": svd["err"],

@@ -54,7 +54,10 @@ enum {
     KIFMM_FP64 = 0,  /* every device stage in double */
     KIFMM_FP32 = 1,  /* every device stage in float; M2L/translation GEMMs on FP32 MFMA */
     KIFMM_BF16X3 = 2 /* as FP32, but the M2L GEMM as three BF16 MFMA products (hi*hi + hi*lo +
-                        lo*hi) with FP32 accumulation */
+                        lo*hi) with FP32 accumulation: K~ is split into BF16 high and low parts at
+                        plan time, the gathered q~ columns when they are staged; each product then
+                        carries a relative error of order 2^-16 (the compressed space is padded to
+                        a multiple of 32) */
 };
 
 typedef struct {
@@ -174,9 +177,12 @@ int kifmm_plan_export_tree(kifmm_plan_t plan, int32_t* leaf_coords);
 int kifmm_plan_export_operator(kifmm_plan_t plan, int which, double* out, int64_t* count);
 
 /* Stage timing with HIP events (the tracing facility). While enabled, every
- * apply of the plan records an event on its stream before and after each stage
+ * apply of the plan records an event before and after each stage
  * (KIFMM_STAGE_* order: P2M = surface evaluation + S~ GEMM, M2M, M2L, L2L,
- * L2P = T~ GEMM, P2P = near field + L2T evaluation + scatter, PERM = permute-in).
+ * L2P = T~ GEMM + far-field evaluation at the points, P2P = near field,
+ * PERM = permute-in). The near field runs on a stream of the plan, forked from
+ * the caller's stream after the permute and joined back before the far-field
+ * evaluation, so its time overlaps the other stages'.
  * Enabled applies cannot be captured in a HIP graph. kifmm_profile(plan, 0/1)
  * switches it and clears the totals. */
 int kifmm_profile(kifmm_plan_t plan, int enable);

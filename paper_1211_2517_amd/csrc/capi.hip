@@ -46,6 +46,7 @@ struct kifmm_plan_s {
     HostTree tree;
     HostOps ops;
     int k = 0, kp = 0, nep = 0, R = 1, elt = 4;
+    bool b3 = false;    // M2L in split BF16 (KIFMM_BF16X3); all other stages FP32
     bool on_device = false;
     int device = 0;
     int num_cu = 256;   // compute units of the device (MI355X: 256)
@@ -218,13 +219,54 @@ int neg_class(int c) {
     return class_of_offset(-t[0], -t[1], -t[2]);
 }
 
+// BF16 bits of a float, rounded to nearest even (finite inputs).
+uint16_t bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+double bf16_value(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Split-BF16 table of `nblk` zero-padded rows_pad x cols_pad blocks (cols_pad a
+// multiple of 32): per row and 32-wide column chunk, the 32 high parts
+// hi = bf16(x), then the 32 low parts lo = bf16(x - hi), so a row takes the
+// bytes of cols_pad floats.
+std::vector<uint16_t> split_blocks(int nblk, int rows, int cols, int rows_pad, int cols_pad,
+                                   const std::function<double(int, int, int)>& f) {
+    std::vector<uint16_t> out((size_t)nblk * rows_pad * cols_pad * 2, 0);
+    for (int b = 0; b < nblk; ++b)
+        for (int i = 0; i < rows; ++i)
+            for (int j = 0; j < cols; ++j) {
+                const double x = f(b, i, j);
+                const uint16_t hi = bf16_bits((float)x);
+                const uint16_t lo = bf16_bits((float)(x - bf16_value(hi)));
+                const size_t row = ((size_t)b * rows_pad + i) * cols_pad * 2;
+                const size_t at = row + (size_t)(j / 32) * 64 + (j % 32);
+                out[at] = hi;
+                out[at + 32] = lo;
+            }
+    return out;
+}
+
 template <typename T>
 int upload_tables(kifmm_plan_s* pl, Uploader& up) {
     const HostOps& o = pl->ops;
     const int k = o.k, ne = o.n_eq, kp = pl->kp, nep = pl->nep;
     auto K = [&](int c, int i, int j) { return o.K[((size_t)c * k + i) * k + j]; };
-    pl->Kt = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(c, i, j); }));
-    pl->KtT = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(neg_class(c), j, i); }));
+    if (pl->b3) {
+        pl->Kt = up.put(split_blocks(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(c, i, j); }));
+        pl->KtT = up.put(split_blocks(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(neg_class(c), j, i); }));
+    } else {
+        pl->Kt = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(c, i, j); }));
+        pl->KtT = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(neg_class(c), j, i); }));
+    }
     auto Mf = [&](int b, int i, int j) { return o.M[((size_t)b * k + i) * k + j]; };
     auto Lf = [&](int b, int i, int j) { return o.L[((size_t)b * k + i) * k + j]; };
     pl->Mt = up.put(pad_blocks<T>(8, k, k, kp, kp, Mf));
@@ -491,10 +533,10 @@ void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
         DevSched ds = upload_sched(tmp, hs, pl->elt);
         float ms = 1e30f;
         if (tmp.err == KIFMM_OK) {
-            bool ok = launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->k, pl->k, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st) == hipSuccess;
+            bool ok = launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->k, pl->k, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st, pl->b3) == hipSuccess;
             for (int rep = 0; ok && rep < 3; ++rep) {
                 ok = hipEventRecord(e0, st) == hipSuccess &&
-                     launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->k, pl->k, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st) == hipSuccess &&
+                     launch_gg(ds, pl->elt, pl->Kt, kp16, kp16, pl->k, pl->k, pl->Q, pl->kp, pl->P, pl->kp, pl->R, 0, st, pl->b3) == hipSuccess &&
                      hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
                 float one = 0.f;
                 if (ok && hipEventElapsedTime(&one, e0, e1) == hipSuccess) ms = std::min(ms, one);
@@ -604,9 +646,9 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 0));
     if (far) {
         if (!adjoint)
-            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->P, kp, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->P, kp, R, 0, st, pl->b3));
         else
-            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->KtT, MBk, KPk, pl->k, pl->k, pl->P, kp, pl->Q, kp, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->KtT, MBk, KPk, pl->k, pl->k, pl->P, kp, pl->Q, kp, R, 0, st, pl->b3));
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 0));
@@ -708,7 +750,6 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     if (opts) o = *opts;
     if (o.precision != KIFMM_FP64 && o.precision != KIFMM_FP32 && o.precision != KIFMM_BF16X3)
         return fail(KIFMM_EINVAL, "unknown precision");
-    if (o.precision == KIFMM_BF16X3) return fail(KIFMM_EINVAL, "KIFMM_BF16X3 is not available in this build");
     if (o.max_nrhs < 1 || o.max_nrhs > 16) return fail(KIFMM_EINVAL, "max_nrhs must be in [1, 16]");
     if (o.tile_targets < 0 || o.tile_targets > 4096) return fail(KIFMM_EINVAL, "tile_targets must be in [0, 4096]");
     if (o.device < -1) return fail(KIFMM_EINVAL, "device must be >= -1");
@@ -724,6 +765,7 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     pl->eps = eps;
     pl->leaf_size = leaf_size;
     pl->elt = o.precision == KIFMM_FP64 ? 8 : 4;
+    pl->b3 = o.precision == KIFMM_BF16X3;
     pl->R = 1;
     while (pl->R < o.max_nrhs) pl->R <<= 1;
     try {
@@ -739,7 +781,8 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         return fail(KIFMM_ENOMEM, "host allocation failed");
     }
     pl->k = pl->ops.k;
-    pl->kp = (pl->k + 15) / 16 * 16;
+    // split-BF16 M2L works on 32-wide K-chunks
+    pl->kp = pl->b3 ? (pl->k + 31) / 32 * 32 : (pl->k + 15) / 16 * 16;
     pl->nep = (pl->ops.n_eq + 15) / 16 * 16;
     if (pl->kp > 19 * 16 || pl->nep > 19 * 16) {
         delete pl;

@@ -30,9 +30,13 @@ struct DevSched {
 //  a_rows x a_cols hold data and the rest is zero (the padding is not read);
 //  X rows of length ldx (>= KP16*16, zero past a_cols), Y rows of length
 //  ldy (>= MB*16); row of (box b, right-hand side r) is b*R + r.
-// elt = 4 (FP32 MFMA) or 8 (FP64 MFMA). Returns a hipError_t.
+// elt = 4 (FP32 MFMA) or 8 (FP64 MFMA). With b3 (elt 4, KP16 even) A is in
+// the split-BF16 layout (per row and 32-wide K-chunk: 32 high BF16 parts, then
+// 32 low parts) and the products run on BF16 MFMA with FP32 accumulation.
+// Returns a hipError_t.
 hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, int a_rows, int a_cols,
-                     const void* X, int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st);
+                     const void* X, int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st,
+                     bool b3 = false);
 
 // Kernel shapes (one 16-row block per wave; chunks hold 32 / R pairs):
 //   0 = 8 waves (128 output rows per workgroup), all of a CU's LDS;

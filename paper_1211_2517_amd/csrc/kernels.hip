@@ -125,6 +125,35 @@ __device__ __forceinline__ int bload1(__amdgpu_buffer_rsrc_t r, uint32_t voff, u
     return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
 }
 
+// Split-BF16 product of one 32-wide K-chunk on v_mfma_f32_16x16x32_bf16:
+// d += ah*bh + ah*bl + al*bh, where (ah, al) and (bh, bl) are the high and low
+// BF16 parts of A and B (x = hi + lo + O(2^-16 |x|)); the dropped al*bl term
+// is of the same order. Lane l supplies A[l%16][8*(l/16) + j] and
+// B[8*(l/16) + j][l%16], j = 0..7, and holds D[4*(l/16) + q][l%16] as in the
+// FP32 form.
+__device__ __forceinline__ f32x4 mfma_b3(f32x4 ah, f32x4 al, f32x4 bh, f32x4 bl, f32x4 d) {
+    typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+    const bf8 AH = __builtin_bit_cast(bf8, ah), AL = __builtin_bit_cast(bf8, al);
+    const bf8 BH = __builtin_bit_cast(bf8, bh), BL = __builtin_bit_cast(bf8, bl);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL, BH, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, BL, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, BH, d, 0, 0, 0);
+    return d;
+}
+
+// High and low BF16 parts (round to nearest even) of 4 floats, packed two per word.
+__device__ __forceinline__ void split_bf16(const f32x4& v, uint2& hi, uint2& lo) {
+    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const bf2 h01 = __builtin_convertvector(f2{v[0], v[1]}, bf2);
+    const bf2 h23 = __builtin_convertvector(f2{v[2], v[3]}, bf2);
+    const f2 r01 = f2{v[0], v[1]} - __builtin_convertvector(h01, f2);
+    const f2 r23 = f2{v[2], v[3]} - __builtin_convertvector(h23, f2);
+    hi = uint2{__builtin_bit_cast(uint32_t, h01), __builtin_bit_cast(uint32_t, h23)};
+    lo = uint2{__builtin_bit_cast(uint32_t, __builtin_convertvector(r01, bf2)),
+               __builtin_bit_cast(uint32_t, __builtin_convertvector(r23, bf2))};
+}
+
 // Scheduling pattern for an MFMA sequence of N K-chunks: DS0 LDS reads first,
 // then per K-chunk MF MFMAs, DS LDS reads (operands of a later K-chunk; none
 // in the last LA chunks) and LD vector-memory reads, so that loads issued
@@ -193,8 +222,15 @@ __device__ __forceinline__ double meta_scale<double>(int lo, int hi) {
 // k % n_rg of tile ((q / xcd_run)*8 + b%8)*xcd_run + q % xcd_run. Tiles are
 // Morton-ordered ranges of targets, so the row groups of a tile, and
 // neighbouring tiles of a run, share their source columns in one L2.
-template <typename T, int KP16, int WAVES, int MBW>
+//
+// B3 (split BF16, FP32 data): A holds per row and 32-wide K-chunk c the 32
+// high BF16 parts then the 32 low parts (the 128 bytes of two FP32 16-wide
+// K-chunks); the staging converts the gathered FP32 columns into the same
+// layout in LDS. Register sets and LDS addresses are those of the FP32 form;
+// K-chunk pair (2c, 2c+1) of the FP32 form is (hi, lo) of 32-wide chunk c.
+template <typename T, int KP16, int WAVES, int MBW, bool B3 = false>
 __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGParams p) {
+    static_assert(!B3 || (sizeof(T) == 4 && KP16 % 2 == 0), "split BF16 needs FP32 data and 32-wide K-chunks");
     using M = Mfma<T>;
     using V4 = typename M::V4;
     constexpr int NT = 64 * WAVES;
@@ -270,7 +306,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         const int blk = min(wave * MBW + m, nmb - 1);
         const int row = row0 + blk * 16 + j;
         aoff[m] = row < p.a_rows ? (uint32_t)((row * p.lda + 4 * grp) * (int)sizeof(T)) : kOffNone;
-        aofl[m] = (row < p.a_rows && 16 * (KP16 - 1) + 4 * grp < p.a_cols)
+        aofl[m] = (row < p.a_rows && (B3 || 16 * (KP16 - 1) + 4 * grp < p.a_cols))
                       ? aoff[m] + 16 * (KP16 - 1) * (int)sizeof(T) : kOffNone;
     }
     const uint32_t a_cls_bytes = (uint32_t)(p.a_stride * (int64_t)sizeof(T));
@@ -279,7 +315,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     // staging map: 4-vector f = i*NT + tid of the chunk is part f % V4C of
     // staged column f / V4C (pair f / V4C / R, right-hand side f / V4C % R).
     // Threads past the end repeat the last 4-vector (identical stores).
-    int spair[NLD], soff[NLD];
+    int spair[NLD], soff[NLD];   // soff: FP32 offset, or (B3) offset of the high parts
     uint32_t xoff[NLD];
     bool xpad[NLD];     // 4-vector entirely in the zero padding past a_cols
 #pragma unroll
@@ -289,7 +325,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         spair[i] = c / R;
         const int rhs = c - spair[i] * R;
         const int part = 4 * (f - c * V4C);
-        soff[i] = c * LDB + part;
+        soff[i] = B3 ? c * LDB + (part / 32) * 32 + (part % 32) / 2 : c * LDB + part;
         xoff[i] = (uint32_t)((rhs * p.ldx + part) * (int)sizeof(T));
         xpad[i] = part >= p.a_cols;
     }
@@ -332,7 +368,16 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     };
     auto stage_store = [&](int buf, const V4 (&v)[NLD]) {
 #pragma unroll
-        for (int i = 0; i < NLD; ++i) *reinterpret_cast<V4*>(bbuf + buf * 32 * LDB + soff[i]) = v[i];
+        for (int i = 0; i < NLD; ++i) {
+            if constexpr (B3) {
+                uint2 hi, lo;
+                split_bf16(v[i], hi, lo);
+                *reinterpret_cast<uint2*>(bbuf + buf * 32 * LDB + soff[i]) = hi;
+                *reinterpret_cast<uint2*>(bbuf + buf * 32 * LDB + soff[i] + 16) = lo;
+            } else {
+                *reinterpret_cast<V4*>(bbuf + buf * 32 * LDB + soff[i]) = v[i];
+            }
+        }
     };
     auto load_a = [&](V4 (&dst)[MBW][KP16], int cls) {
         const uint32_t so = (uint32_t)cls * a_cls_bytes;
@@ -402,12 +447,23 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
 #pragma unroll
             for (int t = 0; t < KP16; ++t) {
                 __builtin_amdgcn_sched_barrier(0);
+                if constexpr (B3) {
+                    if (t & 1) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
+                        for (int m = 0; m < MBW; ++m) {
+                            d[m][(t >> 1) & 1] = mfma_b3(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][(t >> 1) & 1]);
+                            d[m][2 + ((t >> 1) & 1)] =
+                                mfma_b3(a[m][t - 1], a[m][t], b1[t - 1], b1[t], d[m][2 + ((t >> 1) & 1)]);
+                        }
+                    }
+                } else {
 #pragma unroll
-                    for (int m = 0; m < MBW; ++m) {
-                        d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
-                        d[m][2 + (t & 1)] = M::step(a[m][t][e], b1[t][e], d[m][2 + (t & 1)]);
+                    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                        for (int m = 0; m < MBW; ++m) {
+                            d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
+                            d[m][2 + (t & 1)] = M::step(a[m][t][e], b1[t][e], d[m][2 + (t & 1)]);
+                        }
                     }
                 }
                 __builtin_amdgcn_sched_barrier(0);
@@ -434,10 +490,18 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
 #pragma unroll
             for (int t = 0; t < KP16; ++t) {
                 __builtin_amdgcn_sched_barrier(0);
+                if constexpr (B3) {
+                    if (t & 1) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
+                        for (int m = 0; m < MBW; ++m)
+                            d[m][(t >> 1) & 1] = mfma_b3(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][(t >> 1) & 1]);
+                    }
+                } else {
 #pragma unroll
-                    for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
+                    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                        for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
+                    }
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 if (t + LA < KP16) b0[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * (t + LA));
@@ -453,13 +517,24 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                 V4 d[MBW][2];
 #pragma unroll
                 for (int m = 0; m < MBW; ++m) d[m][0] = d[m][1] = V4{0, 0, 0, 0};
+                if constexpr (B3) {
 #pragma unroll
-                for (int t = 0; t < KP16; ++t) {
-                    const V4 bv = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
+                    for (int t = 0; t < KP16; t += 2) {
+                        const V4 bh = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
+                        const V4 bl = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * (t + 1));
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
+                        for (int m = 0; m < MBW; ++m)
+                            d[m][(t >> 1) & 1] = mfma_b3(a[m][t], a[m][t + 1], bh, bl, d[m][(t >> 1) & 1]);
+                    }
+                } else {
 #pragma unroll
-                        for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], bv[e], d[m][t & 1]);
+                    for (int t = 0; t < KP16; ++t) {
+                        const V4 bv = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                            for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], bv[e], d[m][t & 1]);
+                        }
                     }
                 }
                 T* pp = blk ? acc_ptr(col1_c) : p0;
@@ -803,25 +878,29 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     }
 }
 
-template <typename T, int KP16, int WAVES, int MBW>
+template <typename T, int KP16, int WAVES, int MBW, bool B3>
 hipError_t gg_launch_t(const GGParams& p, int blocks, size_t lds, hipStream_t st) {
-    static size_t attr_set = 0;
-    if (lds > 65536 && lds > attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES, MBW>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = lds;
+    if constexpr (B3 && (KP16 % 2 != 0 || sizeof(T) != 4)) {
+        return hipErrorInvalidValue;
+    } else {
+        static size_t attr_set = 0;
+        if (lds > 65536 && lds > attr_set) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES, MBW, B3>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+            attr_set = lds;
+        }
+        hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES, MBW, B3>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES, MBW>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
-    return hipGetLastError();
 }
 
-template <typename T, int WAVES, int MBW>
+template <typename T, int WAVES, int MBW, bool B3 = false>
 hipError_t gg_dispatch(int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st) {
     switch (KP16) {
 #define KIFMM_GG_CASE(K) \
     case K:              \
-        return gg_launch_t<T, K, WAVES, MBW>(p, blocks, lds, st);
+        return gg_launch_t<T, K, WAVES, MBW, B3>(p, blocks, lds, st);
         KIFMM_GG_CASE(1) KIFMM_GG_CASE(2) KIFMM_GG_CASE(3) KIFMM_GG_CASE(4) KIFMM_GG_CASE(5)
         KIFMM_GG_CASE(6) KIFMM_GG_CASE(7) KIFMM_GG_CASE(8) KIFMM_GG_CASE(9) KIFMM_GG_CASE(10)
         KIFMM_GG_CASE(11) KIFMM_GG_CASE(12) KIFMM_GG_CASE(13) KIFMM_GG_CASE(14) KIFMM_GG_CASE(15)
@@ -833,7 +912,20 @@ hipError_t gg_dispatch(int KP16, const GGParams& p, int blocks, size_t lds, hipS
 }
 
 template <typename T>
-hipError_t gg_variant(int variant, int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st) {
+hipError_t gg_variant(int variant, int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st,
+                      bool b3) {
+    if (b3) {
+        if constexpr (sizeof(T) == 4) {
+            switch (variant) {
+                case 0: return gg_dispatch<T, 8, 1, true>(KP16, p, blocks, lds, st);
+                case 1:
+                case 2: return gg_dispatch<T, 4, 1, true>(KP16, p, blocks, lds, st);
+                case 3: return gg_dispatch<T, 4, 2, true>(KP16, p, blocks, lds, st);
+                default: return hipErrorInvalidValue;
+            }
+        }
+        return hipErrorInvalidValue;
+    }
     switch (variant) {
         case 0: return gg_dispatch<T, 8, 1>(KP16, p, blocks, lds, st);
         case 1:
@@ -877,8 +969,10 @@ size_t gg_lds_bytes(int elt, int variant, int KP16, int cols) {
 }
 
 hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16, int a_rows, int a_cols,
-                     const void* X, int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st) {
+                     const void* X, int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st,
+                     bool b3) {
     if (s.n_tiles == 0) return hipSuccess;
+    if (b3 && (elt != 4 || KP16 % 2 != 0)) return hipErrorInvalidValue;
     if (a_rows < 1 || a_rows > MB * 16 || a_cols < 1 || a_cols > KP16 * 16) return hipErrorInvalidValue;
     GGParams p;
     p.A = A;
@@ -923,8 +1017,8 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
     if (lds > gg_lds_limit(s.variant) || KP16 < 1 || KP16 > 19) return hipErrorInvalidValue;
     p.xcd_run = GG_XCD_RUN;
     const int blocks = (s.n_tiles + 8 * p.xcd_run - 1) / (8 * p.xcd_run) * 8 * p.xcd_run * p.n_rg;
-    if (elt == 4) return gg_variant<float>(s.variant, KP16, p, blocks, lds, st);
-    return gg_variant<double>(s.variant, KP16, p, blocks, lds, st);
+    if (elt == 4) return gg_variant<float>(s.variant, KP16, p, blocks, lds, st, b3);
+    return gg_variant<double>(s.variant, KP16, p, blocks, lds, st, false);
 }
 
 #define KIFMM_R_SWITCH(R, BODY)                      \

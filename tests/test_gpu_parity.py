@@ -95,6 +95,24 @@ def test_fp32_svd_vs_dense_oracle_cube(p):
     assert e < 1e-5
 
 
+# ------------------------------------------------------------ split-BF16 M2L
+# Bound for the split-BF16 M2L: each product drops the lo*lo term and rounds
+# the low parts to BF16, a relative error of order 2^-16 ~ 1.5e-5 per product
+# entry; the M2L contribution is a fraction of the potential and the errors of
+# the 32-term BF16 sums are not aligned, so the matvec stays well inside 2e-5
+# (measured 3.4e-6 on this case, 3.3e-7 on the benchmark sphere).
+@pytest.mark.parametrize("p", [4, 6])
+def test_bf16x3_svd_vs_dense_oracle_cube(p):
+    x, s = cube()
+    want = oracle_phi("cube", 4096, p, 1e-6, 64, "dense")
+    got, plan = gpu_apply(x, s, p, 1e-6, 64, precision="bf16x3")
+    info = plan.info()
+    assert info["k_pad"] % 32 == 0
+    e = rel(got, want)
+    print(f"p={p} k={info['k']} bf16x3-svd vs fp64-dense oracle: {e:.3e}")
+    assert e < 2e-5
+
+
 def test_fp64_dense_gpu_vs_dense_oracle_cube_p6():
     # The uncompressed operators amplify rounding (pseudo-inverse of the
     # check-to-equivalent systems): only FP64 reaches the oracle's accuracy.
@@ -134,7 +152,7 @@ def test_full_size_sphere_sampled():
     g = json.load(open(GOLDEN))
     x, s = sphere(g["n"])
     idx = np.asarray(g["sample"])
-    for dense, prec, tol in ((False, "fp32", 1e-5), (True, "fp64", 1e-8)):
+    for dense, prec, tol in ((False, "fp32", 1e-5), (False, "bf16x3", 1e-5), (True, "fp64", 1e-8)):
         got, plan = gpu_apply(x, s, g["p"], g["eps"], g["leaf_size"], precision=prec, dense=dense)
         assert plan.info()["depth"] == g["depth"]
         e = rel(got[idx], g["phi_dense"])
