@@ -14,6 +14,9 @@
 #ifndef GG_XCD_RUN
 #define GG_XCD_RUN 1
 #endif
+#ifndef GG_GD
+#define GG_GD 2
+#endif
 #ifndef GG_LA
 #define GG_LA 2
 #endif
@@ -190,12 +193,12 @@ __device__ __forceinline__ double meta_scale<double>(int lo, int hi) {
 // holds up to 32 columns (two 16-column MFMA blocks, the second one only when
 // used) of one class. The chunk loop is a software pipeline; while the MFMAs of
 // chunk c run, the workgroup has in flight
-//   - the gathered source columns of chunks c+1 and c+2 (all threads, into two
+//   - the gathered source columns of chunks c+1 .. c+GD (all threads, into
 //     register sets; chunk c+1's are stored to the other LDS staging buffer
-//     after the MFMAs, so a gather has two chunks' time to arrive),
+//     after the MFMAs),
 //   - the A rows of chunk c+1 for each wave (second register set),
 //   - the target columns of chunk c+1, the metadata of chunk c+3 and the
-//     source rows of chunk c+4.
+//     source rows of chunk c+GD+2.
 // A value is first needed one iteration after the one that loads it (A rows,
 // target columns, source rows) or two (gathers, metadata).
 // Every load of the loop is a buffer load with a lane offset fixed for the
@@ -335,14 +338,20 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
 
     // pipeline state entering the iteration of chunk c: the class, block count
     // and scale of chunks c and c+1, the metadata word of chunk c+2 (loaded),
-    // the target columns of chunk c, the source rows of chunks c+2 and c+3 and
-    // the gathered columns of chunk c+1 (in flight)
+    // the target columns of chunk c, the source rows of chunks c+GD and
+    // c+GD+1 and the gathered columns of chunks c+1 .. c+GD-1 (in flight)
     int cls_c, nb_c, cls_n, nb_n, m_q;
     T sc_c, sc_n;
     int col0_c, col1_c;         // target columns of this lane in chunk c (blocks 0 and 1)
     int src_q[NLD];             // source rows of chunk c+2
     int src_q2[NLD];            // source rows of chunk c+3
-    V4 g0[NLD], g1[NLD];        // gathered columns, alternating by chunk parity
+    // gathered columns: GD = 2 chunks ahead in two register sets (chunk
+    // parity), or GD = 3 in four sets (chunk index mod 4; FP32 only, the FP64
+    // sets would not fit the registers)
+    constexpr int GD = sizeof(T) == 8 ? 2 : GG_GD;
+    static_assert(GD == 2 || GD == 3, "gather distance");
+    constexpr int FILL = GD == 2 ? 2 : 4;   // pipeline-fill iterations before chunk cb
+    V4 g0[NLD], g1[NLD], g2[GD == 3 ? NLD : 1], g3[GD == 3 ? NLD : 1];
     V4 a0[MBW][KP16];
     V4 a1[ADBL ? MBW : 1][KP16];
 
@@ -544,7 +553,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         }
     };
 
-    // The loop starts two chunks early, at c = cb-2: those two iterations
+    // The loop starts FILL chunks early, at c = cb-FILL: those iterations
     // only fill the pipeline (chunk indices are clamped into the tile, their
     // MFMAs are skipped), so every load of the loop is issued by the same code
     // in the same order, and the wait counts are the same on every iteration.
@@ -556,8 +565,8 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     nb_c = 0;
     sc_c = T(0);
     col0_c = col1_c = -1;
-    load_src(cb, src_q);
-    load_src(clampc(cb + 1), src_q2);
+    load_src(clampc(cb - FILL + GD), src_q);
+    load_src(clampc(cb - FILL + GD + 1), src_q2);
     // drain the prologue's loads (s_waitcnt vmcnt(0)), so that the wait
     // counts computed for the loop follow its steady state only
     __builtin_amdgcn_s_waitcnt(0x0F70);
@@ -589,7 +598,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
             }
             if (t == KP16 - 1) {
                 gather(go, src_q);
-                load_src(clampc(ch + 4), src4);
+                load_src(clampc(ch + GD + 2), src4);
                 m3 = load_meta(clampc(ch + 3));
                 tcol(clampc(ch + 1), n0, n1);
             }
@@ -620,18 +629,37 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         }
         __syncthreads();
     };
-    // both iterations of the unrolled pair always run (one past the last
-    // chunk when the count is odd; its MFMAs are skipped), so the loop has a
-    // single back edge and the wait counts stay exact
-    if constexpr (ADBL) {
-        for (int ch = cb - 2; ch < ce; ch += 2) {
-            step(ch, 0, a0, a1, g1, g0);
-            step(ch + 1, 1, a1, a0, g0, g1);
+    // all iterations of the unrolled group always run (up to three past the
+    // last chunk; their MFMAs are skipped), so the loop has a single back edge
+    // and the wait counts stay exact. Iteration ch stores the gathers of chunk
+    // ch+1 (set (ch+1-cb) mod 4) and issues those of chunk ch+GD.
+    if constexpr (GD == 2) {
+        if constexpr (ADBL) {
+            for (int ch = cb - FILL; ch < ce; ch += 2) {
+                step(ch, 0, a0, a1, g1, g0);
+                step(ch + 1, 1, a1, a0, g0, g1);
+            }
+        } else {
+            for (int ch = cb - FILL; ch < ce; ch += 2) {
+                step(ch, 0, a0, a0, g1, g0);
+                step(ch + 1, 1, a0, a0, g0, g1);
+            }
         }
     } else {
-        for (int ch = cb - 2; ch < ce; ch += 2) {
-            step(ch, 0, a0, a0, g1, g0);
-            step(ch + 1, 1, a0, a0, g0, g1);
+        if constexpr (ADBL) {
+            for (int ch = cb - FILL; ch < ce; ch += 4) {
+                step(ch, 0, a0, a1, g1, g3);
+                step(ch + 1, 1, a1, a0, g2, g0);
+                step(ch + 2, 0, a0, a1, g3, g1);
+                step(ch + 3, 1, a1, a0, g0, g2);
+            }
+        } else {
+            for (int ch = cb - FILL; ch < ce; ch += 4) {
+                step(ch, 0, a0, a0, g1, g3);
+                step(ch + 1, 1, a0, a0, g2, g0);
+                step(ch + 2, 0, a0, a0, g3, g1);
+                step(ch + 3, 1, a0, a0, g0, g2);
+            }
         }
     }
     for (int idx = tid; idx < ncol * rows; idx += NT) {
