@@ -337,14 +337,21 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     const int colb1 = 16 / R;   // pair index of the first column of block 1
 
     // pipeline state entering the iteration of chunk c: the class, block count
-    // and scale of chunks c and c+1, the metadata word of chunk c+2 (loaded),
-    // the target columns of chunk c, the source rows of chunks c+GD and
-    // c+GD+1 and the gathered columns of chunks c+1 .. c+GD-1 (in flight)
-    int cls_c, nb_c, cls_n, nb_n, m_q;
+    // and scale of chunks c and c+1 (scalars), the gathered columns of chunks
+    // c+1 .. c+GD-1 (in flight), and in two sets of registers by chunk parity
+    // (set (x - cb) & 1 for chunk x) the metadata words of chunks c+2 and c+3,
+    // the target columns of chunks c and c+1 and the source rows of chunks
+    // c+GD and c+GD+1. A loaded value stays in the register its load wrote
+    // until it is used: a register copy of a value still in flight would make
+    // the copy wait for it, and with it for every load issued before it.
+    struct Ring {
+        int src[NLD];   // source rows of a chunk
+        int meta;       // metadata word of a chunk (lanes 0..3)
+        int col0, col1; // target columns of this lane in a chunk (blocks 0 and 1)
+    };
+    Ring ring[2];
+    int cls_c, nb_c, cls_n, nb_n;
     T sc_c, sc_n;
-    int col0_c, col1_c;         // target columns of this lane in chunk c (blocks 0 and 1)
-    int src_q[NLD];             // source rows of chunk c+2
-    int src_q2[NLD];            // source rows of chunk c+3
     // gathered columns: GD = 2 chunks ahead in two register sets (chunk
     // parity), or GD = 3 in four sets (chunk index mod 4; FP32 only, the FP64
     // sets would not fit the registers)
@@ -422,12 +429,13 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         }
     };
 
-    // MFMAs of one chunk whose B operands sit in LDS buffer `buf`; for each of
-    // the wave's MBW row blocks and each 16-column block two accumulation
-    // chains over K (even and odd K-chunks)
     // MFMAs of one chunk whose B operands sit in LDS buffer `buf`: for each of
     // the wave's MBW row blocks and each 16-column block, two accumulation
-    // chains over K (even and odd K-chunks).
+    // chains over K (even and odd K-chunks). `on` (uniform) says whether the
+    // chunk is computed; hook(t) runs in every case, in one code path, so that
+    // the loads it issues write their registers directly (a load issued on
+    // two branches would need a register copy at the join, and the copy a
+    // wait for the load).
     //
     // PRE2 shapes issue their memory traffic inside the MFMA sequence, in
     // program order between fences (sched_barrier), so that the loads of all
@@ -437,11 +445,11 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     // this iteration's other loads). Other shapes call hook(t) for every t
     // before the MFMAs.
     constexpr int LA = GG_LA;
-    auto mfma_chunk = [&](int buf, const V4 (&a)[MBW][KP16], auto&& hook) {
+    auto mfma_chunk = [&](int buf, const V4 (&a)[MBW][KP16], const Ring& cur, bool on, auto&& hook) {
         const T* bcol = bbuf + (buf * 32 + j) * LDB + 4 * grp;
         const T scale = sc_c;
-        T* p0 = acc_ptr(col0_c);
-        if (PRE2 && nb_c > 1) {
+        const bool two = on && nb_c > 1;
+        if constexpr (PRE2) {
             V4 b0[KP16], b1[KP16];
 #pragma unroll
             for (int t = 0; t < LA && t < KP16; ++t) {
@@ -458,20 +466,34 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                 __builtin_amdgcn_sched_barrier(0);
                 if constexpr (B3) {
                     if (t & 1) {
+                        if (two) {
 #pragma unroll
-                        for (int m = 0; m < MBW; ++m) {
-                            d[m][(t >> 1) & 1] = mfma_b3(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][(t >> 1) & 1]);
-                            d[m][2 + ((t >> 1) & 1)] =
-                                mfma_b3(a[m][t - 1], a[m][t], b1[t - 1], b1[t], d[m][2 + ((t >> 1) & 1)]);
+                            for (int m = 0; m < MBW; ++m) {
+                                d[m][(t >> 1) & 1] = mfma_b3(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][(t >> 1) & 1]);
+                                d[m][2 + ((t >> 1) & 1)] =
+                                    mfma_b3(a[m][t - 1], a[m][t], b1[t - 1], b1[t], d[m][2 + ((t >> 1) & 1)]);
+                            }
+                        } else if (on) {
+#pragma unroll
+                            for (int m = 0; m < MBW; ++m)
+                                d[m][(t >> 1) & 1] = mfma_b3(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][(t >> 1) & 1]);
                         }
                     }
                 } else {
+                    if (two) {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
+                        for (int e = 0; e < 4; ++e) {
 #pragma unroll
-                        for (int m = 0; m < MBW; ++m) {
-                            d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
-                            d[m][2 + (t & 1)] = M::step(a[m][t][e], b1[t][e], d[m][2 + (t & 1)]);
+                            for (int m = 0; m < MBW; ++m) {
+                                d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
+                                d[m][2 + (t & 1)] = M::step(a[m][t][e], b1[t][e], d[m][2 + (t & 1)]);
+                            }
+                        }
+                    } else if (on) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                            for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
                         }
                     }
                 }
@@ -483,72 +505,48 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                 hook(t);
             }
             __builtin_amdgcn_sched_barrier(0);
-            T* p1 = acc_ptr(col1_c);
+            if (on) {
+                T* p0 = acc_ptr(cur.col0);
 #pragma unroll
-            for (int m = 0; m < MBW; ++m) {
-                acc_add(p0 + 16 * m, d[m][0], d[m][1], scale);
-                acc_add(p1 + 16 * m, d[m][2], d[m][3], scale);
+                for (int m = 0; m < MBW; ++m) acc_add(p0 + 16 * m, d[m][0], d[m][1], scale);
             }
-        } else if (PRE2) {
-            V4 b0[KP16];
+            if (two) {
+                T* p1 = acc_ptr(cur.col1);
 #pragma unroll
-            for (int t = 0; t < LA && t < KP16; ++t) b0[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
-            V4 d[MBW][2];
-#pragma unroll
-            for (int m = 0; m < MBW; ++m) d[m][0] = d[m][1] = V4{0, 0, 0, 0};
-#pragma unroll
-            for (int t = 0; t < KP16; ++t) {
-                __builtin_amdgcn_sched_barrier(0);
-                if constexpr (B3) {
-                    if (t & 1) {
-#pragma unroll
-                        for (int m = 0; m < MBW; ++m)
-                            d[m][(t >> 1) & 1] = mfma_b3(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][(t >> 1) & 1]);
-                    }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-#pragma unroll
-                        for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                if (t + LA < KP16) b0[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * (t + LA));
-                hook(t);
+                for (int m = 0; m < MBW; ++m) acc_add(p1 + 16 * m, d[m][2], d[m][3], scale);
             }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int m = 0; m < MBW; ++m) acc_add(p0 + 16 * m, d[m][0], d[m][1], scale);
         } else {
 #pragma unroll
             for (int t = 0; t < KP16; ++t) hook(t);
-            for (int blk = 0; blk < nb_c; ++blk) {
-                V4 d[MBW][2];
+            if (on) {
+                for (int blk = 0; blk < nb_c; ++blk) {
+                    V4 d[MBW][2];
 #pragma unroll
-                for (int m = 0; m < MBW; ++m) d[m][0] = d[m][1] = V4{0, 0, 0, 0};
-                if constexpr (B3) {
+                    for (int m = 0; m < MBW; ++m) d[m][0] = d[m][1] = V4{0, 0, 0, 0};
+                    if constexpr (B3) {
 #pragma unroll
-                    for (int t = 0; t < KP16; t += 2) {
-                        const V4 bh = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
-                        const V4 bl = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * (t + 1));
+                        for (int t = 0; t < KP16; t += 2) {
+                            const V4 bh = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
+                            const V4 bl = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * (t + 1));
 #pragma unroll
-                        for (int m = 0; m < MBW; ++m)
-                            d[m][(t >> 1) & 1] = mfma_b3(a[m][t], a[m][t + 1], bh, bl, d[m][(t >> 1) & 1]);
-                    }
-                } else {
+                            for (int m = 0; m < MBW; ++m)
+                                d[m][(t >> 1) & 1] = mfma_b3(a[m][t], a[m][t + 1], bh, bl, d[m][(t >> 1) & 1]);
+                        }
+                    } else {
 #pragma unroll
-                    for (int t = 0; t < KP16; ++t) {
-                        const V4 bv = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
+                        for (int t = 0; t < KP16; ++t) {
+                            const V4 bv = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
+                            for (int e = 0; e < 4; ++e) {
 #pragma unroll
-                            for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], bv[e], d[m][t & 1]);
+                                for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], bv[e], d[m][t & 1]);
+                            }
                         }
                     }
-                }
-                T* pp = blk ? acc_ptr(col1_c) : p0;
+                    T* pp = acc_ptr(blk ? cur.col1 : cur.col0);
 #pragma unroll
-                for (int m = 0; m < MBW; ++m) acc_add(pp + 16 * m, d[m][0], d[m][1], scale);
+                    for (int m = 0; m < MBW; ++m) acc_add(pp + 16 * m, d[m][0], d[m][1], scale);
+                }
             }
         }
     };
@@ -559,22 +557,25 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     // in the same order, and the wait counts are the same on every iteration.
     // A clamped chunk index past the last chunk only repeats valid loads.
     auto clampc = [&](int ch) { return min(max(ch, cb), ce - 1); };
+    static_assert(FILL % 2 == 0, "the first iteration has parity 0");
     unpack_meta(load_meta(cb), cls_n, nb_n, sc_n);
-    m_q = load_meta(cb);
+    ring[0].meta = load_meta(cb);
+    ring[1].meta = 0;
     cls_c = -1;
     nb_c = 0;
     sc_c = T(0);
-    col0_c = col1_c = -1;
-    load_src(clampc(cb - FILL + GD), src_q);
-    load_src(clampc(cb - FILL + GD + 1), src_q2);
+    ring[0].col0 = ring[0].col1 = ring[1].col0 = ring[1].col1 = -1;
+    load_src(clampc(cb - FILL + GD), ring[GD & 1].src);
+    load_src(clampc(cb - FILL + GD + 1), ring[(GD + 1) & 1].src);
     // drain the prologue's loads (s_waitcnt vmcnt(0)), so that the wait
     // counts computed for the loop follow its steady state only
     __builtin_amdgcn_s_waitcnt(0x0F70);
 
     // one iteration: chunk ch with its A rows in `a`; `an` receives chunk
     // ch+1's rows, `gi` holds chunk ch+1's gathered columns (in flight) and
-    // `go` receives chunk ch+2's
-    auto step = [&](int ch, int buf, V4 (&a)[MBW][KP16], V4 (&an)[MBW][KP16], V4 (&gi)[NLD], V4 (&go)[NLD]) {
+    // `go` receives chunk ch+GD's. `cur` is the ring set of chunk ch's parity.
+    auto step = [&](int ch, int buf, V4 (&a)[MBW][KP16], V4 (&an)[MBW][KP16], V4 (&gi)[NLD], V4 (&go)[NLD],
+                    Ring& cur, Ring& oth) {
         // Every iteration issues the same loads in the same order (the A rows
         // of the next chunk are loaded even when its class is unchanged; they
         // then come from L2): vmcnt retires loads in issue order, so with a
@@ -587,8 +588,9 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         // iterations later. So no wait ever retires a load of its own iteration
         // that it does not need, and waiting for the last A rows does not
         // retire the gathers.
-        int src4[NLD];
-        int m3, n0, n1;
+        // source rows of chunk ch+GD (used here), reloaded with those of
+        // chunk ch+GD+2 (same parity)
+        int (&sq)[NLD] = (GD % 2 == 0) ? cur.src : oth.src;
         auto hook = [&](int t) {
             if (ADBL) {
                 const uint32_t so = (uint32_t)cls_n * a_cls_bytes;
@@ -597,36 +599,23 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                     an[m][t] = bload4<T>(ra, t == KP16 - 1 ? aofl[m] : aoff[m] + 16 * t * (int)sizeof(T), so);
             }
             if (t == KP16 - 1) {
-                gather(go, src_q);
-                load_src(clampc(ch + GD + 2), src4);
-                m3 = load_meta(clampc(ch + 3));
-                tcol(clampc(ch + 1), n0, n1);
+                gather(go, sq);
+                load_src(clampc(ch + GD + 2), sq);
+                oth.meta = load_meta(clampc(ch + 3));
+                tcol(clampc(ch + 1), oth.col0, oth.col1);
             }
         };
         // with one staging buffer every chunk uses buffer 0, and the store of
         // the next chunk waits until all waves have read the current one
         const bool one = p.nbuf == 1;
-        if (wact && ch >= cb && ch < ce) {
-            mfma_chunk(one ? 0 : buf, a, hook);
-        } else {
-#pragma unroll
-            for (int t = 0; t < KP16; ++t) hook(t);
-        }
+        mfma_chunk(one ? 0 : buf, a, cur, wact && ch >= cb && ch < ce, hook);
         if (one) __syncthreads();
         stage_store(one ? 0 : buf ^ 1, gi);
         if (!ADBL && cls_n != cls_c) load_a(a, cls_n);
         cls_c = cls_n;
         nb_c = nb_n;
         sc_c = sc_n;
-        unpack_meta(m_q, cls_n, nb_n, sc_n);
-        m_q = m3;
-        col0_c = n0;
-        col1_c = n1;
-#pragma unroll
-        for (int i = 0; i < NLD; ++i) {
-            src_q[i] = src_q2[i];
-            src_q2[i] = src4[i];
-        }
+        unpack_meta(cur.meta, cls_n, nb_n, sc_n);   // chunk ch+2
         __syncthreads();
     };
     // all iterations of the unrolled group always run (up to three past the
@@ -636,29 +625,29 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     if constexpr (GD == 2) {
         if constexpr (ADBL) {
             for (int ch = cb - FILL; ch < ce; ch += 2) {
-                step(ch, 0, a0, a1, g1, g0);
-                step(ch + 1, 1, a1, a0, g0, g1);
+                step(ch, 0, a0, a1, g1, g0, ring[0], ring[1]);
+                step(ch + 1, 1, a1, a0, g0, g1, ring[1], ring[0]);
             }
         } else {
             for (int ch = cb - FILL; ch < ce; ch += 2) {
-                step(ch, 0, a0, a0, g1, g0);
-                step(ch + 1, 1, a0, a0, g0, g1);
+                step(ch, 0, a0, a0, g1, g0, ring[0], ring[1]);
+                step(ch + 1, 1, a0, a0, g0, g1, ring[1], ring[0]);
             }
         }
     } else {
         if constexpr (ADBL) {
             for (int ch = cb - FILL; ch < ce; ch += 4) {
-                step(ch, 0, a0, a1, g1, g3);
-                step(ch + 1, 1, a1, a0, g2, g0);
-                step(ch + 2, 0, a0, a1, g3, g1);
-                step(ch + 3, 1, a1, a0, g0, g2);
+                step(ch, 0, a0, a1, g1, g3, ring[0], ring[1]);
+                step(ch + 1, 1, a1, a0, g2, g0, ring[1], ring[0]);
+                step(ch + 2, 0, a0, a1, g3, g1, ring[0], ring[1]);
+                step(ch + 3, 1, a1, a0, g0, g2, ring[1], ring[0]);
             }
         } else {
             for (int ch = cb - FILL; ch < ce; ch += 4) {
-                step(ch, 0, a0, a0, g1, g3);
-                step(ch + 1, 1, a0, a0, g2, g0);
-                step(ch + 2, 0, a0, a0, g3, g1);
-                step(ch + 3, 1, a0, a0, g0, g2);
+                step(ch, 0, a0, a0, g1, g3, ring[0], ring[1]);
+                step(ch + 1, 1, a0, a0, g2, g0, ring[1], ring[0]);
+                step(ch + 2, 0, a0, a0, g3, g1, ring[0], ring[1]);
+                step(ch + 3, 1, a0, a0, g0, g2, ring[1], ring[0]);
             }
         }
     }
