@@ -359,8 +359,8 @@ int row_groups(int rows_pad, int variant) {
 }
 
 // M2L schedule over every box of levels 2..L (one contiguous target range);
-// tiles are cut at equal work (pairs + a per-target cost) into `n_tiles` tiles,
-// or uniformly into `tile` targets when tile > 0.
+// tiles are cut at equal estimated kernel cost (chunks, blocks, targets) into
+// at most `n_tiles` tiles, or uniformly into `tile` targets when tile > 0.
 GGSched build_m2l_sched(const kifmm_plan_s* pl, int variant, int n_tiles, int tile) {
     const HostTree& t = pl->tree;
     GGSched s;
@@ -377,8 +377,17 @@ GGSched build_m2l_sched(const kifmm_plan_s* pl, int variant, int n_tiles, int ti
         for (int64_t b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b) group[b - b0] = l - 2;
     }
     const int cap = max_tile_for(pl, variant, pl->kp);
+    // The loop of the kernel costs about the same per chunk whatever its fill,
+    // plus a share per 16-column block of MFMA work and a little per target
+    // (accumulator set-up and store); tiles of equal pair counts would differ
+    // by up to 2.3x in chunks (coarse levels have short class runs).
+    TileCost w;
+    w.per_chunk = 1.0;
+    w.per_block = 0.5;
+    w.per_target = 0.05;
     std::vector<int64_t> cuts = tile > 0 ? uniform_cuts(nb, std::min(tile, cap))
-                                         : balanced_cuts(nb, &t.v_ptr[b0], n_tiles, cap, 8.0);
+                                         : chunk_cuts(nb, &t.v_ptr[b0], t.v_cls.data(), group.data(), s.cp,
+                                                      pl->R, n_tiles, cap, w);
     gg_build(s, b0, nb, &t.v_ptr[b0], t.v_src.data(), t.v_cls.data(), group.data(), scale, cuts);
     return s;
 }

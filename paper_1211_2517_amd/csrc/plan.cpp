@@ -455,6 +455,84 @@ std::vector<int64_t> balanced_cuts(int64_t n_tgt, const int32_t* ptr, int n_tile
     return cuts;
 }
 
+std::vector<int64_t> chunk_cuts(int64_t n_tgt, const int32_t* ptr, const int32_t* cls, const int32_t* group,
+                                int cp, int rhs, int n_tiles, int max_tile, const TileCost& w) {
+    std::vector<int64_t> cuts{0};
+    if (n_tgt == 0) return cuts;
+    int n_groups = 1;
+    if (group)
+        for (int64_t t = 0; t < n_tgt; ++t) n_groups = std::max(n_groups, group[t] + 1);
+    const int cpb = std::max(1, 16 / std::max(1, rhs));   // pairs per 16-column block (rhs <= 16)
+    std::vector<int32_t> cnt((size_t)n_groups * NCLASS * 8, 0);
+    std::vector<int32_t> touched;
+    // cost of adding target t to the current tile (counts not yet updated)
+    auto delta = [&](int64_t t) {
+        double d = w.per_target;
+        const int64_t g = group ? group[t] : 0;
+        for (int32_t q = ptr[t]; q < ptr[t + 1]; ++q) {
+            const int32_t n = cnt[(size_t)(g * NCLASS * 8 + cls[q])];
+            if (n % cp == 0) d += w.per_chunk;
+            if (n % cpb == 0) d += w.per_block;
+        }
+        return d;
+    };
+    auto add = [&](int64_t t) {
+        const int64_t g = group ? group[t] : 0;
+        for (int32_t q = ptr[t]; q < ptr[t + 1]; ++q) {
+            int32_t& n = cnt[(size_t)(g * NCLASS * 8 + cls[q])];
+            if (n == 0) touched.push_back((int32_t)(g * NCLASS * 8 + cls[q]));
+            ++n;
+        }
+    };
+    auto reset = [&]() {
+        for (int32_t k : touched) cnt[(size_t)k] = 0;
+        touched.clear();
+    };
+    // greedy cut at cost threshold T: a tile closes before the target that
+    // would take it over T or past max_tile targets
+    auto greedy = [&](double T, std::vector<int64_t>* out) {
+        int64_t tiles = 1, start = 0;
+        double cost = 0.0;
+        reset();
+        for (int64_t t = 0; t < n_tgt; ++t) {
+            double d = delta(t);
+            if (t > start && (cost + d > T || t - start >= max_tile)) {
+                if (out) out->push_back(t);
+                ++tiles;
+                start = t;
+                cost = 0.0;
+                reset();
+                d = delta(t);
+            }
+            add(t);
+            cost += d;
+        }
+        reset();
+        return tiles;
+    };
+    // smallest threshold giving at most n_tiles tiles (bisection)
+    double hi = 0.0;
+    {
+        reset();
+        for (int64_t t = 0; t < n_tgt; ++t) {
+            hi += delta(t);
+            add(t);
+        }
+        reset();
+    }
+    double lo = 0.0;
+    for (int it = 0; it < 40 && hi - lo > 1e-3 * hi; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (greedy(mid, nullptr) <= std::max(1, n_tiles))
+            hi = mid;
+        else
+            lo = mid;
+    }
+    greedy(hi, &cuts);
+    cuts.push_back(n_tgt);
+    return cuts;
+}
+
 void gg_build(GGSched& s, int64_t tgt_row0, int64_t n_tgt, const int32_t* ptr, const int32_t* src,
               const int32_t* cls, const int32_t* group, const std::vector<double>& group_scale,
               const std::vector<int64_t>& cuts) {

@@ -106,4 +106,17 @@ std::vector<int64_t> uniform_cuts(int64_t n_tgt, int tile);
 std::vector<int64_t> balanced_cuts(int64_t n_tgt, const int32_t* ptr, int n_tiles, int max_tile,
                                    double per_target);
 
+// Estimated kernel cost of a tile: per chunk, per 16-column block and per
+// target (accumulator set-up and store).
+struct TileCost {
+    double per_chunk = 1.0;
+    double per_block = 0.0;
+    double per_target = 0.0;
+};
+// About `n_tiles` tiles of equal estimated cost, none larger than `max_tile`
+// targets; chunks and blocks are counted as gg_build forms them (`cp` pairs
+// per chunk, `rhs` columns per pair; classes are read as in gg_build).
+std::vector<int64_t> chunk_cuts(int64_t n_tgt, const int32_t* ptr, const int32_t* cls, const int32_t* group,
+                                int cp, int rhs, int n_tiles, int max_tile, const TileCost& w);
+
 }  // namespace kifmm
