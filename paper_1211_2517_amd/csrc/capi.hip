@@ -210,6 +210,36 @@ DevSched upload_sched(Uploader& up, const GGSched& s, int elt) {
     d.chunk_meta = (const int32_t*)up.put(meta);
     d.chunk_src = (const int32_t*)up.put(s.chunk_src);
     d.chunk_col = (const int32_t*)up.put(s.chunk_col);
+    // one pair for every target of every tile: the direct form of the kernel
+    int64_t lo = INT64_MAX, hi = 0;
+    for (int t = 0; t < d.n_tiles; ++t) {
+        lo = std::min<int64_t>(lo, s.tile_tgt0[t]);
+        hi = std::max<int64_t>(hi, (int64_t)s.tile_tgt0[t] + s.tile_ntgt[t]);
+    }
+    std::vector<int32_t> seen((size_t)(hi - lo), 0), tgt(s.chunk_col.size(), -1);
+    int64_t need = 0;
+    for (int t = 0; t < d.n_tiles; ++t) need += s.tile_ntgt[t];
+    int64_t got = 0;
+    bool direct = true;
+    for (int t = 0; t < d.n_tiles && direct; ++t) {
+        for (int c = s.tile_chunk0[t]; c < s.tile_chunk0[t + 1] && direct; ++c) {
+            for (int i = 0; i < s.cp; ++i) {
+                const int32_t col = s.chunk_col[(size_t)c * s.cp + i];
+                if (col < 0) continue;
+                const int64_t g = (int64_t)s.tile_tgt0[t] + col;
+                if (++seen[(size_t)(g - lo)] > 1) {
+                    direct = false;
+                    break;
+                }
+                tgt[(size_t)c * s.cp + i] = (int32_t)g;
+                ++got;
+            }
+        }
+    }
+    if (direct && got == need) {
+        d.direct = true;
+        d.chunk_tgt = (const int32_t*)up.put(tgt);
+    }
     return d;
 }
 

@@ -23,6 +23,11 @@ struct DevSched {
     const int32_t* chunk_meta = nullptr;
     const int32_t* chunk_src = nullptr;
     const int32_t* chunk_col = nullptr;
+    // every target of the schedule has exactly one pair: launch_gg runs one
+    // workgroup per chunk and writes the results directly (no LDS
+    // accumulator); chunk_tgt holds the target row of each chunk slot (-1 empty)
+    bool direct = false;
+    const int32_t* chunk_tgt = nullptr;
 };
 
 // Y[tgt] (+)= scale * sum_chunks A[cls] X[src] for every tile of `s`.

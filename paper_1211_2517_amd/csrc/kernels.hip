@@ -658,6 +658,113 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     }
 }
 
+// Grouped GEMM of a schedule in which every target has exactly one pair (the
+// leaf S~ and T~ products, L2L and, in the adjoint, the transposed M2M):
+// nothing is summed across chunks, so a workgroup computes one chunk for all
+// output rows and writes (or adds into) Y directly, without an accumulator in
+// LDS. The workgroups are small and run no pipeline; the loads of one are
+// hidden behind the MFMAs of the others on its CU.
+//
+// The workgroup stages the chunk's 32 source columns in LDS; wave w computes
+// the 16-row blocks w, w+4, ... of the output for the 16-column blocks that
+// hold data, with the A rows of a block in registers and the same K-permuted
+// operand layout as gg_kernel. Empty slots have no target and are not
+// written. Targets are distinct within and across chunks, so every output
+// element is written once by one lane.
+struct GDParams {
+    const void* A;
+    int64_t a_stride;
+    int lda;
+    const void* X;
+    int ldx;
+    void* Y;
+    int ldy;
+    int MB;
+    int R;
+    int cp;
+    int accumulate;
+    const int32_t* chunk_meta;
+    const int32_t* chunk_src;
+    const int32_t* chunk_tgt;   // per chunk slot: target row (box), -1 for an empty slot
+};
+
+template <typename T, int KP16>
+__global__ void __launch_bounds__(256) gd_kernel(GDParams p) {
+    using M = Mfma<T>;
+    using V4 = typename M::V4;
+    constexpr int KDIM = KP16 * 16;
+    constexpr int LDB = KDIM + 4;
+    constexpr int V4C = KDIM / 4;
+    constexpr int NSV = 32 * V4C;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* bb = reinterpret_cast<T*>(smem_raw);   // [32][LDB]
+    const int ch = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int j = lane & 15;
+    const int grp = lane >> 4;
+    const int R = p.R;
+    const int cp = p.cp;
+    const int cls = uload<int32_t>(p.chunk_meta, 4 * ch);
+    const int nblk = uload<int32_t>(p.chunk_meta, 4 * ch + 1);
+    const T scale = meta_scale<T>(uload<int32_t>(p.chunk_meta, 4 * ch + 2), uload<int32_t>(p.chunk_meta, 4 * ch + 3));
+    const T* __restrict__ X = static_cast<const T*>(p.X);
+    for (int f = tid; f < NSV; f += 256) {
+        const int c = f / V4C;
+        const int part = 4 * (f - c * V4C);
+        const int pr = c / R;
+        const int src = p.chunk_src[ch * cp + pr];
+        V4 v = V4{0, 0, 0, 0};
+        if (src >= 0) v = *reinterpret_cast<const V4*>(X + ((int64_t)src * R + (c - pr * R)) * p.ldx + part);
+        *reinterpret_cast<V4*>(bb + c * LDB + part) = v;
+    }
+    // output row (target row * R + right-hand side) of this lane's column in
+    // each 16-column block, -1 for an empty slot
+    int64_t orow[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int c = b * 16 + j;
+        const int pr = c / R;
+        const int tgt = p.chunk_tgt[ch * cp + pr];
+        orow[b] = tgt >= 0 ? (int64_t)tgt * R + (c - pr * R) : -1;
+    }
+    __syncthreads();
+    const T* __restrict__ A = static_cast<const T*>(p.A) + (int64_t)cls * p.a_stride;
+    T* __restrict__ Y = static_cast<T*>(p.Y);
+    for (int blk = wave; blk < p.MB; blk += 4) {
+        V4 a[KP16];
+        const T* ar = A + (int64_t)(blk * 16 + j) * p.lda + 4 * grp;
+#pragma unroll
+        for (int t = 0; t < KP16; ++t) a[t] = *reinterpret_cast<const V4*>(ar + 16 * t);
+        for (int cb = 0; cb < nblk; ++cb) {
+            V4 d0 = V4{0, 0, 0, 0}, d1 = V4{0, 0, 0, 0};
+            const T* bc = bb + (cb * 16 + j) * LDB + 4 * grp;
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) {
+                const V4 bv = *reinterpret_cast<const V4*>(bc + 16 * t);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (t & 1)
+                        d1 = M::step(a[t][e], bv[e], d1);
+                    else
+                        d0 = M::step(a[t][e], bv[e], d0);
+                }
+            }
+            const int64_t o = cb ? orow[1] : orow[0];
+            if (o >= 0) {
+                T* yp = Y + o * p.ldy + blk * 16;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int r = M::row(q, grp);
+                    const T v = scale * (d0[q] + d1[q]);
+                    yp[r] = p.accumulate ? yp[r] + v : v;
+                }
+            }
+        }
+    }
+}
+
 template <typename T, int R>
 __global__ void __launch_bounds__(256) permute_in_kernel(int64_t n, const int32_t* __restrict__ perm,
                                                          const T* __restrict__ sigma, int64_t ld,
@@ -895,6 +1002,35 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     }
 }
 
+template <typename T, int KP16>
+hipError_t gd_launch_t(const GDParams& p, int blocks, size_t lds, hipStream_t st) {
+    static size_t attr_set = 0;
+    if (lds > 65536 && lds > attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gd_kernel<T, KP16>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = lds;
+    }
+    hipLaunchKernelGGL((gd_kernel<T, KP16>), dim3(blocks), dim3(256), lds, st, p);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gd_dispatch(int KP16, const GDParams& p, int blocks, size_t lds, hipStream_t st) {
+    switch (KP16) {
+#define KIFMM_GD_CASE(K) \
+    case K:              \
+        return gd_launch_t<T, K>(p, blocks, lds, st);
+        KIFMM_GD_CASE(1) KIFMM_GD_CASE(2) KIFMM_GD_CASE(3) KIFMM_GD_CASE(4) KIFMM_GD_CASE(5)
+        KIFMM_GD_CASE(6) KIFMM_GD_CASE(7) KIFMM_GD_CASE(8) KIFMM_GD_CASE(9) KIFMM_GD_CASE(10)
+        KIFMM_GD_CASE(11) KIFMM_GD_CASE(12) KIFMM_GD_CASE(13) KIFMM_GD_CASE(14) KIFMM_GD_CASE(15)
+        KIFMM_GD_CASE(16) KIFMM_GD_CASE(17) KIFMM_GD_CASE(18) KIFMM_GD_CASE(19)
+#undef KIFMM_GD_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, int KP16, int WAVES, int MBW, bool B3>
 hipError_t gg_launch_t(const GGParams& p, int blocks, size_t lds, hipStream_t st) {
     if constexpr (B3 && (KP16 % 2 != 0 || sizeof(T) != 4)) {
@@ -991,6 +1127,28 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
     if (s.n_tiles == 0) return hipSuccess;
     if (b3 && (elt != 4 || KP16 % 2 != 0)) return hipErrorInvalidValue;
     if (a_rows < 1 || a_rows > MB * 16 || a_cols < 1 || a_cols > KP16 * 16) return hipErrorInvalidValue;
+    if (s.direct && !b3) {
+        // one pair per target: one workgroup per chunk, results written directly
+        if (KP16 < 1 || KP16 > 19 || s.cp * R != 32 || s.chunk_tgt == nullptr) return hipErrorInvalidValue;
+        GDParams g;
+        g.A = A;
+        g.a_stride = (int64_t)MB * 16 * KP16 * 16;
+        g.lda = KP16 * 16;
+        g.X = X;
+        g.ldx = ldx;
+        g.Y = Y;
+        g.ldy = ldy;
+        g.MB = MB;
+        g.R = R;
+        g.cp = s.cp;
+        g.accumulate = accumulate;
+        g.chunk_meta = s.chunk_meta;
+        g.chunk_src = s.chunk_src;
+        g.chunk_tgt = s.chunk_tgt;
+        const size_t lds = (size_t)32 * (KP16 * 16 + 4) * elt;
+        if (elt == 4) return gd_dispatch<float>(KP16, g, s.n_chunks, lds, st);
+        return gd_dispatch<double>(KP16, g, s.n_chunks, lds, st);
+    }
     GGParams p;
     p.A = A;
     p.a_stride = (int64_t)MB * 16 * KP16 * 16;
