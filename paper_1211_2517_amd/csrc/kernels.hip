@@ -11,11 +11,13 @@
 //                the leaf's points (L2T, Sec. 2.2), scattered to caller order.
 #include "kernels.h"
 
+#include <type_traits>
+
 #ifndef GG_XCD_RUN
 #define GG_XCD_RUN 1
 #endif
 #ifndef GG_GD
-#define GG_GD 2
+#define GG_GD 3
 #endif
 #ifndef GG_LA
 #define GG_LA 2
@@ -352,13 +354,15 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     Ring ring[2];
     int cls_c, nb_c, cls_n, nb_n;
     T sc_c, sc_n;
-    // gathered columns: GD = 2 chunks ahead in two register sets (chunk
-    // parity), or GD = 3 in four sets (chunk index mod 4; FP32 only, the FP64
-    // sets would not fit the registers)
-    constexpr int GD = sizeof(T) == 8 ? 2 : GG_GD;
-    static_assert(GD == 2 || GD == 3, "gather distance");
+    // gathered columns: GD = 3 or 4 chunks ahead in four register sets (chunk
+    // index mod 4) in the FP32 8-wave shape up to K = 224 (measured: 8% faster
+    // than GD = 2 there, slower in the 4-wave shapes, whose waves issue twice
+    // the gathers), else GD = 2 in two sets (chunk parity)
+    constexpr bool SETS4_FIT = sizeof(T) == 4 && WAVES == 8 && KP16 <= 14;
+    constexpr int GD = SETS4_FIT ? GG_GD : 2;
+    static_assert(GD >= 2 && GD <= 4, "gather distance");
     constexpr int FILL = GD == 2 ? 2 : 4;   // pipeline-fill iterations before chunk cb
-    V4 g0[NLD], g1[NLD], g2[GD == 3 ? NLD : 1], g3[GD == 3 ? NLD : 1];
+    V4 g0[NLD], g1[NLD], g2[GD > 2 ? NLD : 1], g3[GD > 2 ? NLD : 1];
     V4 a0[MBW][KP16];
     V4 a1[ADBL ? MBW : 1][KP16];
 
@@ -635,19 +639,40 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
             }
         }
     } else {
+        // four sets: chunk ch0 + i (ch0 the first chunk of an unrolled group)
+        // has its gathers in set i mod 4
+        auto gs = [&](auto idx) -> V4 (&)[NLD] {
+            constexpr int i = decltype(idx)::value % 4;
+            if constexpr (i == 0)
+                return g0;
+            else if constexpr (i == 1)
+                return g1;
+            else if constexpr (i == 2)
+                return g2;
+            else
+                return g3;
+        };
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        using I4 = std::integral_constant<int, 4>;
+        using G0 = std::integral_constant<int, GD>;
+        using G1 = std::integral_constant<int, GD + 1>;
+        using G2 = std::integral_constant<int, GD + 2>;
+        using G3 = std::integral_constant<int, GD + 3>;
         if constexpr (ADBL) {
             for (int ch = cb - FILL; ch < ce; ch += 4) {
-                step(ch, 0, a0, a1, g1, g3, ring[0], ring[1]);
-                step(ch + 1, 1, a1, a0, g2, g0, ring[1], ring[0]);
-                step(ch + 2, 0, a0, a1, g3, g1, ring[0], ring[1]);
-                step(ch + 3, 1, a1, a0, g0, g2, ring[1], ring[0]);
+                step(ch, 0, a0, a1, gs(I1{}), gs(G0{}), ring[0], ring[1]);
+                step(ch + 1, 1, a1, a0, gs(I2{}), gs(G1{}), ring[1], ring[0]);
+                step(ch + 2, 0, a0, a1, gs(I3{}), gs(G2{}), ring[0], ring[1]);
+                step(ch + 3, 1, a1, a0, gs(I4{}), gs(G3{}), ring[1], ring[0]);
             }
         } else {
             for (int ch = cb - FILL; ch < ce; ch += 4) {
-                step(ch, 0, a0, a0, g1, g3, ring[0], ring[1]);
-                step(ch + 1, 1, a0, a0, g2, g0, ring[1], ring[0]);
-                step(ch + 2, 0, a0, a0, g3, g1, ring[0], ring[1]);
-                step(ch + 3, 1, a0, a0, g0, g2, ring[1], ring[0]);
+                step(ch, 0, a0, a0, gs(I1{}), gs(G0{}), ring[0], ring[1]);
+                step(ch + 1, 1, a0, a0, gs(I2{}), gs(G1{}), ring[1], ring[0]);
+                step(ch + 2, 0, a0, a0, gs(I3{}), gs(G2{}), ring[0], ring[1]);
+                step(ch + 3, 1, a0, a0, gs(I4{}), gs(G3{}), ring[1], ring[0]);
             }
         }
     }
