@@ -889,7 +889,10 @@ __global__ void __launch_bounds__(256) eval_surface_kernel(int64_t n_leaf, const
 // as 4-vectors (x, y, z in target-leaf units, sigma for one right-hand side;
 // the sigmas of several right-hand sides sit in a second array), so each
 // interaction reads one broadcast LDS vector; batches of at most CAP points
-// are staged and consumed in turn. For the far field the wave stages the
+// are staged and consumed in turn. The near-field entries (at most 27 in a
+// uniform tree, at most 64 here) are resolved in parallel, one per lane, and
+// a prefix sum of their point counts numbers the staged points, so every
+// staged point is one independent load: a batch costs one memory latency. For the far field the wave stages the
 // leaf's downward equivalent surface as (x, y, z, E) vectors the same way
 // (one right-hand side), or reads E from global memory (several).
 template <typename T, int R, int MODE>
@@ -920,6 +923,25 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     const int q0 = near_ptr[leaf];
     const int q1 = near_ptr[leaf + 1];
     const bool far_on = (MODE & 2) && E != nullptr;
+    // near-field entries, one per lane: first point, point count, offset code,
+    // and the inclusive prefix sum of the counts (the entries' staged ranges)
+    int e_b0 = 0, e_cnt = 0, e_code = 13, e_incl = 0, n_near = 0;
+    if constexpr ((MODE & 1) != 0) {
+        const int nq = min(q1 - q0, 64);
+        if (lane < nq) {
+            const int nb = near_leaf[q0 + lane];
+            e_code = near_code[q0 + lane];
+            e_b0 = leaf_ptr[nb];
+            e_cnt = leaf_ptr[nb + 1] - e_b0;
+        }
+        e_incl = e_cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(e_incl, off);
+            if (lane >= off) e_incl += v;
+        }
+        n_near = __shfl(e_incl, 63);
+    }
     if constexpr ((MODE & 2) && R == 1) {
         if (far_on) {
             for (int a = lane; a < n_eq; a += 64)
@@ -952,36 +974,42 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
             }
             __builtin_amdgcn_wave_barrier();
         };
-        int n_st = 0;
-        for (int q = (MODE & 1) ? q0 : q1; q < q1; ++q) {
-            const int nb = near_leaf[q];
-            const int code = near_code[q];
-            // source shifted into target-leaf units: s - 2 d, d = target - source cube
-            const T shx = T(2 * (code / 9 - 1)), shy = T(2 * ((code / 3) % 3 - 1)), shz = T(2 * (code % 3 - 1));
-            const int b0 = leaf_ptr[nb];
-            const int c = leaf_ptr[nb + 1] - b0;
-            for (int base = 0; base < c; base += 64) {
-                const int cnt = min(64, c - base);
-                if (n_st + cnt > CAP) {
-                    consume(n_st);
-                    n_st = 0;
+        // stage and consume the near-field points in batches of CAP
+        for (int base = 0; base < n_near; base += CAP) {
+            const int cnt = min(CAP, n_near - base);
+#pragma unroll
+            for (int k = 0; k < CAP / 64; ++k) {
+                const int slot = k * 64 + lane;
+                const int sidx = base + slot;
+                // entry of staged point sidx: the number of entries whose
+                // range ends at or before it (binary search over the lanes)
+                int e = 0;
+#pragma unroll
+                for (int stp = 32; stp > 0; stp >>= 1) {
+                    const int v = __shfl(e_incl, e + stp - 1);
+                    if (v <= sidx) e += stp;
                 }
-                if (lane < cnt) {
-                    const int jj = b0 + base + lane;
+                e = min(e, 63);
+                const int b0 = __shfl(e_b0, e);
+                const int ex = __shfl(e_incl, e) - __shfl(e_cnt, e);
+                const int code = __shfl(e_code, e);
+                if (slot < cnt) {
+                    const int jj = b0 + (sidx - ex);
+                    // source shifted into target-leaf units: s - 2 d, d = target - source cube
+                    const T shx = T(2 * (code / 9 - 1)), shy = T(2 * ((code / 3) % 3 - 1)), shz = T(2 * (code % 3 - 1));
                     const P4<T> sv = pts[jj];
                     T w0 = T(0);
                     if constexpr (R == 1) {
                         w0 = sig[jj];
                     } else {
 #pragma unroll
-                        for (int r = 0; r < R; ++r) sst[(n_st + lane) * R + r] = sig[(int64_t)jj * R + r];
+                        for (int r = 0; r < R; ++r) sst[slot * R + r] = sig[(int64_t)jj * R + r];
                     }
-                    st[n_st + lane] = P4<T>{sv.x - shx, sv.y - shy, sv.z - shz, w0};
+                    st[slot] = P4<T>{sv.x - shx, sv.y - shy, sv.z - shz, w0};
                 }
-                n_st += cnt;
             }
+            consume(cnt);
         }
-        if (n_st > 0) consume(n_st);
         T far[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) far[r] = 0;
