@@ -34,7 +34,7 @@ def _sign(o01):
 def fmm(x: np.ndarray, sigma: np.ndarray, p: int, eps: float, leaf_size: int,
         mode: str = "dense", cd: float = 0.5, rcond: float = 1e-10,
         depth: int | None = None, max_depth: int = 16, sample: np.ndarray | None = None,
-        ops=None, tree=None):
+        ops=None, tree=None, c2: float = 0.0):
     """Potential phi (N,) or (N,m) at every point (or at `sample` indices).
 
     Returns (phi, info) where info holds the tree and the operators.
@@ -48,7 +48,7 @@ def fmm(x: np.ndarray, sigma: np.ndarray, p: int, eps: float, leaf_size: int,
     if tree is None:
         tree = build_tree(x, leaf_size, depth=depth, max_depth=max_depth)
     if ops is None:
-        ops = build_operators(p, eps, leaf_size, mode=mode, cd=cd, rcond=rcond)
+        ops = build_operators(p, eps, leaf_size, mode=mode, cd=cd, rcond=rcond, c2=c2)
     L = tree.depth
 
     # ---- Step 2: upward pass -------------------------------------------------
@@ -91,7 +91,11 @@ def fmm(x: np.ndarray, sigma: np.ndarray, p: int, eps: float, leaf_size: int,
                 acc += ops.L[_sign(o)] @ down[level - 1][parent]
             for c in tree.interaction(level, b):                       # M2L, Sec. 2.2
                 t = (b[0] - c[0], b[1] - c[1], b[2] - c[2])
-                acc += (ops.K[t] @ up[level][c]) / r
+                if ops.K2 is not None:                                  # stage 2, Sec. 3.2
+                    Uh, Vh = ops.K2[t]
+                    acc += (Uh @ (Vh @ up[level][c])) / r
+                else:
+                    acc += (ops.K[t] @ up[level][c]) / r
             down[level][b] = acc
 
     # ---- L2T (Sec. 2.2) and Step 4 S2T ----------------------------------------

@@ -29,6 +29,14 @@ in Sec. 3.1). Then K~ = U~^T K U~ and, from Sec. 3.3, S~ = U~^T S,
 M~ = U~^T M U~, L~ = U~^T L U~, T~ = T U~ (the printed "T~ = T~ U~" is read as
 T~ = T U~).
 
+Stage-2 low rank (Sec. 3.2, mode "svd2"): each compressed M2L matrix is
+factored by its own SVD, K~^(t) = U S Q^T, and the singular values below
+eps2 * ||K_fat||_2 are dropped, eps2 = C2 * eps / k (eq. for eps2 in Sec. 3.2,
+with eps the stage-1 threshold and k the compressed dimension). M2L then applies
+U^ (V^ q) with V^ = S^ Q^^T: two thin products of rank r_t instead of one k x k
+product. The 2-norm error of each factored matrix is the first dropped singular
+value, at most eps2 * ||K_fat||_2.
+
 The pseudo-inverse is a truncated SVD with relative cutoff `rcond` (the paper
 does not say how the check-to-equivalent systems are solved).
 """
@@ -85,11 +93,30 @@ class Operators:
     sing: np.ndarray | None = None   # singular values of K_fat (svd mode)
     U: np.ndarray | None = None      # U~ (n_eq, k) (svd mode)
     K_full: dict | None = None       # uncompressed K^(t) (svd mode keeps them for checks)
+    K2: dict | None = None           # svd2 mode: offset t -> (U^ (k, r_t), V^ (r_t, k))
+    eps2: float | None = None        # svd2 mode: absolute stage-2 cutoff eps2 * ||K_fat||_2
+
+
+def stage2_factors(K: dict, sigma0: float, eps: float, k: int, c2: float):
+    """Per-class low-rank factors of the compressed M2L matrices (Sec. 3.2).
+
+    Returns ({t: (U^, V^)}, cutoff) with cutoff = C2 * eps / k * sigma0, keeping
+    the singular values not below the cutoff (V^ = S^ Q^^T).
+    """
+    cut = c2 * eps / k * sigma0
+    out = {}
+    for t, Kt in K.items():
+        U, S, Qt = np.linalg.svd(Kt)
+        r = int(np.count_nonzero(S >= cut))
+        out[t] = (U[:, :r], S[:r, None] * Qt[:r, :])
+    return out, cut
 
 
 def build_operators(p: int, eps: float, leaf_size: int, mode: str = "dense",
-                    cd: float = 0.5, rcond: float = 1e-10) -> Operators:
-    if mode not in ("dense", "svd"):
+                    cd: float = 0.5, rcond: float = 1e-10, c2: float = 0.0) -> Operators:
+    """Operators of `mode`: "dense" (uncompressed), "svd" (stage 1, Sec. 3.1 and
+    3.3) or "svd2" (stage 1 plus the stage-2 factors of Sec. 3.2 with constant c2)."""
+    if mode not in ("dense", "svd", "svd2"):
         raise ValueError(mode)
     E = surface_template(p)
     n = E.shape[0]
@@ -109,11 +136,13 @@ def build_operators(p: int, eps: float, leaf_size: int, mode: str = "dense",
     U, sing, _ = np.linalg.svd(K_fat, full_matrices=False)
     k = int(np.count_nonzero(sing >= eps * sing[0]))
     Ut = U[:, :k]
+    Kc = {t: Ut.T @ K[t] @ Ut for t in K}
+    K2, cut = stage2_factors(Kc, sing[0], eps, k, c2) if mode == "svd2" else (None, None)
     return Operators(
         p=p, n_eq=n, d=d, rcond=rcond, mode=mode, k=k, UE=UE, UC=UC, DC=DC, DE=DE,
         S=Ut.T @ P_up,
         M={o: Ut.T @ M[o] @ Ut for o in CHILD_SIGNS},
-        K={t: Ut.T @ K[t] @ Ut for t in K},
+        K=Kc,
         L={o: Ut.T @ L[o] @ Ut for o in CHILD_SIGNS},
         T=P_dn @ Ut,
-        sing=sing, U=Ut, K_full=K)
+        sing=sing, U=Ut, K_full=K, K2=K2, eps2=cut)

@@ -286,3 +286,67 @@ def test_fmm_multiple_rhs_columns():
     for j in range(3):
         one, _ = fmm(x, Q[:, j], 4, 1e-6, 32, ops=ops, tree=info["tree"])
         assert np.allclose(both[:, j], one, rtol=1e-13, atol=1e-13)
+
+
+# ---------------------------------------------------------------- stage 2 (Sec. 3.2)
+@functools.lru_cache(maxsize=None)
+def ops2_cached(p, eps, leaf, c2):
+    return build_operators(p, eps, leaf, mode="svd2", c2=c2)
+
+
+@pytest.mark.parametrize("p,eps,c2", [(4, 1e-6, 10.0), (6, 1e-6, 10.0), (6, 1e-6, 100.0)])
+def test_stage2_truncation_bound(p, eps, c2):
+    # Sec. 3.2: dropping the singular values below eps2 ||K_fat||_2 leaves
+    # ||K^ - K~||_2 <= eps2 ||K_fat||_2 per class, eps2 = C2 eps / k, with
+    # ||K_fat||_2 computed here from the uncompressed matrices.
+    ops = ops2_cached(p, eps, 64, c2)
+    k = ops.k
+    sigma0 = np.linalg.norm(np.concatenate([ops.K_full[t] for t in offset_classes()], axis=1), 2)
+    cut = c2 * eps / k * sigma0
+    worst = 0.0
+    for t, (Uh, Vh) in ops.K2.items():
+        assert Uh.shape[1] == Vh.shape[0] <= k
+        assert np.allclose(Uh.T @ Uh, np.eye(Uh.shape[1]), atol=1e-12)
+        worst = max(worst, np.linalg.norm(ops.K[t] - Uh @ Vh, 2) / cut)
+    assert worst <= 1 + 1e-9
+    assert worst >= 0.5   # the cutoff binds for some class
+
+
+def test_stage2_ranks_well_below_k():
+    # Sec. 3.2 and Fig. 1: most compressed M2L matrices have numerical ranks much
+    # lower than the compressed dimension.
+    ops = ops2_cached(6, 1e-6, 64, 10.0)
+    ranks = np.array([Uh.shape[1] for Uh, _ in ops.K2.values()])
+    assert ranks.max() < ops.k and ranks.mean() < ops.k / 3
+
+
+def test_stage2_transpose_classes():
+    # K~^(-t) = K~^(t)^T (R11) has the same singular values, so the factored
+    # matrices keep the symmetry: K^^(-t) = K^^(t)^T.
+    ops = ops2_cached(6, 1e-6, 64, 10.0)
+    for t, (Uh, Vh) in ops.K2.items():
+        U2, V2 = ops.K2[(-t[0], -t[1], -t[2])]
+        a, b = Uh @ Vh, (U2 @ V2).T
+        assert np.linalg.norm(a - b, 2) <= 1e-10 * np.linalg.norm(a, 2)
+
+
+def test_stage2_c2_zero_is_stage1():
+    # eps2 = 0 keeps every singular value: the factors multiply back to K~.
+    x, q, _ = _cube4096()
+    a, _ = fmm(x, q, 4, 1e-6, 64, mode="svd")
+    b, _ = fmm(x, q, 4, 1e-6, 64, mode="svd2", c2=0.0)
+    assert rel(b, a) < 1e-13
+
+
+def test_stage2_error_grows_with_c2_and_stays_small():
+    # Sec. 3.2 sets eps2 so that the added error is of the order of eps; larger
+    # C2 drops more singular values (Table 1 and 2 trends).
+    x, q, _ = _cube4096()
+    dense, _ = fmm(x, q, 6, 1e-6, 64, mode="dense")
+    svd, _ = fmm(x, q, 6, 1e-6, 64, mode="svd")
+    errs = []
+    for c2 in (1.0, 10.0, 100.0):
+        v, _ = fmm(x, q, 6, 1e-6, 64, ops=ops2_cached(6, 1e-6, 64, c2))
+        errs.append(rel(v, svd))
+        assert rel(v, dense) < 5e-6
+    assert errs[0] < errs[1] < errs[2]

@@ -73,3 +73,34 @@ def test_planted_mistake_is_caught(mutate):
     ops = copy.copy(_setup()[3])
     mutate(ops)
     assert _err(ops) > BOUND
+
+
+# stage-2 factors (Sec. 3.2): planted mistakes in the factored M2L matrices
+@functools.lru_cache(maxsize=None)
+def _setup2():
+    return build_operators(P, EPS, LEAF, mode="svd2", c2=10.0)
+
+
+def test_stage2_unmutated_meets_bound():
+    assert _err(_setup2()) < BOUND
+
+
+def _k2_unscaled(o):
+    # V^ without the singular values (Q^^T instead of S^ Q^^T)
+    o.K2 = {t: (U, V / np.linalg.norm(V, axis=1, keepdims=True)) for t, (U, V) in o.K2.items()}
+
+
+def _k2_transposed_factors(o):
+    # the class of -t (the transposed matrix) applied for t
+    o.K2 = {t: o.K2[(-t[0], -t[1], -t[2])] for t in o.K2}
+
+
+def _k2_rank_one(o):
+    o.K2 = {t: (U[:, :1], V[:1]) for t, (U, V) in o.K2.items()}
+
+
+@pytest.mark.parametrize("mutate", [_k2_unscaled, _k2_transposed_factors, _k2_rank_one])
+def test_stage2_planted_mistake_is_caught(mutate):
+    ops = copy.copy(_setup2())
+    mutate(ops)
+    assert _err(ops) > BOUND
