@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "KIFMM matvec ms + M2L MFMA util at N=1M p=6: SVD-M2L vs dense-M2L, same acc"
 PEAK_FP32_MFMA_TFLOPS = 157.3
 N, P, EPS, LEAF = 1 << 20, 6, 1e-6, 64
+STAGE2_C2 = 10.0   # C2 of the stage-2 plan (Sec. 3.2; the paper uses 10 and 100)
 
 
 def log(msg):
@@ -97,7 +98,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["svd", "dense64", "dense32", "svd_bf16x3"], default=None,
+    ap.add_argument("--only", choices=["svd", "dense64", "dense32", "svd_bf16x3", "svd_stage2"], default=None,
                     help="time one plan only (profiling runs); prints no JSON line")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MB (a kernel of known "
@@ -140,12 +141,15 @@ def main():
     # in FP32 (same precision as svd; its rounding error is reported, it does
     # not reach the accuracy because the uncompressed translations amplify it).
     # svd_bf16x3: the compressed path with the split-BF16 M2L (precision mode).
-    for name, dense, prec in (("svd", False, "fp32"), ("dense64", True, "fp64"), ("dense32", True, "fp32"),
-                              ("svd_bf16x3", False, "bf16x3")):
+    # svd_stage2: the compressed path with the stage-2 low-rank M2L factors
+    # (Sec. 3.2, C2 = 10), FP32.
+    for name, dense, prec, c2 in (("svd", False, "fp32", 0.0), ("dense64", True, "fp64", 0.0),
+                                  ("dense32", True, "fp32", 0.0), ("svd_bf16x3", False, "bf16x3", 0.0),
+                                  ("svd_stage2", False, "fp32", STAGE2_C2)):
         if args.only and name != args.only:
             continue
         log(f"plan {name}")
-        plan = K.Plan(x, p=P, eps=EPS, leaf_size=LEAF, precision=prec, dense_m2l=dense)
+        plan = K.Plan(x, p=P, eps=EPS, leaf_size=LEAF, precision=prec, dense_m2l=dense, c2=c2)
         if prec == "fp64":
             sd_run = sd.double()
             out_run = torch.empty_like(sd_run)
@@ -167,6 +171,16 @@ def main():
     if args.only:
         return
     svd = res["svd"]
+
+    def stage2_record(r):
+        i = r["info"]
+        m2l = r["stages"]["m2l"]
+        return {"c2": STAGE2_C2, "ms_per_step": round(r["ms"], 4), "err_vs_fp64_dense_oracle": r["err"],
+                "rank_mean": round(i["m2l_rank_mean"], 2), "rank_max": i["m2l_rank_max"],
+                "m2l_ms": round(m2l, 4), "m2l_flops": i["flops"]["m2l"],
+                "m2l_tflops": round(i["flops"]["m2l"] / (m2l * 1e-3) / 1e12, 3),
+                "m2l_speedup_vs_stage1": round(svd["stages"]["m2l"] / m2l, 3),
+                "stage_ms": {k: round(v, 4) for k, v in r["stages"].items()}}
     info = svd["info"]
     m2l_ms = svd["stages"]["m2l"]
     achieved = info["flops"]["m2l"] / (m2l_ms * 1e-3) / 1e12
@@ -201,6 +215,7 @@ def main():
         "svd_bf16x3": {"ms_per_step": round(res["svd_bf16x3"]["ms"], 4),
                        "err_vs_fp64_dense_oracle": res["svd_bf16x3"]["err"],
                        "m2l_ms": round(res["svd_bf16x3"]["stages"]["m2l"], 4)},
+        "svd_stage2": stage2_record(res["svd_stage2"]),
         "m2l_mfma_util": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
         "stage_ms": {k: round(v, 4) for k, v in svd["stages"].items()},
         "err_vs_fp64_dense_oracle": svd["err"],

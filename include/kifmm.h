@@ -79,6 +79,12 @@ typedef struct {
                            (default), 0..3 forces one shape (the tile count is still tuned
                            unless tile_targets > 0); KIFMM_EINVAL if the shape does not
                            exist in the requested precision */
+    double c2;          /* stage-2 low rank of the compressed M2L matrices (Sec. 3.2): each
+                           K~^(t) is replaced by U^ V^ from its SVD, keeping the singular
+                           values >= eps2 * Sigma_00 with eps2 = c2 * eps / k (the paper's
+                           eps2 = C2 eps1 / k); M2L then runs as two thin products per pair
+                           (w = V^ q into a per-pair buffer, then p += U^ w). 0 = off
+                           (default). KIFMM_EINVAL with dense_m2l or KIFMM_BF16X3 */
 } kifmm_opts_t;
 
 /* Per-stage counters; index with the KIFMM_STAGE_* values. */
@@ -113,6 +119,8 @@ typedef struct {
                                1 = 4 waves x 16 rows, 2 = 4 waves x 16 rows at two workgroups per CU,
                                3 = 4 waves x 32 rows (FP32 only) */
     int m2l_tiles;          /* M2L target tiles (workgroups = tiles x row groups) */
+    int m2l_rank_max;       /* stage 2: largest rank of the factored M2L matrices, else 0 */
+    double m2l_rank_mean;   /* stage 2: mean rank over the 316 classes, else 0 */
 } kifmm_info_t;
 
 /* Fill `o` with the defaults listed above. Returns KIFMM_EINVAL if o is NULL. */
@@ -173,6 +181,10 @@ int kifmm_plan_export_tree(kifmm_plan_t plan, int32_t* leaf_coords);
  *   4 M~^o (8 x k x k; o = 4*ox + 2*oy + oz, child position bits)
  *   5 L~^o (8 x k x k)    6 K~^(t) (316 x k x k; t in lexicographic order over
  *                            [-3,3]^3 with max|t_a| >= 2)
+ *   stage-2 plans only (opts.c2 > 0; KIFMM_EINVAL otherwise), r = info.m2l_rank_max:
+ *   7 ranks of the 316 classes (as doubles)
+ *   8 U^ (316 x k x r, zero past each class's rank)
+ *   9 V^ = S^ Q^^T (316 x r x k, zero past each class's rank)
  * `out` must hold the number of doubles stated; `count` (may be NULL) receives it. */
 int kifmm_plan_export_operator(kifmm_plan_t plan, int which, double* out, int64_t* count);
 

@@ -42,7 +42,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cd", ctypes.c_double), ("pinv_rcond", ctypes.c_double),
                 ("depth", ctypes.c_int), ("max_depth", ctypes.c_int), ("dense_m2l", ctypes.c_int),
                 ("max_nrhs", ctypes.c_int), ("device", ctypes.c_int), ("mem_limit", ctypes.c_size_t),
-                ("tile_targets", ctypes.c_int), ("m2l_shape", ctypes.c_int)]
+                ("tile_targets", ctypes.c_int), ("m2l_shape", ctypes.c_int), ("c2", ctypes.c_double)]
 
 
 class _Info(ctypes.Structure):
@@ -54,7 +54,8 @@ class _Info(ctypes.Structure):
                 ("r0", ctypes.c_double), ("flops", ctypes.c_double * 7), ("bytes", ctypes.c_double * 7),
                 ("device_bytes", ctypes.c_size_t), ("m2l_tile_targets", ctypes.c_int),
                 ("sigma0", ctypes.c_double), ("plan_seconds", ctypes.c_double),
-                ("m2l_variant", ctypes.c_int), ("m2l_tiles", ctypes.c_int)]
+                ("m2l_variant", ctypes.c_int), ("m2l_tiles", ctypes.c_int),
+                ("m2l_rank_max", ctypes.c_int), ("m2l_rank_mean", ctypes.c_double)]
 
 
 _LIB = None
@@ -115,7 +116,7 @@ class Plan:
     def __init__(self, points, p: int = 6, eps: float = 1e-6, leaf_size: int = 64, *,
                  precision: str = "fp32", dense_m2l: bool = False, max_nrhs: int = 1, device: int = 0,
                  depth: int = 0, max_depth: int = 16, cd: float = 0.5, pinv_rcond: float = 1e-10,
-                 mem_limit: int = 0, tile_targets: int = 0, m2l_shape: int = -1):
+                 mem_limit: int = 0, tile_targets: int = 0, m2l_shape: int = -1, c2: float = 0.0):
         lib = load_library()
         pts = np.ascontiguousarray(np.asarray(points.cpu().numpy() if hasattr(points, "cpu") else points,
                                               dtype=np.float64))
@@ -134,6 +135,7 @@ class Plan:
         o.mem_limit = int(mem_limit)
         o.tile_targets = int(tile_targets)
         o.m2l_shape = int(m2l_shape)
+        o.c2 = float(c2)
         h = ctypes.c_void_p()
         _check(lib.kifmm_plan_ex(pts.ctypes.data, pts.shape[0], int(p), float(eps), int(leaf_size),
                                  ctypes.byref(o), ctypes.byref(h)))

@@ -47,6 +47,8 @@ struct kifmm_plan_s {
     HostOps ops;
     int k = 0, kp = 0, nep = 0, R = 1, elt = 4;
     bool b3 = false;    // M2L in split BF16 (KIFMM_BF16X3); all other stages FP32
+    bool st2 = false;   // stage-2 low-rank M2L (opts.c2 > 0)
+    int rp = 0;         // stage-2 rank padded to 16
     bool on_device = false;
     int device = 0;
     int num_cu = 256;   // compute units of the device (MI355X: 256)
@@ -56,6 +58,7 @@ struct kifmm_plan_s {
     std::vector<GGSched> h_up, h_down;   // indexed by target level
     // device schedules
     DevSched d_leafup, d_leafdown, d_m2l;
+    DevSched d_s2a, d_s2b;   // stage-2 M2L: w = V^ q per chunk slot, then p += scale U^ w
     std::vector<DevSched> d_up, d_down;
     // device data
     void* pts = nullptr;
@@ -67,6 +70,8 @@ struct kifmm_plan_s {
     int32_t* near_code = nullptr;
     void *Kt = nullptr, *KtT = nullptr, *Mt = nullptr, *MtT = nullptr, *Lt = nullptr, *LtT = nullptr;
     void *Sop = nullptr, *SopT = nullptr, *Top = nullptr, *TopT = nullptr;
+    void *V2t = nullptr, *U2t = nullptr, *U2tT = nullptr, *V2tT = nullptr;   // stage-2 factors
+    void* W = nullptr;   // stage-2 per-slot products w = V^ q (n_chunks x 32 rows of rp)
     void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
     std::vector<void*> allocs;
     size_t device_bytes = 0;
@@ -307,6 +312,18 @@ int upload_tables(kifmm_plan_s* pl, Uploader& up) {
     pl->SopT = up.put(pad_blocks<T>(1, ne, k, nep, kp, [&](int, int a, int i) { return o.S[(size_t)i * ne + a]; }));
     pl->Top = up.put(pad_blocks<T>(1, ne, k, nep, kp, [&](int, int a, int i) { return o.T[(size_t)a * k + i]; }));
     pl->TopT = up.put(pad_blocks<T>(1, k, ne, kp, nep, [&](int, int i, int a) { return o.T[(size_t)a * k + i]; }));
+    if (pl->st2) {
+        // stage-2 factors (Sec. 3.2), zero-padded to rp: phase A multiplies by V^
+        // (rp x kp per class), phase B by U^ (kp x rp); the adjoint applies the
+        // class -t transposed: U^(-t)^T in phase A and V^(-t)^T in phase B
+        const int rm = o.r2max, rp = pl->rp;
+        auto U2 = [&](int c, int i, int j) { return j < rm ? o.U2[((size_t)c * k + i) * rm + j] : 0.0; };
+        auto V2 = [&](int c, int j, int i) { return j < rm ? o.V2[((size_t)c * rm + j) * k + i] : 0.0; };
+        pl->V2t = up.put(pad_blocks<T>(NCLASS, rm, k, rp, kp, V2));
+        pl->U2t = up.put(pad_blocks<T>(NCLASS, k, rm, kp, rp, U2));
+        pl->U2tT = up.put(pad_blocks<T>(NCLASS, rm, k, rp, kp, [&](int c, int j, int i) { return U2(neg_class(c), i, j); }));
+        pl->V2tT = up.put(pad_blocks<T>(NCLASS, k, rm, kp, rp, [&](int c, int i, int j) { return V2(neg_class(c), j, i); }));
+    }
     std::vector<T> surf(3 * ne);
     for (int i = 0; i < 3 * ne; ++i) surf[i] = (T)o.outer[i];
     pl->surf = up.put(surf);
@@ -315,6 +332,56 @@ int upload_tables(kifmm_plan_s* pl, Uploader& up) {
         for (int a = 0; a < 3; ++a) pts[4 * i + a] = (T)pl->tree.u[3 * i + a];
     pl->pts = up.put(pts);
     return up.err;
+}
+
+// Device schedules and buffer of the stage-2 M2L (Sec. 3.2), from the M2L
+// schedule (same tiles and chunks): phase A writes w = V^ q of every pair into
+// its own chunk slot (direct form: one output row per slot), phase B adds
+// scale * U^ w into the targets. Word 1 of the chunk metadata carries, above
+// the block count, the 16-blocks of the class's rank (phase A: rows of V^;
+// phase B: K-chunks of U^); the rank of a class and of its negation are
+// equal up to rounding at the cutoff, and the larger one is used for both.
+void upload_stage2(kifmm_plan_s* pl, Uploader& up) {
+    const GGSched& s = pl->h_m2l;
+    const int nch = s.n_chunks();
+    if (nch == 0) return;
+    const HostOps& o = pl->ops;
+    const int64_t wbytes = (int64_t)nch * 32 * pl->rp * pl->elt;
+    if (wbytes >= ((int64_t)1 << 31)) {
+        up.err = KIFMM_EINVAL;
+        up.msg = "stage-2 product buffer exceeds 2 GiB (" + std::to_string(wbytes) + " bytes): use c2 = 0";
+        return;
+    }
+    DevSched a = upload_sched(up, s, pl->elt);
+    if (up.err != KIFMM_OK) return;
+    std::vector<int32_t> meta((size_t)4 * nch, 0), slot(s.chunk_src.size(), -1);
+    for (int c = 0; c < nch; ++c) {
+        const int cls = s.chunk_cls[c];
+        const int rb = (std::max(o.rank2[cls], o.rank2[neg_class(cls)]) + 15) / 16;
+        meta[4 * c] = cls;
+        meta[4 * c + 1] = s.chunk_nblk[c] | (rb << 8);
+        if (pl->elt == 4) {
+            const float f = (float)s.chunk_scale[c];
+            std::memcpy(&meta[4 * c + 2], &f, sizeof f);
+        } else {
+            std::memcpy(&meta[4 * c + 2], &s.chunk_scale[c], sizeof(double));
+        }
+    }
+    for (size_t i = 0; i < slot.size(); ++i)
+        if (s.chunk_src[i] >= 0) slot[i] = (int32_t)i;
+    a.chunk_meta = (const int32_t*)up.put(meta);
+    const int32_t* dslot = (const int32_t*)up.put(slot);
+    DevSched b = a;
+    a.direct = true;          // target of a slot = the slot's row of w
+    a.unit_scale = true;      // the level scale is applied in phase B
+    a.chunk_tgt = dslot;
+    b.direct = false;
+    b.chunk_tgt = nullptr;
+    b.chunk_src = dslot;      // source of a slot = the slot's row of w
+    b.max_src = (int)slot.size() - 1;
+    pl->d_s2a = a;
+    pl->d_s2b = b;
+    pl->W = up.zeros((size_t)wbytes);
 }
 
 void fill_info(kifmm_plan_s* pl, double seconds) {
@@ -354,6 +421,15 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
     in.flops[KIFMM_STAGE_P2M] = far ? 11.0 * N * ne + 2.0 * k * ne * nl : 0;
     in.flops[KIFMM_STAGE_M2M] = far ? 2.0 * k * k * (double)nbox_up : 0;
     in.flops[KIFMM_STAGE_M2L] = 2.0 * k * k * (double)in.v_pairs;
+    if (pl->st2) {
+        // two thin products per pair: 2 k r (w = V^ q) + 2 k r (U^ w), r the class rank
+        double f = 0.0, rs = 0.0;
+        for (int32_t c : t.v_cls) f += 4.0 * k * pl->ops.rank2[c];
+        for (int32_t r : pl->ops.rank2) rs += r;
+        in.flops[KIFMM_STAGE_M2L] = f;
+        in.m2l_rank_max = pl->ops.r2max;
+        in.m2l_rank_mean = rs / NCLASS;
+    }
     in.flops[KIFMM_STAGE_L2L] = far ? 2.0 * k * k * (double)nbox_up : 0;
     in.flops[KIFMM_STAGE_L2P] = far ? 11.0 * N * ne + 2.0 * k * ne * nl : 0;
     in.flops[KIFMM_STAGE_P2P] = 11.0 * (double)inter;
@@ -683,7 +759,14 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 0));
-    if (far) {
+    if (far && pl->st2) {
+        // stage 2 (Sec. 3.2): w = V^ q per pair, then p += r_l^-1 U^ w
+        const int MBr = pl->rp / 16;
+        KIFMM_HIP(launch_gg(pl->d_s2a, elt, adjoint ? pl->U2tT : pl->V2t, MBr, KPk, pl->rp, pl->k,
+                            adjoint ? pl->P : pl->Q, kp, pl->W, pl->rp, R, 0, st));
+        KIFMM_HIP(launch_gg(pl->d_s2b, elt, adjoint ? pl->V2tT : pl->U2t, MBk, MBr, pl->k, pl->rp, pl->W, pl->rp,
+                            adjoint ? pl->Q : pl->P, kp, R, 0, st));
+    } else if (far) {
         if (!adjoint)
             KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->P, kp, R, 0, st, pl->b3));
         else
@@ -796,6 +879,9 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         return fail(KIFMM_EINVAL, "m2l_shape must be -1 or in [0, " + std::to_string(kGGVariants - 1) + "]");
     if (o.m2l_shape >= 0 && !gg_variant_supported(o.m2l_shape, o.precision == KIFMM_FP64 ? 8 : 4))
         return fail(KIFMM_EINVAL, "m2l_shape " + std::to_string(o.m2l_shape) + " is not available in this precision");
+    if (!(o.c2 >= 0.0) || !std::isfinite(o.c2)) return fail(KIFMM_EINVAL, "c2 must be finite and >= 0");
+    if (o.c2 > 0.0 && (o.dense_m2l || o.precision == KIFMM_BF16X3))
+        return fail(KIFMM_EINVAL, "c2 > 0 (stage-2 low rank) needs compressed operators in FP32 or FP64");
     const auto t0 = std::chrono::steady_clock::now();
     kifmm_plan_s* pl = new (std::nothrow) kifmm_plan_s();
     if (!pl) return fail(KIFMM_ENOMEM, "host allocation failed");
@@ -812,6 +898,7 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         if (!(eps >= 0.0 && eps < 1.0)) throw PlanError{KIFMM_EINVAL, "eps must be in [0, 1)"};
         pl->tree = build_host_tree(points, n, leaf_size, o.depth, o.max_depth);
         pl->ops = build_host_ops(p, eps, leaf_size, o.cd, o.pinv_rcond, o.dense_m2l != 0);
+        if (o.c2 > 0.0) build_stage2(pl->ops, o.c2);
     } catch (const PlanError& e) {
         delete pl;
         return fail(e.code, e.msg);
@@ -820,6 +907,8 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         return fail(KIFMM_ENOMEM, "host allocation failed");
     }
     pl->k = pl->ops.k;
+    pl->st2 = o.c2 > 0.0;
+    pl->rp = pl->st2 ? (pl->ops.r2max + 15) / 16 * 16 : 0;
     // split-BF16 M2L works on 32-wide K-chunks
     pl->kp = pl->b3 ? (pl->k + 31) / 32 * 32 : (pl->k + 15) / 16 * 16;
     pl->nep = (pl->ops.n_eq + 15) / 16 * 16;
@@ -871,6 +960,7 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         for (size_t l = 0; l < pl->h_up.size(); ++l) pl->d_up[l] = upload_sched(up, pl->h_up[l], pl->elt);
         for (size_t l = 0; l < pl->h_down.size(); ++l) pl->d_down[l] = upload_sched(up, pl->h_down[l], pl->elt);
         if (up.err == KIFMM_OK && tune) autotune_m2l(pl, up);
+        if (up.err == KIFMM_OK && pl->st2 && t.depth >= 2) upload_stage2(pl, up);
         if (up.err == KIFMM_OK &&
             (hipStreamCreateWithFlags(&pl->near_stream, hipStreamNonBlocking) != hipSuccess ||
              hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -947,8 +1037,19 @@ int kifmm_plan_export_operator(kifmm_plan_t plan, int which, double* out, int64_
         case 4: v = &o.M; break;
         case 5: v = &o.L; break;
         case 6: v = &o.K; break;
+        case 8: v = &o.U2; break;
+        case 9: v = &o.V2; break;
+        case 7: {
+            if (o.rank2.empty()) return fail(KIFMM_EINVAL, "operator 7 exists only in stage-2 plans (c2 > 0)");
+            if (count) *count = (int64_t)o.rank2.size();
+            if (out)
+                for (size_t i = 0; i < o.rank2.size(); ++i) out[i] = o.rank2[i];
+            return KIFMM_OK;
+        }
         default: return fail(KIFMM_EINVAL, "unknown operator id");
     }
+    if ((which == 8 || which == 9) && v->empty())
+        return fail(KIFMM_EINVAL, "operators 8 and 9 exist only in stage-2 plans (c2 > 0)");
     if (count) *count = (int64_t)v->size();
     if (out) std::memcpy(out, v->data(), sizeof(double) * v->size());
     return KIFMM_OK;

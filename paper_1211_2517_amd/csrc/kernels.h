@@ -18,8 +18,10 @@ struct DevSched {
     const int32_t* tile_tgt0 = nullptr;
     const int32_t* tile_ntgt = nullptr;
     const int32_t* tile_chunk0 = nullptr;
-    // per chunk 4 words: class, 16-column blocks holding data, scale (float
-    // bits in word 2, or the low and high words of a double in words 2 and 3)
+    // per chunk 4 words: class; 16-column blocks holding data (bits 0..7) and,
+    // when nonzero, the 16-wide K-chunks (gg form) or 16-row blocks of A
+    // (direct form) holding data (bits 8..); scale (float bits in word 2, or
+    // the low and high words of a double in words 2 and 3)
     const int32_t* chunk_meta = nullptr;
     const int32_t* chunk_src = nullptr;
     const int32_t* chunk_col = nullptr;
@@ -28,6 +30,8 @@ struct DevSched {
     // accumulator); chunk_tgt holds the target row of each chunk slot (-1 empty)
     bool direct = false;
     const int32_t* chunk_tgt = nullptr;
+    // direct form only: write the products unscaled (the chunk scale is ignored)
+    bool unit_scale = false;
 };
 
 // Y[tgt] (+)= scale * sum_chunks A[cls] X[src] for every tile of `s`.

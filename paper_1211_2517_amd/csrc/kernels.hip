@@ -146,6 +146,18 @@ __device__ __forceinline__ f32x4 mfma_b3(f32x4 ah, f32x4 al, f32x4 bh, f32x4 bl,
     return d;
 }
 
+// The same three products into two accumulators (da += al*bh + ah*bh,
+// db += ah*bl), so that consecutive MFMAs of one block do not all wait for
+// each other's results.
+__device__ __forceinline__ void mfma_b3x(f32x4 ah, f32x4 al, f32x4 bh, f32x4 bl, f32x4& da, f32x4& db) {
+    typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+    const bf8 AH = __builtin_bit_cast(bf8, ah), AL = __builtin_bit_cast(bf8, al);
+    const bf8 BH = __builtin_bit_cast(bf8, bh), BL = __builtin_bit_cast(bf8, bl);
+    da = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AL, BH, da, 0, 0, 0);
+    db = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, BL, db, 0, 0, 0);
+    da = __builtin_amdgcn_mfma_f32_16x16x32_bf16(AH, BH, da, 0, 0, 0);
+}
+
 // High and low BF16 parts (round to nearest even) of 4 floats, packed two per word.
 __device__ __forceinline__ void split_bf16(const f32x4& v, uint2& hi, uint2& lo) {
     typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
@@ -452,7 +464,13 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     auto mfma_chunk = [&](int buf, const V4 (&a)[MBW][KP16], const Ring& cur, bool on, auto&& hook) {
         const T* bcol = bbuf + (buf * 32 + j) * LDB + 4 * grp;
         const T scale = sc_c;
-        const bool two = on && nb_c > 1;
+        // metadata word 1: 16-column blocks holding data, and (bits 8..) the
+        // K-chunks holding data when fewer than KP16 (stage-2 factors of rank
+        // below the padded rank); the other K-chunks multiply zeros only
+        // (read only for K up to 96, the padded stage-2 ranks; wider kernels
+        // always run every K-chunk, which multiplies zeros there)
+        const bool two = on && (nb_c & 0xff) > 1;
+        const int kc = (KP16 <= 6 && (nb_c >> 8)) ? (nb_c >> 8) : KP16;
         if constexpr (PRE2) {
             V4 b0[KP16], b1[KP16];
 #pragma unroll
@@ -473,31 +491,31 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                         if (two) {
 #pragma unroll
                             for (int m = 0; m < MBW; ++m) {
-                                d[m][(t >> 1) & 1] = mfma_b3(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][(t >> 1) & 1]);
-                                d[m][2 + ((t >> 1) & 1)] =
-                                    mfma_b3(a[m][t - 1], a[m][t], b1[t - 1], b1[t], d[m][2 + ((t >> 1) & 1)]);
+                                mfma_b3x(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][0], d[m][1]);
+                                mfma_b3x(a[m][t - 1], a[m][t], b1[t - 1], b1[t], d[m][2], d[m][3]);
                             }
                         } else if (on) {
 #pragma unroll
-                            for (int m = 0; m < MBW; ++m)
-                                d[m][(t >> 1) & 1] = mfma_b3(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][(t >> 1) & 1]);
+                            for (int m = 0; m < MBW; ++m) mfma_b3x(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][0], d[m][1]);
                         }
                     }
                 } else {
-                    if (two) {
+                    // two accumulation chains per block (step parity), so that
+                    // consecutive MFMAs of a block are independent
+                    if (two && t < kc) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
 #pragma unroll
                             for (int m = 0; m < MBW; ++m) {
-                                d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
-                                d[m][2 + (t & 1)] = M::step(a[m][t][e], b1[t][e], d[m][2 + (t & 1)]);
+                                d[m][e & 1] = M::step(a[m][t][e], b0[t][e], d[m][e & 1]);
+                                d[m][2 + (e & 1)] = M::step(a[m][t][e], b1[t][e], d[m][2 + (e & 1)]);
                             }
                         }
-                    } else if (on) {
+                    } else if (on && t < kc) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
 #pragma unroll
-                            for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], b0[t][e], d[m][t & 1]);
+                            for (int m = 0; m < MBW; ++m) d[m][e & 1] = M::step(a[m][t][e], b0[t][e], d[m][e & 1]);
                         }
                     }
                 }
@@ -523,7 +541,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
 #pragma unroll
             for (int t = 0; t < KP16; ++t) hook(t);
             if (on) {
-                for (int blk = 0; blk < nb_c; ++blk) {
+                for (int blk = 0; blk < (nb_c & 0xff); ++blk) {
                     V4 d[MBW][2];
 #pragma unroll
                     for (int m = 0; m < MBW; ++m) d[m][0] = d[m][1] = V4{0, 0, 0, 0};
@@ -539,11 +557,13 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                     } else {
 #pragma unroll
                         for (int t = 0; t < KP16; ++t) {
-                            const V4 bv = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
+                            if (t < kc) {
+                                const V4 bv = *reinterpret_cast<const V4*>(bcol + blk * 16 * LDB + 16 * t);
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) {
+                                for (int e = 0; e < 4; ++e) {
 #pragma unroll
-                                for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], bv[e], d[m][t & 1]);
+                                    for (int m = 0; m < MBW; ++m) d[m][t & 1] = M::step(a[m][t][e], bv[e], d[m][t & 1]);
+                                }
                             }
                         }
                     }
@@ -708,6 +728,7 @@ struct GDParams {
     int R;
     int cp;
     int accumulate;
+    int unit_scale;             // 1: ignore the chunk scale (products written unscaled)
     const int32_t* chunk_meta;
     const int32_t* chunk_src;
     const int32_t* chunk_tgt;   // per chunk slot: target row (box), -1 for an empty slot
@@ -732,8 +753,14 @@ __global__ void __launch_bounds__(256) gd_kernel(GDParams p) {
     const int R = p.R;
     const int cp = p.cp;
     const int cls = uload<int32_t>(p.chunk_meta, 4 * ch);
-    const int nblk = uload<int32_t>(p.chunk_meta, 4 * ch + 1);
-    const T scale = meta_scale<T>(uload<int32_t>(p.chunk_meta, 4 * ch + 2), uload<int32_t>(p.chunk_meta, 4 * ch + 3));
+    // word 1: 16-column blocks holding data and (bits 8..) the 16-row blocks
+    // of A holding data when fewer than MB (stage-2 factors)
+    const int w1 = uload<int32_t>(p.chunk_meta, 4 * ch + 1);
+    const int nblk = w1 & 0xff;
+    const int nrb = (w1 >> 8) ? min(w1 >> 8, p.MB) : p.MB;
+    const T scale = p.unit_scale ? T(1)
+                                 : meta_scale<T>(uload<int32_t>(p.chunk_meta, 4 * ch + 2),
+                                                 uload<int32_t>(p.chunk_meta, 4 * ch + 3));
     const T* __restrict__ X = static_cast<const T*>(p.X);
     for (int f = tid; f < NSV; f += 256) {
         const int c = f / V4C;
@@ -757,7 +784,7 @@ __global__ void __launch_bounds__(256) gd_kernel(GDParams p) {
     __syncthreads();
     const T* __restrict__ A = static_cast<const T*>(p.A) + (int64_t)cls * p.a_stride;
     T* __restrict__ Y = static_cast<T*>(p.Y);
-    for (int blk = wave; blk < p.MB; blk += 4) {
+    for (int blk = wave; blk < nrb; blk += 4) {
         V4 a[KP16];
         const T* ar = A + (int64_t)(blk * 16 + j) * p.lda + 4 * grp;
 #pragma unroll
@@ -1195,6 +1222,7 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
         g.R = R;
         g.cp = s.cp;
         g.accumulate = accumulate;
+        g.unit_scale = s.unit_scale ? 1 : 0;
         g.chunk_meta = s.chunk_meta;
         g.chunk_src = s.chunk_src;
         g.chunk_tgt = s.chunk_tgt;

@@ -428,6 +428,35 @@ HostOps build_host_ops(int p, double eps, int leaf_size, double cd, double rcond
     return o;
 }
 
+void build_stage2(HostOps& o, double c2) {
+    if (o.dense) throw PlanError{-1, "stage-2 low rank needs the compressed operators (dense_m2l = 0)"};
+    if (!(c2 > 0.0) || !std::isfinite(c2)) throw PlanError{-1, "c2 must be finite and > 0"};
+    const int k = o.k;
+    o.c2 = c2;
+    o.eps2 = c2 * o.eps / double(k) * o.sigma0;
+    std::vector<std::vector<double>> Us(NCLASS), Vs(NCLASS), ss(NCLASS);
+    o.rank2.assign(NCLASS, 0);
+    parallel_for(NCLASS, [&](int64_t c) {
+        svd_jacobi(k, k, &o.K[(size_t)c * k * k], ss[c], Us[c], Vs[c]);
+        int r = 0;
+        for (int i = 0; i < k; ++i)
+            if (ss[c][i] >= o.eps2) ++r;
+        o.rank2[c] = std::max(r, 1);
+    });
+    o.r2max = *std::max_element(o.rank2.begin(), o.rank2.end());
+    const int rm = o.r2max;
+    o.U2.assign((size_t)NCLASS * k * rm, 0.0);
+    o.V2.assign((size_t)NCLASS * rm * k, 0.0);
+    for (int c = 0; c < NCLASS; ++c) {
+        const int r = o.rank2[c];
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < r; ++j) o.U2[((size_t)c * k + i) * rm + j] = Us[c][(size_t)i * k + j];
+        // V^ = S^ Q^^T: row j is s_j times column j of the right singular vectors
+        for (int j = 0; j < r; ++j)
+            for (int i = 0; i < k; ++i) o.V2[((size_t)c * rm + j) * k + i] = ss[c][j] * Vs[c][(size_t)i * k + j];
+    }
+}
+
 std::vector<int64_t> uniform_cuts(int64_t n_tgt, int tile) {
     std::vector<int64_t> cuts;
     for (int64_t t = 0; t < n_tgt; t += tile) cuts.push_back(t);

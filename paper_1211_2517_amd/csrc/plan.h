@@ -63,9 +63,20 @@ struct HostOps {
     std::vector<double> T;      // n_eq x k
     std::vector<double> M, L;   // 8 x k x k (octant 4*ox+2*oy+oz)
     std::vector<double> K;      // 316 x k x k
+    // stage-2 factors (Sec. 3.2), empty unless build_stage2 ran
+    double c2 = 0, eps2 = 0;    // constant C2 and the absolute cutoff C2 eps / k * sigma0
+    int r2max = 0;              // largest rank
+    std::vector<int32_t> rank2; // 316 ranks
+    std::vector<double> U2;     // 316 x k x r2max: U^ (zero past the rank)
+    std::vector<double> V2;     // 316 x r2max x k: V^ = S^ Q^^T (zero past the rank)
 };
 
 HostOps build_host_ops(int p, double eps, int leaf_size, double cd, double rcond, bool dense);
+
+// Stage-2 low rank of the compressed M2L matrices (Sec. 3.2): per class the SVD
+// K~ = U S Q^T, keeping the singular values not below C2 eps / k * sigma0.
+// Requires compressed operators (not dense); c2 > 0.
+void build_stage2(HostOps& o, double c2);
 
 // Work schedule of the grouped gather GEMM Y[t] (+)= scale * sum A[cls] X[src].
 // `cp` pairs of one class form a chunk; `rhs` right-hand-side columns per pair.

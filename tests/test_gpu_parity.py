@@ -152,13 +152,75 @@ def test_full_size_sphere_sampled():
     g = json.load(open(GOLDEN))
     x, s = sphere(g["n"])
     idx = np.asarray(g["sample"])
-    for dense, prec, tol in ((False, "fp32", 1e-5), (False, "bf16x3", 1e-5), (True, "fp64", 1e-8)):
-        got, plan = gpu_apply(x, s, g["p"], g["eps"], g["leaf_size"], precision=prec, dense=dense)
+    for dense, prec, tol, c2 in ((False, "fp32", 1e-5, 0.0), (False, "bf16x3", 1e-5, 0.0), (True, "fp64", 1e-8, 0.0),
+                                 (False, "fp32", 1e-5, 10.0)):
+        got, plan = gpu_apply(x, s, g["p"], g["eps"], g["leaf_size"], precision=prec, dense=dense, c2=c2)
         assert plan.info()["depth"] == g["depth"]
         e = rel(got[idx], g["phi_dense"])
-        print(f"dense_m2l={dense} {prec} sampled rel err vs fp64 dense oracle {e:.3e}; "
+        print(f"dense_m2l={dense} {prec} c2={c2} sampled rel err vs fp64 dense oracle {e:.3e}; "
               f"vs direct {rel(got[idx], g['phi_direct']):.3e}")
         assert e < tol
+
+
+# ------------------------------------------------ stage-2 low rank (Sec. 3.2)
+@functools.lru_cache(maxsize=None)
+def oracle_phi_svd2(p, c2):
+    x, s = cube()
+    ops = oracle.build_operators(p, 1e-6, 64, mode="svd2", c2=c2)
+    return oracle.fmm(x, s, p, 1e-6, 64, ops=ops)[0]
+
+
+@pytest.mark.parametrize("p,tol", [(4, 1e-10), (6, 3e-9)])
+def test_stage2_fp64_matches_oracle_svd2(p, tol):
+    # two thin products per pair (w = V^ q per chunk slot, then U^ w) against
+    # the oracle's stage-2 M2L with the same C2 (ranks equal on both sides here).
+    # A wrong factor or rank would show at the size of the dropped singular
+    # values (eps2 ~ 1e-7 relative); FP64 rounding of the two sides' operators
+    # is amplified by the reduced S~ (|S~| ~ 1e5 at p = 6): measured 6.5e-10.
+    x, s = cube()
+    got, plan = gpu_apply(x, s, p, 1e-6, 64, precision="fp64", c2=10.0)
+    want = oracle_phi_svd2(p, 10.0)
+    info = plan.info()
+    assert 0 < info["m2l_rank_max"] < info["k"]
+    assert rel(got, want) < tol
+
+
+@pytest.mark.parametrize("p", [4, 6])
+def test_stage2_fp32_vs_dense_oracle_cube(p):
+    x, s = cube()
+    want = oracle_phi("cube", 4096, p, 1e-6, 64, "dense")
+    got, plan = gpu_apply(x, s, p, 1e-6, 64, c2=10.0)
+    e = rel(got, want)
+    print(f"p={p} fp32 stage-2 (C2=10, mean rank {plan.info()['m2l_rank_mean']:.1f}) vs dense oracle: {e:.3e}")
+    assert e < 1e-5
+
+
+def test_stage2_adjoint_dot_product_fp64():
+    torch = _torch()
+    x, s = cube()
+    g = workloads.uniform_density(4096, 77)
+    plan = _k().Plan(x, p=6, eps=1e-6, leaf_size=64, precision="fp64", c2=10.0)
+    sd = torch.tensor(s, dtype=torch.float64, device="cuda:0")
+    gd = torch.tensor(g, dtype=torch.float64, device="cuda:0")
+    fs = plan.apply(sd).double().cpu().numpy()
+    ftg = plan.apply_adjoint(gd).double().cpu().numpy()
+    # the stage-2 factors of t and -t are transposes of each other up to rounding
+    assert abs(g @ fs - ftg @ s) <= 1e-10 * np.linalg.norm(g) * np.linalg.norm(fs)
+
+
+def test_stage2_batched_columns_match_single():
+    # 3 right-hand sides through the per-slot product buffer (rows slot*R + r)
+    torch = _torch()
+    K = _k()
+    x, _ = cube()
+    S = workloads.uniform_density(4096, 9, nrhs=3)
+    plan = K.Plan(x, p=6, eps=1e-6, leaf_size=64, max_nrhs=4, c2=10.0)
+    single = K.Plan(x, p=6, eps=1e-6, leaf_size=64, c2=10.0)
+    Sd = torch.tensor(S, dtype=torch.float32, device="cuda:0")
+    out = plan.apply_batched(Sd).cpu().numpy()
+    for j in range(3):
+        one = single.apply(Sd[:, j].contiguous()).cpu().numpy()
+        assert np.allclose(out[:, j], one, rtol=1e-6, atol=1e-6 * np.abs(one).max())
 
 
 # ----------------------------------------------------------------- adjoint

@@ -141,3 +141,48 @@ def test_duplicate_points_cap_depth():
     x = np.repeat(workloads.uniform_cube(10, 2), 20, axis=0)   # 20 copies of 10 points
     pl = K.Plan(x, p=4, eps=1e-6, leaf_size=8, device=-1, max_depth=6)
     assert pl.info()["depth"] == 6
+
+
+@pytest.mark.parametrize("p,eps,c2", [(4, 1e-6, 10.0), (6, 1e-6, 10.0), (6, 1e-6, 100.0)])
+def test_stage2_factors_match_oracle(p, eps, c2):
+    # stage-2 low rank (Sec. 3.2): same ranks as the oracle and the same factored
+    # matrices U^ V^ (in the U~ basis, which is unique up to signs)
+    x = workloads.uniform_cube(4096, 1211)
+    pl = K.Plan(x, p=p, eps=eps, leaf_size=64, device=-1, c2=c2)
+    ops = oracle.build_operators(p, eps, 64, mode="svd2", c2=c2)
+    k = ops.k
+    info = pl.info()
+    ranks = pl.export_operator(7).astype(int)
+    want = np.array([ops.K2[t][0].shape[1] for t in oracle.offset_classes()])
+    # a singular value within rounding of the cutoff may fall on either side
+    assert np.abs(ranks - want).max() <= 1 and np.mean(ranks != want) < 0.02
+    assert info["m2l_rank_max"] == ranks.max() and abs(info["m2l_rank_mean"] - ranks.mean()) < 1e-12
+    rm = info["m2l_rank_max"]
+    U = pl.export_operator(1).reshape(ops.n_eq, k)
+    U2 = pl.export_operator(8).reshape(316, k, rm)
+    V2 = pl.export_operator(9).reshape(316, rm, k)
+    scale = max(np.abs(v).max() for v in ops.K_full.values())
+    for i, t in enumerate(oracle.offset_classes()):
+        r = ranks[i]
+        assert not U2[i][:, r:].any() and not V2[i][r:].any()
+        Uh, Vh = ops.K2[t]
+        mine = U @ U2[i] @ V2[i] @ U.T
+        ref = ops.U @ Uh @ Vh @ ops.U.T
+        # equal ranks: the same truncated matrix; one more or fewer singular
+        # value: they differ by that value, which is within rounding of the cutoff
+        assert np.abs(mine - ref).max() <= 1e-9 * scale + (0 if r == Uh.shape[1] else 2 * ops.eps2)
+    # flops of the two thin products
+    assert info["flops"]["m2l"] < 2 * k * k * info["v_pairs"]
+
+
+def test_stage2_rejected_with_dense_or_bf16x3():
+    x = workloads.uniform_cube(500, 1211)
+    with pytest.raises(K.KifmmError):
+        K.Plan(x, p=4, eps=1e-6, leaf_size=64, device=-1, c2=10.0, dense_m2l=True)
+    with pytest.raises(K.KifmmError):
+        K.Plan(x, p=4, eps=1e-6, leaf_size=64, device=-1, c2=10.0, precision="bf16x3")
+    with pytest.raises(K.KifmmError):
+        K.Plan(x, p=4, eps=1e-6, leaf_size=64, device=-1, c2=-1.0)
+    pl = K.Plan(x, p=4, eps=1e-6, leaf_size=64, device=-1)
+    with pytest.raises(K.KifmmError):
+        pl.export_operator(7)
