@@ -22,6 +22,9 @@
 #ifndef GG_LA
 #define GG_LA 2
 #endif
+#ifndef GG_TSMALL
+#define GG_TSMALL (KP16 > 1 ? 1 : 0)
+#endif
 namespace kifmm {
 
 namespace {
@@ -607,11 +610,10 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         // data-dependent load count would make the compiler's waits drain
         // loads issued in the same iteration. The order is: the A rows of chunk
         // c+1, K-chunk by K-chunk (hook(t), spread over the MFMAs; needed by
-        // the next iteration's MFMAs), then the gathers of chunk c+2 (stored at
-        // the end of the next iteration) and the indices consumed one or two
-        // iterations later. So no wait ever retires a load of its own iteration
-        // that it does not need, and waiting for the last A rows does not
-        // retire the gathers.
+        // the next iteration's MFMAs), with the gathers of chunk c+GD (stored
+        // at the end of iteration c+GD-1) and the indices consumed one or two
+        // iterations later issued after K-chunk GG_TSMALL. So no wait ever
+        // retires a load of its own iteration that it does not need.
         // source rows of chunk ch+GD (used here), reloaded with those of
         // chunk ch+GD+2 (same parity)
         int (&sq)[NLD] = (GD % 2 == 0) ? cur.src : oth.src;
@@ -622,7 +624,11 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                 for (int m = 0; m < MBW; ++m)
                     an[m][t] = bload4<T>(ra, t == KP16 - 1 ? aofl[m] : aoff[m] + 16 * t * (int)sizeof(T), so);
             }
-            if (t == KP16 - 1) {
+            // the gathers and the small loads (source rows, metadata, target
+            // columns) go out right after the first K-chunks' MFMAs, so they
+            // have most of an extra iteration to return (issued after the last
+            // K-chunk they left the next iteration waiting on memory latency)
+            if (t == GG_TSMALL) {
                 gather(go, sq);
                 load_src(clampc(ch + GD + 2), sq);
                 oth.meta = load_meta(clampc(ch + 3));
