@@ -208,6 +208,15 @@ def test_stage2_adjoint_dot_product_fp64():
     assert abs(g @ fs - ftg @ s) <= 1e-10 * np.linalg.norm(g) * np.linalg.norm(fs)
 
 
+def test_stage2_without_far_field():
+    # depth < 2 (no interaction fields): the stage-2 plan is the direct sum
+    x = workloads.uniform_cube(60, 5)
+    s = workloads.uniform_density(60, 6)
+    got, plan = gpu_apply(x, s, 4, 1e-6, 64, precision="fp64", c2=10.0)
+    assert plan.info()["depth"] < 2
+    assert rel(got, oracle.direct(x, s)) < 1e-13
+
+
 def test_stage2_batched_columns_match_single():
     # 3 right-hand sides through the per-slot product buffer (rows slot*R + r)
     torch = _torch()
@@ -346,11 +355,13 @@ def test_bitwise_deterministic():
     assert torch.equal(a, b)
 
 
-def test_group_graph_replays_match_eager():
+@pytest.mark.parametrize("c2", [0.0, 10.0])
+def test_group_graph_replays_match_eager(c2):
+    # c2 > 0: the stage-2 M2L launches (per-slot products, then U^ w) inside the graph
     torch = _torch()
     K = _k()
     sets = [workloads.sphere_points(3000, 1), workloads.cube_surface(5000, 2), workloads.torus_random(7000, 3)]
-    plans = [K.Plan(x, p=4, eps=1e-6, leaf_size=32) for x in sets]
+    plans = [K.Plan(x, p=4, eps=1e-6, leaf_size=32, c2=c2) for x in sets]
     sig = [torch.tensor(workloads.uniform_density(x.shape[0], i), dtype=torch.float32, device="cuda:0")
            for i, x in enumerate(sets)]
     eager = [p.apply(s).clone() for p, s in zip(plans, sig)]
