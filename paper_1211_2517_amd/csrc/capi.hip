@@ -623,8 +623,7 @@ void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
         cands.push_back(it->second);
     } else {
         for (int v = 0; v < kGGVariants; ++v)
-            if ((shape < 0 || v == shape) && gg_variant_supported(v, pl->elt) &&
-                (v != 4 || pl->kp <= kGGColumnSplitMaxK))
+            if ((shape < 0 || v == shape) && gg_variant_supported(v, pl->elt))
                 for (int r = 0; r < 3; ++r) cands.push_back({v, r});
     }
     if (cands.size() == 1) {
@@ -916,10 +915,6 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     if (pl->kp > 19 * 16 || pl->nep > 19 * 16) {
         delete pl;
         return fail(KIFMM_EINVAL, "n_eq too large for the device kernels (p <= 8 supported)");
-    }
-    if (o.m2l_shape == 4 && pl->kp > kGGColumnSplitMaxK) {
-        delete pl;
-        return fail(KIFMM_EINVAL, "m2l_shape 4 needs k <= " + std::to_string(kGGColumnSplitMaxK));
     }
     if (o.device >= 0) {
         int ndev = 0;

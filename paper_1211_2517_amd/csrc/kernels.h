@@ -52,13 +52,8 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
 //   1 = 4 waves (64 rows), all of a CU's LDS;
 //   2 = 4 waves (64 rows), half of a CU's LDS, so two workgroups share a CU;
 //   3 = 4 waves with two 16-row blocks each (128 rows), all of a CU's LDS,
-//       one wave per SIMD (FP32 only);
-//   4 = 16 waves (128 rows), all of a CU's LDS: waves w and w + 8 share a
-//       16-row block, one computing the first and one the second 16-column
-//       block of every chunk, four waves per SIMD (FP32, K <= 128 only).
-constexpr int kGGVariants = 5;
-// largest padded K of kernel shape 4 (16 waves of at most 128 registers)
-constexpr int kGGColumnSplitMaxK = 128;
+//       one wave per SIMD (FP32 only).
+constexpr int kGGVariants = 4;
 // Whether shape `variant` exists for element size `elt` (4 or 8 bytes).
 bool gg_variant_supported(int variant, int elt);
 // Output rows per workgroup of a shape (0 for an unknown shape).

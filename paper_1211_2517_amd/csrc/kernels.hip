@@ -248,8 +248,8 @@ __device__ __forceinline__ double meta_scale<double>(int lo, int hi) {
 // K-chunks); the staging converts the gathered FP32 columns into the same
 // layout in LDS. Register sets and LDS addresses are those of the FP32 form;
 // K-chunk pair (2c, 2c+1) of the FP32 form is (hi, lo) of 32-wide chunk c.
-template <typename T, int KP16, int WAVES, int MBW, bool B3 = false, int CS = 1>
-__global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_kernel(GGParams p) {
+template <typename T, int KP16, int WAVES, int MBW, bool B3 = false>
+__global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGParams p) {
     static_assert(!B3 || (sizeof(T) == 4 && KP16 % 2 == 0), "split BF16 needs FP32 data and 32-wide K-chunks");
     using M = Mfma<T>;
     using V4 = typename M::V4;
@@ -276,17 +276,11 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
     T* acc = bbuf + p.nbuf * 32 * LDB;          // [ncol + R][ldl]
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    // CS = 2: the waves come in two halves that share the row blocks, wave
-    // w computing row block(s) of w % RW for 16-column block w / RW of every
-    // chunk (four waves per SIMD at 16 waves instead of two)
-    constexpr int RW = WAVES / CS;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int rwave = CS == 1 ? wave : wave % RW;
-    const int cbw = CS == 1 ? 0 : wave / RW;
-    const int mb_lo = rg * RW * MBW;
-    const int nmb = min(RW * MBW, p.MB - mb_lo);
+    const int mb_lo = rg * WAVES * MBW;
+    const int nmb = min(WAVES * MBW, p.MB - mb_lo);
     const int rows = nmb * 16;
-    const int ldl = RW * MBW * 16 + 4;
+    const int ldl = WAVES * MBW * 16 + 4;
     const int R = p.R;
     const int cp = p.cp;
     const int t0 = uload<int32_t>(p.tile_tgt0, tile);
@@ -316,7 +310,7 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
     // a wave works when its first row block holds output rows; a second row
     // block past the last one reads a valid row of A and accumulates into LDS
     // rows that are never stored
-    const bool wact = rwave * MBW < nmb;
+    const bool wact = wave * MBW < nmb;
     // buffer resources: every load of the chunk loop takes a 32-bit lane
     // offset that is fixed for the kernel plus a scalar offset per chunk
     const __amdgpu_buffer_rsrc_t rx = make_rsrc(p.X, p.x_bytes);
@@ -329,7 +323,7 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
     uint32_t aoff[MBW], aofl[MBW];
 #pragma unroll
     for (int m = 0; m < MBW; ++m) {
-        const int blk = min(rwave * MBW + m, nmb - 1);
+        const int blk = min(wave * MBW + m, nmb - 1);
         const int row = row0 + blk * 16 + j;
         aoff[m] = row < p.a_rows ? (uint32_t)((row * p.lda + 4 * grp) * (int)sizeof(T)) : kOffNone;
         aofl[m] = (row < p.a_rows && (B3 || 16 * (KP16 - 1) + 4 * grp < p.a_cols))
@@ -379,7 +373,7 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
     // index mod 4) in the FP32 8-wave shape up to K = 224 (measured: 8% faster
     // than GD = 2 there, slower in the 4-wave shapes, whose waves issue twice
     // the gathers), else GD = 2 in two sets (chunk parity)
-    constexpr bool SETS4_FIT = sizeof(T) == 4 && RW == 8 && KP16 <= 14;
+    constexpr bool SETS4_FIT = sizeof(T) == 4 && WAVES == 8 && KP16 <= 14;
     constexpr int GD = SETS4_FIT ? GG_GD : 2;
     static_assert(GD >= 2 && GD <= 4, "gather distance");
     constexpr int FILL = GD == 2 ? 2 : 4;   // pipeline-fill iterations before chunk cb
@@ -435,7 +429,7 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
     };
     // accumulator column `col` at this wave's rows; empty slots go to the spare columns
     auto acc_ptr = [&](int col) {
-        return acc + ((col >= 0 ? col : p.trash_col) * R + rj) * ldl + rwave * MBW * 16;
+        return acc + ((col >= 0 ? col : p.trash_col) * R + rj) * ldl + wave * MBW * 16;
     };
 
     // acc[col][rows of this wave] += scale * (u + v), read-modify-write of one
@@ -480,16 +474,12 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
         // always run every K-chunk, which multiplies zeros there)
         const bool two = on && (nb_c & 0xff) > 1;
         const int kc = (KP16 <= 6 && (nb_c >> 8)) ? (nb_c >> 8) : KP16;
-        // CS = 2: this wave's block (cbw) holds data; two1: both blocks in this wave
-        const bool mine = CS == 1 ? on : (cbw ? two : on);
-        const bool two1 = CS == 1 && two;
         if constexpr (PRE2) {
-            const T* bw = bcol + cbw * 16 * LDB;
             V4 b0[KP16], b1[KP16];
 #pragma unroll
             for (int t = 0; t < LA && t < KP16; ++t) {
-                b0[t] = *reinterpret_cast<const V4*>(bw + 16 * t);
-                if constexpr (CS == 1) b1[t] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * t);
+                b0[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
+                b1[t] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * t);
             }
             V4 d[MBW][4];
 #pragma unroll
@@ -501,13 +491,13 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
                 __builtin_amdgcn_sched_barrier(0);
                 if constexpr (B3) {
                     if (t & 1) {
-                        if (two1) {
+                        if (two) {
 #pragma unroll
                             for (int m = 0; m < MBW; ++m) {
                                 mfma_b3x(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][0], d[m][1]);
                                 mfma_b3x(a[m][t - 1], a[m][t], b1[t - 1], b1[t], d[m][2], d[m][3]);
                             }
-                        } else if (mine) {
+                        } else if (on) {
 #pragma unroll
                             for (int m = 0; m < MBW; ++m) mfma_b3x(a[m][t - 1], a[m][t], b0[t - 1], b0[t], d[m][0], d[m][1]);
                         }
@@ -515,7 +505,7 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
                 } else {
                     // two accumulation chains per block (step parity), so that
                     // consecutive MFMAs of a block are independent
-                    if (two1 && t < kc) {
+                    if (two && t < kc) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
 #pragma unroll
@@ -524,7 +514,7 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
                                 d[m][2 + (e & 1)] = M::step(a[m][t][e], b1[t][e], d[m][2 + (e & 1)]);
                             }
                         }
-                    } else if (mine && t < kc) {
+                    } else if (on && t < kc) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
 #pragma unroll
@@ -534,18 +524,18 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 if (t + LA < KP16) {
-                    b0[t + LA] = *reinterpret_cast<const V4*>(bw + 16 * (t + LA));
-                    if constexpr (CS == 1) b1[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * (t + LA));
+                    b0[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * (t + LA));
+                    b1[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * (t + LA));
                 }
                 hook(t);
             }
             __builtin_amdgcn_sched_barrier(0);
-            if (mine) {
-                T* p0 = acc_ptr(cbw ? cur.col1 : cur.col0);
+            if (on) {
+                T* p0 = acc_ptr(cur.col0);
 #pragma unroll
                 for (int m = 0; m < MBW; ++m) acc_add(p0 + 16 * m, d[m][0], d[m][1], scale);
             }
-            if (two1) {
+            if (two) {
                 T* p1 = acc_ptr(cur.col1);
 #pragma unroll
                 for (int m = 0; m < MBW; ++m) acc_add(p1 + 16 * m, d[m][2], d[m][3], scale);
@@ -554,7 +544,7 @@ __global__ void __launch_bounds__(64 * WAVES, (MBW == 1 && CS == 1) ? 2 : 1) gg_
 #pragma unroll
             for (int t = 0; t < KP16; ++t) hook(t);
             if (on) {
-                for (int blk = cbw; blk < (nb_c & 0xff); blk += CS) {
+                for (int blk = 0; blk < (nb_c & 0xff); ++blk) {
                     V4 d[MBW][2];
 #pragma unroll
                     for (int m = 0; m < MBW; ++m) d[m][0] = d[m][1] = V4{0, 0, 0, 0};
@@ -1127,35 +1117,20 @@ hipError_t gd_dispatch(int KP16, const GDParams& p, int blocks, size_t lds, hipS
     }
 }
 
-template <typename T, int KP16, int WAVES, int MBW, bool B3, int CS = 1>
+template <typename T, int KP16, int WAVES, int MBW, bool B3>
 hipError_t gg_launch_t(const GGParams& p, int blocks, size_t lds, hipStream_t st) {
     if constexpr (B3 && (KP16 % 2 != 0 || sizeof(T) != 4)) {
         return hipErrorInvalidValue;
     } else {
         static size_t attr_set = 0;
         if (lds > 65536 && lds > attr_set) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES, MBW, B3, CS>),
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES, MBW, B3>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;
             attr_set = lds;
         }
-        hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES, MBW, B3, CS>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
+        hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES, MBW, B3>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
         return hipGetLastError();
-    }
-}
-
-// the column-split shape (16 waves, 128 registers each) up to K = 128 only
-template <typename T, int WAVES, int MBW, bool B3, int CS>
-hipError_t gg_dispatch_cs(int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st) {
-    switch (KP16) {
-#define KIFMM_GG_CASE(K) \
-    case K:              \
-        return gg_launch_t<T, K, WAVES, MBW, B3, CS>(p, blocks, lds, st);
-        KIFMM_GG_CASE(1) KIFMM_GG_CASE(2) KIFMM_GG_CASE(3) KIFMM_GG_CASE(4) KIFMM_GG_CASE(5)
-        KIFMM_GG_CASE(6) KIFMM_GG_CASE(7) KIFMM_GG_CASE(8)
-#undef KIFMM_GG_CASE
-        default:
-            return hipErrorInvalidValue;
     }
 }
 
@@ -1185,7 +1160,6 @@ hipError_t gg_variant(int variant, int KP16, const GGParams& p, int blocks, size
                 case 1:
                 case 2: return gg_dispatch<T, 4, 1, true>(KP16, p, blocks, lds, st);
                 case 3: return gg_dispatch<T, 4, 2, true>(KP16, p, blocks, lds, st);
-                case 4: return gg_dispatch_cs<T, 16, 1, true, 2>(KP16, p, blocks, lds, st);
                 default: return hipErrorInvalidValue;
             }
         }
@@ -1199,10 +1173,6 @@ hipError_t gg_variant(int variant, int KP16, const GGParams& p, int blocks, size
             // two row blocks per wave: FP32 only (the FP64 registers would spill)
             if constexpr (sizeof(T) == 4) return gg_dispatch<T, 4, 2>(KP16, p, blocks, lds, st);
             return hipErrorInvalidValue;
-        case 4:
-            // 16 waves, each on one 16-column block of every chunk: FP32 only
-            if constexpr (sizeof(T) == 4) return gg_dispatch_cs<T, 16, 1, false, 2>(KP16, p, blocks, lds, st);
-            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -1215,13 +1185,12 @@ int gg_variant_rows(int variant) {
         case 1:
         case 2: return 4 * 16;
         case 3: return 4 * 2 * 16;
-        case 4: return 8 * 16;
         default: return 0;
     }
 }
 
 bool gg_variant_supported(int variant, int elt) {
-    return variant >= 0 && variant < kGGVariants && ((variant != 3 && variant != 4) || elt == 4);
+    return variant >= 0 && variant < kGGVariants && (variant != 3 || elt == 4);
 }
 
 int gg_variant_wgs_per_cu(int variant) { return variant == 2 ? 2 : 1; }

@@ -145,26 +145,6 @@ def test_fp32_sphere_many_tiles_ragged():
     assert rel(got, want) < 1e-5
 
 
-@pytest.mark.parametrize("precision,c2", [("fp32", 0.0), ("bf16x3", 0.0), ("fp32", 10.0)])
-def test_column_split_shape_matches_shape0_bitwise(precision, c2):
-    # kernel shape 4 (16 waves, two per row block, one per 16-column block)
-    # runs the same MFMA chains and accumulator adds as shape 0 on the same
-    # tiles, so the results are bitwise equal; and within the bar of the
-    # dense oracle (stage 2: phase B at K = 48 also runs shape 4)
-    x, s = sphere(20000)
-    want = oracle_phi("sphere", 20000, 6, 1e-6, 32, "dense")
-    got4, plan4 = gpu_apply(x, s, 6, 1e-6, 32, precision=precision, tile_targets=96, m2l_shape=4, c2=c2)
-    got0, plan0 = gpu_apply(x, s, 6, 1e-6, 32, precision=precision, tile_targets=96, m2l_shape=0, c2=c2)
-    assert plan4.info()["m2l_variant"] == 4 and plan0.info()["m2l_variant"] == 0
-    assert plan4.info()["m2l_tiles"] == plan0.info()["m2l_tiles"]
-    assert np.array_equal(got4, got0)
-    assert rel(got4, want) < (2e-5 if precision == "bf16x3" else 1e-5)
-    # the adjoint runs the same launch over the transposed tables
-    adj4, _ = gpu_apply(x, s, 6, 1e-6, 32, precision=precision, tile_targets=96, m2l_shape=4, c2=c2, adjoint=True)
-    adj0, _ = gpu_apply(x, s, 6, 1e-6, 32, precision=precision, tile_targets=96, m2l_shape=0, c2=c2, adjoint=True)
-    assert np.array_equal(adj4, adj0)
-
-
 def test_full_size_sphere_sampled():
     # 2**20 icosphere centroids, p=6, eps=1e-6, leaf 64 (the benchmark workload),
     # checked at 256 sampled points against the oracle (tests/golden, written

@@ -125,9 +125,6 @@ def test_invalid_arguments_are_rejected():
     assert _err(lambda: K.Plan(bad, device=-1)) == -4
     assert _err(lambda: K.Plan(x, max_nrhs=17, device=-1)) == -1
     assert _err(lambda: K.Plan(x, p=9, device=-1)) == -1     # n_eq 386 beyond the device kernels
-    assert _err(lambda: K.Plan(x, p=8, dense_m2l=True, m2l_shape=4, device=-1)) == -1   # k_pad 304 > 128
-    assert _err(lambda: K.Plan(x, m2l_shape=4, precision="fp64", device=-1)) == -1
-    assert _err(lambda: K.Plan(x, m2l_shape=5, device=-1)) == -1
 
 
 def test_host_only_plan_refuses_apply():
