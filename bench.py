@@ -166,6 +166,10 @@ def main():
         err_direct = float(np.linalg.norm(got - ref_direct) / np.linalg.norm(ref_direct))
         log(f"{name}: {ms:.3f} ms/step, err vs FP64 oracle {err:.2e}, stages {stages}")
         res[name] = dict(ms=ms, wall=wall, stages=stages, info=info, err=err, err_direct=err_direct)
+        if c2 > 0:
+            # per-class ranks of the stage-2 factors (the distribution of Fig. 1)
+            ranks = np.bincount(plan.export_operator(7).astype(np.int64))
+            res[name]["rank_histogram"] = [[int(r), int(c)] for r, c in enumerate(ranks) if c]
         plan.close()
 
     if args.only:
@@ -177,6 +181,7 @@ def main():
         m2l = r["stages"]["m2l"]
         return {"c2": STAGE2_C2, "ms_per_step": round(r["ms"], 4), "err_vs_fp64_dense_oracle": r["err"],
                 "rank_mean": round(i["m2l_rank_mean"], 2), "rank_max": i["m2l_rank_max"],
+                "rank_histogram": r["rank_histogram"],
                 "m2l_ms": round(m2l, 4), "m2l_flops": i["flops"]["m2l"],
                 "m2l_tflops": round(i["flops"]["m2l"] / (m2l * 1e-3) / 1e12, 3),
                 "m2l_speedup_vs_stage1": round(svd["stages"]["m2l"] / m2l, 3),
