@@ -175,6 +175,31 @@ def test_stage2_factors_match_oracle(p, eps, c2):
     assert info["flops"]["m2l"] < 2 * k * k * info["v_pairs"]
 
 
+@pytest.mark.parametrize("p", [4, 6])
+def test_stage2_spectra_invariant_under_cube_symmetries(p):
+    # cube surfaces: offsets in one orbit of the 48 axis permutations and
+    # reflections (same sorted |t_a|) have M2L operators related by
+    # orthogonal maps, hence equal stage-2 ranks and kept singular values
+    # (the row norms of V^ = S^ Q^^T); offsets in lexicographic order over
+    # [-3,3]^3 with max |t_a| >= 2
+    x = workloads.uniform_cube(2000, 7)
+    pl = K.Plan(x, p=p, eps=1e-6, leaf_size=64, device=-1, c2=10.0)
+    info = pl.info()
+    k, r = info["k"], info["m2l_rank_max"]
+    ranks = pl.export_operator(7).astype(int)
+    sv = np.linalg.norm(pl.export_operator(9).reshape(316, r, k), axis=2)
+    offs = [(a, b, c) for a in range(-3, 4) for b in range(-3, 4) for c in range(-3, 4)
+            if max(abs(a), abs(b), abs(c)) >= 2]
+    orbits = {}
+    for i, t in enumerate(offs):
+        orbits.setdefault(tuple(sorted(map(abs, t))), []).append(i)
+    assert len(orbits) == 16
+    for idx in orbits.values():
+        assert len(set(ranks[idx])) == 1
+        ref = sv[idx[0]]
+        assert np.max(np.abs(sv[idx] - ref)) <= 1e-10 * ref[0]
+
+
 def test_stage2_rejected_with_dense_or_bf16x3():
     x = workloads.uniform_cube(500, 1211)
     with pytest.raises(K.KifmmError):

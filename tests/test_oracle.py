@@ -330,6 +330,25 @@ def test_stage2_transpose_classes():
         assert np.linalg.norm(a - b, 2) <= 1e-10 * np.linalg.norm(a, 2)
 
 
+@pytest.mark.parametrize("p", [4, 6])
+def test_stage2_spectra_invariant_under_cube_symmetries(p):
+    # The check and equivalent surfaces are cubes, so an axis permutation or
+    # reflection g maps the M2L operator of offset t onto that of g(t) by
+    # orthogonal changes of surface coordinates: the 48 symmetries split the
+    # 316 offsets into 16 orbits (classes of sorted |t_a|), and the stage-2
+    # ranks and kept singular values must agree within each orbit.
+    ops = ops2_cached(p, 1e-6, 64, 10.0)
+    orbits = {}
+    for t, (Uh, Vh) in ops.K2.items():
+        sv = np.linalg.norm(Vh, axis=1)      # V^ = S^ Q^^T: row norms are the kept values
+        orbits.setdefault(tuple(sorted(map(abs, t))), []).append(sv)
+    assert len(orbits) == 16
+    for svs in orbits.values():
+        for sv in svs[1:]:
+            assert sv.shape == svs[0].shape
+            assert np.max(np.abs(sv - svs[0])) <= 1e-10 * svs[0][0]
+
+
 def test_stage2_c2_zero_is_stage1():
     # eps2 = 0 keeps every singular value: the factors multiply back to K~.
     x, q, _ = _cube4096()
