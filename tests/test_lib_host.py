@@ -175,6 +175,24 @@ def test_stage2_factors_match_oracle(p, eps, c2):
     assert info["flops"]["m2l"] < 2 * k * k * info["v_pairs"]
 
 
+@pytest.mark.parametrize("p,dense", [(4, False), (6, False), (4, True)])
+def test_m2l_spectra_invariant_under_cube_symmetries(p, dense):
+    # singular values of the exported M2L matrices (compressed K~, or the
+    # uncompressed K) agree across each orbit of the 48 cube symmetries
+    x = workloads.uniform_cube(2000, 7)
+    pl = K.Plan(x, p=p, eps=1e-6, leaf_size=64, device=-1, dense_m2l=dense)
+    k = pl.info()["k"]
+    sv = np.linalg.svd(pl.export_operator(6).reshape(316, k, k), compute_uv=False)
+    offs = [(a, b, c) for a in range(-3, 4) for b in range(-3, 4) for c in range(-3, 4)
+            if max(abs(a), abs(b), abs(c)) >= 2]
+    orbits = {}
+    for i, t in enumerate(offs):
+        orbits.setdefault(tuple(sorted(map(abs, t))), []).append(i)
+    assert len(orbits) == 16
+    for idx in orbits.values():
+        assert np.max(np.abs(sv[idx] - sv[idx[0]])) <= 1e-12 * sv[idx[0]][0]
+
+
 @pytest.mark.parametrize("p", [4, 6])
 def test_stage2_spectra_invariant_under_cube_symmetries(p):
     # cube surfaces: offsets in one orbit of the 48 axis permutations and

@@ -175,6 +175,23 @@ def test_m2l_class_transpose_symmetry():
         assert np.allclose(ops.K[mt], ops.K[t].T, rtol=1e-14, atol=0)
 
 
+@pytest.mark.parametrize("mode", ["dense", "svd"])
+def test_m2l_spectra_invariant_under_cube_symmetries(mode):
+    # Cube surfaces: an axis permutation or reflection g of the offset t maps
+    # K^(t) onto K^(g t) by permutations of the surface points (dense), and
+    # the compressed K~ by orthogonal maps of the compressed space, so the
+    # singular values agree within each of the 16 orbits of sorted |t_a|.
+    ops = ops_cached(4, 1e-6, 64, mode)
+    orbits = {}
+    for t in offset_classes():
+        sv = np.linalg.svd(ops.K[t], compute_uv=False)
+        orbits.setdefault(tuple(sorted(map(abs, t))), []).append(sv)
+    assert len(orbits) == 16
+    for svs in orbits.values():
+        for sv in svs[1:]:
+            assert np.max(np.abs(sv - svs[0])) <= 1e-12 * svs[0][0]
+
+
 # ---------------------------------------------------------------- FMM
 def test_fmm_single_leaf_is_direct():
     x = workloads.uniform_cube(50, 7)
