@@ -58,7 +58,12 @@ struct kifmm_plan_s {
     std::vector<GGSched> h_up, h_down;   // indexed by target level
     // device schedules
     DevSched d_leafup, d_leafdown, d_m2l;
-    DevSched d_s2a, d_s2b;   // stage-2 M2L: w = V^ q per chunk slot, then p += scale U^ w
+    // stage-2 M2L: w = V^ q per chunk slot (d_s2a), then p += scale U^ w, as
+    // launches over tile ranges (d_s2b), each reading the W rows of its own
+    // slots from byte offset s2b_xoff[r] of W
+    DevSched d_s2a;
+    std::vector<DevSched> d_s2b;
+    std::vector<size_t> s2b_xoff;
     std::vector<DevSched> d_up, d_down;
     // device data
     void* pts = nullptr;
@@ -337,21 +342,21 @@ int upload_tables(kifmm_plan_s* pl, Uploader& up) {
 // Device schedules and buffer of the stage-2 M2L (Sec. 3.2), from the M2L
 // schedule (same tiles and chunks): phase A writes w = V^ q of every pair into
 // its own chunk slot (direct form: one output row per slot), phase B adds
-// scale * U^ w into the targets. Word 1 of the chunk metadata carries, above
-// the block count, the 16-blocks of the class's rank (phase A: rows of V^;
-// phase B: K-chunks of U^); the rank of a class and of its negation are
-// equal up to rounding at the cutoff, and the larger one is used for both.
+// scale * U^ w into the targets. Phase B reads W through 32-bit buffer
+// offsets, so it runs as launches over consecutive tile ranges whose W rows
+// each span less than 2 GiB, with slot numbers relative to the range. Word 1
+// of the chunk metadata carries, above the block count, the 16-blocks of the
+// class's rank (phase A: rows of V^; phase B: K-chunks of U^); the rank of a
+// class and of its negation are equal up to rounding at the cutoff, and the
+// larger one is used for both.
 void upload_stage2(kifmm_plan_s* pl, Uploader& up) {
     const GGSched& s = pl->h_m2l;
     const int nch = s.n_chunks();
     if (nch == 0) return;
     const HostOps& o = pl->ops;
-    const int64_t wbytes = (int64_t)nch * 32 * pl->rp * pl->elt;
-    if (wbytes >= ((int64_t)1 << 31)) {
-        up.err = KIFMM_EINVAL;
-        up.msg = "stage-2 product buffer exceeds 2 GiB (" + std::to_string(wbytes) + " bytes): use c2 = 0";
-        return;
-    }
+    const int64_t row_bytes = (int64_t)pl->rp * pl->elt;          // one W row (slot x rhs)
+    const int64_t slot_bytes = (int64_t)pl->R * row_bytes;
+    const int64_t wbytes = (int64_t)nch * s.cp * slot_bytes;
     DevSched a = upload_sched(up, s, pl->elt);
     if (up.err != KIFMM_OK) return;
     std::vector<int32_t> meta((size_t)4 * nch, 0), slot(s.chunk_src.size(), -1);
@@ -369,18 +374,53 @@ void upload_stage2(kifmm_plan_s* pl, Uploader& up) {
     }
     for (size_t i = 0; i < slot.size(); ++i)
         if (s.chunk_src[i] >= 0) slot[i] = (int32_t)i;
+    // tile ranges of phase B: the W rows of a range's slots stay below 2 GiB,
+    // and its slot numbers below 2^24 (the kernel's 24-bit row multiply)
+    const int64_t lim = ((int64_t)1 << 31) - ((int64_t)1 << 20);
+    const int64_t lim_slots = ((int64_t)1 << 24) - 1;
+    auto too_big = [&](int64_t chunks) { return chunks * s.cp * slot_bytes >= lim || chunks * s.cp >= lim_slots; };
+    std::vector<int> rbeg{0};
+    for (int t = 0; t < s.n_tiles(); ++t)
+        if (t > rbeg.back() && too_big(s.tile_chunk0[t + 1] - s.tile_chunk0[rbeg.back()])) rbeg.push_back(t);
+    rbeg.push_back(s.n_tiles());
+    std::vector<int32_t> rel(slot.size(), -1);
+    std::vector<int32_t> rel_max(rbeg.size() - 1, 0);
+    for (size_t r = 0; r + 1 < rbeg.size(); ++r) {
+        const int64_t c0 = s.tile_chunk0[rbeg[r]], c1 = s.tile_chunk0[rbeg[r + 1]];
+        if (too_big(c1 - c0)) {
+            up.err = KIFMM_EINVAL;
+            up.msg = "stage-2: the products of one M2L tile exceed the 32-bit offsets of the kernel";
+            return;
+        }
+        for (int64_t i = c0 * s.cp; i < c1 * s.cp; ++i)
+            if (slot[i] >= 0) {
+                rel[i] = (int32_t)(slot[i] - c0 * s.cp);
+                rel_max[r] = std::max(rel_max[r], rel[i]);
+            }
+    }
     a.chunk_meta = (const int32_t*)up.put(meta);
     const int32_t* dslot = (const int32_t*)up.put(slot);
+    const int32_t* drel = (const int32_t*)up.put(rel);
     DevSched b = a;
     a.direct = true;          // target of a slot = the slot's row of w
     a.unit_scale = true;      // the level scale is applied in phase B
     a.chunk_tgt = dslot;
     b.direct = false;
     b.chunk_tgt = nullptr;
-    b.chunk_src = dslot;      // source of a slot = the slot's row of w
-    b.max_src = (int)slot.size() - 1;
+    b.chunk_src = drel;       // source of a slot = its row of w, from the range's first slot
     pl->d_s2a = a;
-    pl->d_s2b = b;
+    pl->d_s2b.clear();
+    pl->s2b_xoff.clear();
+    for (size_t r = 0; r + 1 < rbeg.size(); ++r) {
+        DevSched br = b;
+        br.n_tiles = rbeg[r + 1] - rbeg[r];
+        br.tile_tgt0 = b.tile_tgt0 + rbeg[r];
+        br.tile_ntgt = b.tile_ntgt + rbeg[r];
+        br.tile_chunk0 = b.tile_chunk0 + rbeg[r];
+        br.max_src = rel_max[r];
+        pl->d_s2b.push_back(br);
+        pl->s2b_xoff.push_back((size_t)((int64_t)s.tile_chunk0[rbeg[r]] * s.cp * slot_bytes));
+    }
     pl->W = up.zeros((size_t)wbytes);
 }
 
@@ -764,8 +804,10 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
         const int MBr = pl->rp / 16;
         KIFMM_HIP(launch_gg(pl->d_s2a, elt, adjoint ? pl->U2tT : pl->V2t, MBr, KPk, pl->rp, pl->k,
                             adjoint ? pl->P : pl->Q, kp, pl->W, pl->rp, R, 0, st));
-        KIFMM_HIP(launch_gg(pl->d_s2b, elt, adjoint ? pl->V2tT : pl->U2t, MBk, MBr, pl->k, pl->rp, pl->W, pl->rp,
-                            adjoint ? pl->Q : pl->P, kp, R, 0, st));
+        for (size_t r = 0; r < pl->d_s2b.size(); ++r)
+            KIFMM_HIP(launch_gg(pl->d_s2b[r], elt, adjoint ? pl->V2tT : pl->U2t, MBk, MBr, pl->k, pl->rp,
+                                static_cast<const char*>(pl->W) + pl->s2b_xoff[r], pl->rp,
+                                adjoint ? pl->Q : pl->P, kp, R, 0, st));
     } else if (far) {
         if (!adjoint)
             KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->P, kp, R, 0, st, pl->b3));

@@ -64,6 +64,35 @@ def test_p8_precision_modes_vs_oracle(shape):
         assert e < tol
 
 
+def test_p8_stage2_products_beyond_2gib():
+    # stage 2 (C2 = 10) at the p=8, eps=1e-8 configuration on the 2^20-point
+    # sphere: k = 234 and ranks up to 84 (padded to 96) make 2.25 GB of
+    # per-pair products in FP32, past the 32-bit offsets of one launch, so the
+    # second phase runs as two launches over tile ranges. Forward against the
+    # dense oracle at the sampled points to the FP32 bar, and the adjoint
+    # (the same ranges over the transposed factors) against the forward: the
+    # operator is symmetric
+    torch = _torch()
+    K = _k()
+    g = json.load(open(os.path.join(HERE, "golden", "p8_samples.json")))
+    x = workloads.sphere_points(g["n"], g["seed"])
+    sig = workloads.sphere_density(x, g["seed"] + 100)
+    gs = g["sphere"]
+    idx = np.asarray(gs["sample"])
+    plan = K.Plan(x, p=g["p"], eps=g["eps"], leaf_size=g["leaf_size"], precision="fp32", c2=10.0)
+    info = plan.info()
+    assert info["k"] == 234 and info["m2l_rank_max"] > 80
+    sd = torch.tensor(sig, dtype=torch.float32, device="cuda:0")
+    fwd = plan.apply(sd).double().cpu().numpy()
+    adj = plan.apply_adjoint(sd).double().cpu().numpy()
+    plan.close()
+    e = rel(fwd[idx], np.asarray(gs["phi_dense"]))
+    print(f"sphere p=8 eps=1e-8 fp32 stage 2 (ranks <= {info['m2l_rank_max']}): rel err vs dense oracle {e:.3e}, "
+          f"adjoint vs forward {rel(adj, fwd):.3e}")
+    assert e < 1e-5
+    assert rel(adj, fwd) < 1e-5
+
+
 # ----------------------------------------------------------------- batching
 def test_24_surfaces_one_graph_and_16_rhs():
     torch = _torch()
