@@ -376,22 +376,17 @@ void upload_stage2(kifmm_plan_s* pl, Uploader& up) {
         if (s.chunk_src[i] >= 0) slot[i] = (int32_t)i;
     // tile ranges of phase B: the W rows of a range's slots stay below 2 GiB,
     // and its slot numbers below 2^24 (the kernel's 24-bit row multiply)
-    const int64_t lim = ((int64_t)1 << 31) - ((int64_t)1 << 20);
-    const int64_t lim_slots = ((int64_t)1 << 24) - 1;
-    auto too_big = [&](int64_t chunks) { return chunks * s.cp * slot_bytes >= lim || chunks * s.cp >= lim_slots; };
-    std::vector<int> rbeg{0};
-    for (int t = 0; t < s.n_tiles(); ++t)
-        if (t > rbeg.back() && too_big(s.tile_chunk0[t + 1] - s.tile_chunk0[rbeg.back()])) rbeg.push_back(t);
-    rbeg.push_back(s.n_tiles());
+    const std::vector<int> rbeg = split_tile_ranges(s.tile_chunk0, s.cp, slot_bytes,
+                                                    ((int64_t)1 << 31) - ((int64_t)1 << 20), ((int64_t)1 << 24) - 1);
+    if (rbeg.empty()) {
+        up.err = KIFMM_EINVAL;
+        up.msg = "stage-2: the products of one M2L tile exceed the 32-bit offsets of the kernel";
+        return;
+    }
     std::vector<int32_t> rel(slot.size(), -1);
     std::vector<int32_t> rel_max(rbeg.size() - 1, 0);
     for (size_t r = 0; r + 1 < rbeg.size(); ++r) {
         const int64_t c0 = s.tile_chunk0[rbeg[r]], c1 = s.tile_chunk0[rbeg[r + 1]];
-        if (too_big(c1 - c0)) {
-            up.err = KIFMM_EINVAL;
-            up.msg = "stage-2: the products of one M2L tile exceed the 32-bit offsets of the kernel";
-            return;
-        }
         for (int64_t i = c0 * s.cp; i < c1 * s.cp; ++i)
             if (slot[i] >= 0) {
                 rel[i] = (int32_t)(slot[i] - c0 * s.cp);

@@ -457,6 +457,22 @@ void build_stage2(HostOps& o, double c2) {
     }
 }
 
+std::vector<int> split_tile_ranges(const std::vector<int32_t>& tile_chunk0, int cp, int64_t slot_bytes,
+                                   int64_t max_bytes, int64_t max_slots) {
+    const int n_tiles = tile_chunk0.empty() ? 0 : (int)tile_chunk0.size() - 1;
+    auto fits = [&](int t0, int t1) {
+        const int64_t slots = (int64_t)(tile_chunk0[t1] - tile_chunk0[t0]) * cp;
+        return slots * slot_bytes < max_bytes && slots < max_slots;
+    };
+    std::vector<int> starts{0};
+    for (int t = 0; t < n_tiles; ++t) {
+        if (!fits(t, t + 1)) return {};
+        if (!fits(starts.back(), t + 1)) starts.push_back(t);
+    }
+    starts.push_back(n_tiles);
+    return starts;
+}
+
 std::vector<int64_t> uniform_cuts(int64_t n_tgt, int tile) {
     std::vector<int64_t> cuts;
     for (int64_t t = 0; t < n_tgt; t += tile) cuts.push_back(t);

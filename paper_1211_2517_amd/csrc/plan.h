@@ -130,4 +130,11 @@ struct TileCost {
 std::vector<int64_t> chunk_cuts(int64_t n_tgt, const int32_t* ptr, const int32_t* cls, const int32_t* group,
                                 int cp, int rhs, int n_tiles, int max_tile, const TileCost& w);
 
+// Consecutive tile ranges of a schedule whose chunk slots (cp per chunk,
+// slot_bytes each) span less than max_bytes and fewer than max_slots per
+// range: the first tile of every range, then the tile count. Each range is
+// the longest that fits, in order. Empty if one tile alone does not fit.
+std::vector<int> split_tile_ranges(const std::vector<int32_t>& tile_chunk0, int cp, int64_t slot_bytes,
+                                   int64_t max_bytes, int64_t max_slots);
+
 }  // namespace kifmm
