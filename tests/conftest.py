@@ -21,7 +21,7 @@ def pytest_collection_modifyitems(config, items):
     except Exception:  # pragma: no cover
         have_gpu = False
     if have_gpu or "gpu" in (config.getoption("markexpr") or "").replace("not gpu", ""):
-        return  # on a GPU machine, or GPU tests asked for explicitly: never skip silently
+        return  # a GPU is present, or GPU tests were asked for explicitly: never skip silently
     skip = pytest.mark.skip(reason="no GPU in this environment")
     for item in items:
         if "gpu" in item.keywords:
