@@ -337,6 +337,20 @@ def test_stage2_ranks_well_below_k():
     assert ranks.max() < ops.k and ranks.mean() < ops.k / 3
 
 
+@pytest.mark.parametrize("p", [4, 6])
+def test_stage2_ranks_fall_with_separation(p):
+    # Fig. 1 shows the ranks spread over the classes; the interaction of two
+    # boxes is smoother the farther apart they are, so the stage-2 rank falls
+    # with |t| (measured correlation about -0.9; offsets next to the near
+    # field need about twice the rank of the far corners)
+    ops = ops2_cached(p, 1e-6, 64, 10.0)
+    t = list(ops.K2)
+    r = np.array([ops.K2[k][0].shape[1] for k in t], dtype=float)
+    d = np.array([np.linalg.norm(k) for k in t])
+    assert np.corrcoef(r, d)[0, 1] < -0.8
+    assert r[d < 2.9].mean() > 2 * r[d >= 4].mean()
+
+
 def test_stage2_transpose_classes():
     # K~^(-t) = K~^(t)^T (R11) has the same singular values, so the factored
     # matrices keep the symmetry: K^^(-t) = K^^(t)^T.
