@@ -27,6 +27,10 @@
  *    may be captured in a HIP graph. Applies of one plan must not overlap in
  *    time (they share the plan's workspace): issue them on one stream or
  *    order them with events.
+ *  - Threads: plans may be built, applied and destroyed from several host
+ *    threads at once (process-wide state - the autotuner's cache and the
+ *    kernels' LDS limits - is guarded by locks), but the calls on one plan or
+ *    one group must not run concurrently with each other.
  */
 #ifndef KIFMM_H
 #define KIFMM_H
@@ -195,8 +199,10 @@ int kifmm_plan_export_operator(kifmm_plan_t plan, int which, double* out, int64_
  * PERM = permute-in). The near field runs on a stream of the plan, forked from
  * the caller's stream after the permute and joined back before the far-field
  * evaluation, so its time overlaps the other stages'.
- * Enabled applies cannot be captured in a HIP graph. kifmm_profile(plan, 0/1)
- * switches it and clears the totals. */
+ * Enabled applies cannot be captured in a HIP graph: an apply of such a plan
+ * on a capturing stream, and kifmm_group_apply on a group holding one, return
+ * KIFMM_ESTATE without recording anything. kifmm_profile(plan, 0/1) switches
+ * it and clears the totals. */
 int kifmm_profile(kifmm_plan_t plan, int enable);
 /* Waits for the recorded events and returns the summed milliseconds per stage
  * since profiling was enabled (ms[KIFMM_STAGE_COUNT]) and the number of

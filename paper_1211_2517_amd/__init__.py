@@ -196,6 +196,23 @@ class Plan:
             raise ValueError(f"{name} is on device {x.device.index}, plan on {self.device}")
         return x.contiguous()
 
+    def _check_out(self, out, name, shape):
+        """An output tensor is written in place by the kernels: it must already
+        have the plan's dtype and device, the exact shape and a contiguous
+        layout (no copy is made, so a mismatch is an error)."""
+        torch = _torch()
+        if not isinstance(out, torch.Tensor) or not out.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if out.dtype != self._dtype():
+            raise TypeError(f"{name} must be {self._dtype()} for a {self.precision} plan")
+        if out.device.index != self.device:
+            raise ValueError(f"{name} is on device {out.device.index}, plan on {self.device}")
+        if tuple(out.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(out.shape)}")
+        if not out.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return out
+
     def _stream(self):
         torch = _torch()
         return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
@@ -206,6 +223,10 @@ class Plan:
             raise ValueError(f"sigma must have shape ({self.n},)")
         if out is None:
             out = _torch().empty_like(sigma)
+        else:
+            self._check_out(out, "out", (self.n,))
+        if out.data_ptr() == sigma.data_ptr():
+            raise ValueError("out must not alias sigma")
         _check(self._lib.kifmm_apply(self._h, sigma.data_ptr(), out.data_ptr(), self._stream()))
         return out
 
@@ -215,6 +236,10 @@ class Plan:
             raise ValueError(f"g must have shape ({self.n},)")
         if out is None:
             out = _torch().empty_like(g)
+        else:
+            self._check_out(out, "out", (self.n,))
+        if out.data_ptr() == g.data_ptr():
+            raise ValueError("out must not alias g")
         _check(self._lib.kifmm_apply_adjoint(self._h, g.data_ptr(), out.data_ptr(), self._stream()))
         return out
 
@@ -224,6 +249,14 @@ class Plan:
         if sigma.dim() != 2 or sigma.shape[0] != self.n:
             raise ValueError(f"sigma must have shape ({self.n}, nrhs)")
         nrhs = sigma.shape[1]
+        if not 1 <= nrhs <= self.max_nrhs:
+            raise ValueError(f"nrhs must be in [1, {self.max_nrhs}] (max_nrhs of the plan)")
+        if out is not None:
+            # filled by a copy from the library's column-major result, so any
+            # layout will do; dtype, device and shape must match
+            self._check_vec(out, "out")
+            if tuple(out.shape) != (self.n, nrhs):
+                raise ValueError(f"out must have shape ({self.n}, {nrhs})")
         colmajor = self._check_vec(sigma.t().contiguous(), "sigma")   # (nrhs, N): column-major N x nrhs
         res = torch.empty_like(colmajor)
         _check(self._lib.kifmm_apply_batched(self._h, colmajor.data_ptr(), res.data_ptr(), nrhs, self.n,
@@ -262,10 +295,20 @@ class Group:
         n = len(self._plans)
         if len(sigmas) != n or len(outs) != n:
             raise ValueError("need one sigma and one output per plan")
-        for pl, s, o in zip(self._plans, sigmas, outs):
-            pl._check_vec(s, "sigma")
-            pl._check_vec(o, "out")
-        sp = (ctypes.c_void_p * n)(*[s.data_ptr() for s in sigmas])
+        # the graph captures raw device pointers: every sigma is checked (and
+        # made contiguous, the copy kept alive here until the call returns;
+        # a replay with other pointers re-captures), every out must be exactly
+        # the plan's vector since it is written in place
+        ins = []
+        for i, (pl, s, o) in enumerate(zip(self._plans, sigmas, outs)):
+            s = pl._check_vec(s, f"sigmas[{i}]")
+            if tuple(s.shape) != (pl.n,):
+                raise ValueError(f"sigmas[{i}] must have shape ({pl.n},)")
+            pl._check_out(o, f"outs[{i}]", (pl.n,))
+            if o.data_ptr() == s.data_ptr():
+                raise ValueError(f"outs[{i}] must not alias sigmas[{i}]")
+            ins.append(s)
+        sp = (ctypes.c_void_p * n)(*[s.data_ptr() for s in ins])
         op = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
         _check(self._lib.kifmm_group_apply(self._h, sp, op, self._plans[0]._stream()))
         return outs

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -643,9 +644,15 @@ struct TuneKey {
                std::tie(o.n, o.n_box, o.v_pairs, o.kp, o.elt, o.R, o.num_cu, o.shape);
     }
 };
+// The cache is shared by every plan of the process; plans may be built from
+// several threads, so every access holds tune_mutex().
 std::map<TuneKey, std::pair<int, int>>& tune_cache() {
     static std::map<TuneKey, std::pair<int, int>> c;
     return c;
+}
+std::mutex& tune_mutex() {
+    static std::mutex m;
+    return m;
 }
 
 void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
@@ -653,10 +660,16 @@ void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
     const int shape = pl->opts.m2l_shape;
     const TuneKey key{t.n, t.n_box(), (int64_t)t.v_src.size(), pl->kp, pl->elt, pl->R, pl->num_cu, shape};
     std::vector<std::pair<int, int>> cands;   // (kernel shape, extra rounds)
-    auto it = tune_cache().find(key);
-    if (it != tune_cache().end()) {
-        cands.push_back(it->second);
-    } else {
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lock(tune_mutex());
+        auto it = tune_cache().find(key);
+        if (it != tune_cache().end()) {
+            cands.push_back(it->second);
+            cached = true;
+        }
+    }
+    if (!cached) {
         for (int v = 0; v < kGGVariants; ++v)
             if ((shape < 0 || v == shape) && gg_variant_supported(v, pl->elt))
                 for (int r = 0; r < 3; ++r) cands.push_back({v, r});
@@ -704,7 +717,10 @@ void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(st);
     if (best_ms < 1e29f) {
-        tune_cache()[key] = best;
+        {
+            std::lock_guard<std::mutex> lock(tune_mutex());
+            tune_cache()[key] = best;
+        }
         pl->h_m2l = std::move(best_sched);
         pl->tuned_ms = best_ms;
     }
@@ -730,6 +746,13 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
     const int elt = pl->elt, R = pl->R, kp = pl->kp, nep = pl->nep;
     const int MBk = kp / 16, KPk = kp / 16, MBe = nep / 16, KPe = nep / 16;
     const int64_t nleaf = t.n_leaf();
+    // Profiled applies record timing events that are read back later; an
+    // event recorded inside a stream capture must not be used outside it, so
+    // a profiled plan refuses to be captured.
+    hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
+    KIFMM_HIP(hipStreamIsCapturing(st, &cap_status));
+    if (pl->profiling && cap_status != hipStreamCaptureStatusNone)
+        return fail(KIFMM_ESTATE, "a plan with profiling on cannot be applied inside a stream capture");
     int cur = 0;
     KIFMM_HIP(hipGetDevice(&cur));
     if (cur != pl->device) KIFMM_HIP(hipSetDevice(pl->device));
@@ -759,8 +782,6 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
     // and far fields in one kernel at the end): the fork and join events are
     // also recorded by eager applies, and an event recorded during a capture
     // must not be reused outside it.
-    hipStreamCaptureStatus cap_status = hipStreamCaptureStatusNone;
-    KIFMM_HIP(hipStreamIsCapturing(st, &cap_status));
     const bool fork = far && cap_status == hipStreamCaptureStatusNone;
     if (fork) {
         hipStream_t ns = pl->near_stream;
@@ -1171,6 +1192,10 @@ int kifmm_group_apply(kifmm_group_t g, const void* const* sigma, void* const* ph
     const int np = (int)g->plans.size();
     for (int i = 0; i < np; ++i)
         if (!sigma[i] || !phi[i] || sigma[i] == phi[i]) return fail(KIFMM_EINVAL, "bad sigma/phi pointer");
+    for (int i = 0; i < np; ++i)
+        if (g->plans[i]->profiling)
+            return fail(KIFMM_ESTATE, "plan " + std::to_string(i) +
+                                          " of the group has profiling on; profiled applies cannot be captured");
     hipStream_t st = (hipStream_t)stream;
     bool same = g->exec != nullptr && g->key_stream == st;
     for (int i = 0; same && i < np; ++i) same = g->key_sigma[i] == sigma[i] && g->key_phi[i] == phi[i];

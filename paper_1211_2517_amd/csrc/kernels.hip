@@ -11,7 +11,10 @@
 //                the leaf's points (L2T, Sec. 2.2), scattered to caller order.
 #include "kernels.h"
 
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 
 #ifndef GG_XCD_RUN
 #define GG_XCD_RUN 1
@@ -1088,15 +1091,28 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     }
 }
 
+// Raise the dynamic-LDS limit of kernel `fn` on the current device to at
+// least `lds` bytes (no call below 64 KiB). Safe to call from several
+// threads: the limits already set are kept per (kernel, device) under a lock.
+hipError_t ensure_lds(const void* fn, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, size_t> done;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& cur = done[{fn, dev}];
+    if (lds <= cur) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) cur = lds;
+    return e;
+}
+
 template <typename T, int KP16>
 hipError_t gd_launch_t(const GDParams& p, int blocks, size_t lds, hipStream_t st) {
-    static size_t attr_set = 0;
-    if (lds > 65536 && lds > attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gd_kernel<T, KP16>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = lds;
-    }
+    hipError_t e = ensure_lds(reinterpret_cast<const void*>(&gd_kernel<T, KP16>), lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((gd_kernel<T, KP16>), dim3(blocks), dim3(256), lds, st, p);
     return hipGetLastError();
 }
@@ -1122,13 +1138,8 @@ hipError_t gg_launch_t(const GGParams& p, int blocks, size_t lds, hipStream_t st
     if constexpr (B3 && (KP16 % 2 != 0 || sizeof(T) != 4)) {
         return hipErrorInvalidValue;
     } else {
-        static size_t attr_set = 0;
-        if (lds > 65536 && lds > attr_set) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES, MBW, B3>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            if (e != hipSuccess) return e;
-            attr_set = lds;
-        }
+        hipError_t e = ensure_lds(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES, MBW, B3>), lds);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES, MBW, B3>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
         return hipGetLastError();
     }

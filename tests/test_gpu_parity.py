@@ -41,6 +41,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def maxrel(a, b):
+    """max |a - b| / max |b| (a wrong value at one point is not diluted)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
 def gpu_apply(x, s, p, eps, leaf, precision="fp32", dense=False, adjoint=False, **kw):
     torch = _torch()
     plan = _k().Plan(x, p=p, eps=eps, leaf_size=leaf, precision=precision, dense_m2l=dense, **kw)
@@ -156,10 +163,10 @@ def test_full_size_sphere_sampled():
                                  (False, "fp32", 1e-5, 10.0)):
         got, plan = gpu_apply(x, s, g["p"], g["eps"], g["leaf_size"], precision=prec, dense=dense, c2=c2)
         assert plan.info()["depth"] == g["depth"]
-        e = rel(got[idx], g["phi_dense"])
-        print(f"dense_m2l={dense} {prec} c2={c2} sampled rel err vs fp64 dense oracle {e:.3e}; "
-              f"vs direct {rel(got[idx], g['phi_direct']):.3e}")
-        assert e < tol
+        e, m = rel(got[idx], g["phi_dense"]), maxrel(got[idx], g["phi_dense"])
+        print(f"dense_m2l={dense} {prec} c2={c2} sampled rel err vs fp64 dense oracle {e:.3e} "
+              f"(max {m:.3e}); vs direct {rel(got[idx], g['phi_direct']):.3e}")
+        assert e < tol and m < tol
 
 
 # ------------------------------------------------ stage-2 low rank (Sec. 3.2)
@@ -314,6 +321,94 @@ def test_batched_columns_match_single_applies():
         one = single.apply(Sd[:, j].contiguous()).cpu().numpy()
         assert np.allclose(out[:, j], one, rtol=1e-6, atol=1e-6 * np.abs(one).max())
         assert rel(out[:, j], oracle.fmm(x, S[:, j], 4, 1e-6, 64, ops=oracle_ops(4, 1e-6, 64, "dense"))[0]) < 1e-5
+
+
+# Several right-hand sides per launch at every padded width R (2, 4, 8; a
+# ragged count below the width) and in every precision, each column against
+# the FP64 dense-M2L oracle evaluated on all columns at once. Bounds as for
+# single applies: FP64 1e-8 (operator rounding of the two sides, as in the
+# dense FP64 test), FP32 1e-5, BF16X3 2e-5.
+@pytest.mark.parametrize("precision,max_nrhs,nrhs,tol", [
+    ("fp32", 2, 2, 1e-5), ("fp32", 8, 5, 1e-5), ("fp32", 8, 8, 1e-5),
+    ("fp64", 4, 3, 1e-8), ("bf16x3", 8, 6, 2e-5), ("bf16x3", 2, 1, 2e-5)])
+def test_batched_widths_and_precisions_vs_oracle(precision, max_nrhs, nrhs, tol):
+    torch = _torch()
+    K = _k()
+    x, _ = cube()
+    S = workloads.uniform_density(4096, 31 + nrhs, nrhs=nrhs)
+    want = oracle.fmm(x, S, 6, 1e-6, 64, ops=oracle_ops(6, 1e-6, 64, "dense"))[0]
+    plan = K.Plan(x, p=6, eps=1e-6, leaf_size=64, precision=precision, max_nrhs=max_nrhs)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    got = plan.apply_batched(torch.tensor(S, dtype=dt, device="cuda:0")).double().cpu().numpy()
+    errs = [max(rel(got[:, j], want[:, j]), maxrel(got[:, j], want[:, j])) for j in range(nrhs)]
+    print(f"{precision} R<={max_nrhs} nrhs={nrhs}: worst column error vs oracle {max(errs):.3e}")
+    assert max(errs) < tol
+
+
+# The split-BF16 adjoint multiplies by the split table of the transposed class
+# matrices. Both products carry relative errors of order 2^-16 per entry, so
+# the adjoint identity and adjoint = forward (the FMM operator is symmetric)
+# hold to that level: bound 2e-5, the BF16X3 bar.
+def test_bf16x3_adjoint_identity_and_symmetry():
+    torch = _torch()
+    x, s = cube()
+    g = workloads.uniform_density(4096, 77)
+    plan = _k().Plan(x, p=6, eps=1e-6, leaf_size=64, precision="bf16x3")
+    sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
+    gd = torch.tensor(g, dtype=torch.float32, device="cuda:0")
+    fs = plan.apply(sd).double().cpu().numpy()
+    ftg = plan.apply_adjoint(gd).double().cpu().numpy()
+    fts = plan.apply_adjoint(sd).double().cpu().numpy()
+    ident = abs(g @ fs - ftg @ s) / (np.linalg.norm(g) * np.linalg.norm(fs))
+    sym = rel(fts, fs)
+    want = oracle_phi("cube", 4096, 6, 1e-6, 64, "dense")
+    print(f"bf16x3 adjoint: identity {ident:.3e}, adjoint vs forward {sym:.3e}, adjoint vs oracle {rel(fts, want):.3e}")
+    assert ident < 2e-5 and sym < 2e-5 and rel(fts, want) < 2e-5
+
+
+def test_profiled_plan_refuses_capture():
+    # profiled applies record timing events that must not be captured: a
+    # group holding a profiled plan is refused before any capture begins
+    torch = _torch()
+    K = _k()
+    x, s = cube()
+    plan = K.Plan(x, p=4, eps=1e-6, leaf_size=64)
+    sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
+    out = torch.empty_like(sd)
+    plan.profile(True)
+    grp = K.Group([plan])
+    with pytest.raises(K.KifmmError) as err:
+        grp.apply([sd], [out])
+    assert err.value.code == -5
+    plan.profile(False)
+    grp.apply([sd], [out])
+    torch.cuda.synchronize()
+    assert torch.equal(out, plan.apply(sd))
+
+
+def test_binding_rejects_bad_outputs():
+    # outputs are written in place by the kernels: wrong shape, dtype or a
+    # strided view is an error, raised before anything is launched
+    torch = _torch()
+    K = _k()
+    x, s = cube()
+    plan = K.Plan(x, p=4, eps=1e-6, leaf_size=64)
+    sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
+    for bad, exc in ((torch.empty(4095, device="cuda:0"), ValueError),
+                     (torch.empty(4096, dtype=torch.float64, device="cuda:0"), TypeError),
+                     (torch.empty(8192, device="cuda:0")[::2], ValueError),
+                     (torch.empty(4096), TypeError)):
+        with pytest.raises(exc):
+            plan.apply(sd, out=bad)
+        with pytest.raises(exc):
+            plan.apply_adjoint(sd, out=bad)
+    with pytest.raises(ValueError):
+        plan.apply(sd, out=sd)
+    grp = K.Group([plan])
+    with pytest.raises(ValueError):
+        grp.apply([sd[:100]], [torch.empty_like(sd)])
+    with pytest.raises(ValueError):
+        grp.apply([sd], [torch.empty(4095, device="cuda:0")])
 
 
 # ------------------------------------------------------------- edge cases
