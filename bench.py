@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KIFMM matvec ms + M2L MFMA util at N=1M p=6: SVD-M2L vs dense-M2L, same acc"
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_BF16_MFMA_TFLOPS = 2500.0
+M2L_KERNEL = "gg_kernel (M2L, compressed, FP32 MFMA)"
 N, P, EPS, LEAF = 1 << 20, 6, 1e-6, 64
 STAGE2_C2 = 10.0   # C2 of the stage-2 plan (Sec. 3.2; the paper uses 10 and 100)
 
@@ -35,24 +37,37 @@ def log(msg):
 
 
 def time_plan(plan, sd, out, steps, warmup):
+    """Time `steps` applies (after `warmup`), each bracketed by events on the
+    stream the library launches on (torch's current stream): mean, median,
+    min and max per step. A second, profiled pass of the same length records
+    the library's per-stage HIP events (on the launch streams) for the stage
+    breakdown and the M2L kernel time; it is kept out of the timed pass."""
     import torch
     for _ in range(warmup):
         plan.apply(sd, out)
     torch.cuda.synchronize()
-    plan.profile(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record()
-    for _ in range(steps):
+    for a, b in ev:
+        a.record()
         plan.apply(sd, out)
+        b.record()
     stop.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    timing = {"mean": start.elapsed_time(stop) / steps, "median": per[len(per) // 2], "min": per[0],
+              "max": per[-1]}
+    plan.profile(True)
+    for _ in range(steps):
+        plan.apply(sd, out)
     stage_ms, calls = plan.profile_read()
     plan.profile(False)
-    return start.elapsed_time(stop) / steps, wall, {k: v / calls for k, v in stage_ms.items()}
+    return timing, wall, {k: v / calls for k, v in stage_ms.items()}
 
 
 def traffic_record(info):
@@ -68,28 +83,47 @@ def traffic_record(info):
     return rec.get("bytes_per_launch")
 
 
+def trace_record(flops):
+    """The M2L kernel's average duration in the committed rocprofv3 kernel
+    trace of this benchmark (profiles/m2l_trace_sphere1m_p6.json, written from
+    the trace's stats), and the roofline fraction it gives; None if absent or
+    taken on another kernel source."""
+    path = os.path.join(ROOT, "profiles", "m2l_trace_sphere1m_p6.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1211_2517_amd", "csrc", "kernels.hip"), "rb").read()
+    if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    ms = rec["avg_ms"]
+    return {"avg_launch_ms": ms, "frac": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
+            "source": "profiles/m2l_trace_sphere1m_p6.json"}
+
+
 def cpu_baseline():
     """The oracle (FP64, numpy) as it stands, timed on a bounded sample of the
-    workload: the same sphere recipe at N = 2**17 points, dense-M2L KIFMM
-    evaluation only (tree and operators built before the clock starts)."""
+    workload: the same sphere recipe at N = 2**17 points (one level shallower
+    than at 2**20, with the same leaf size), the complete dense-M2L KIFMM evaluation (tree and
+    operators built before the clock starts), with the BLAS pool held to one
+    thread; its box-by-box loops are single-threaded Python, so one core does
+    all of the work. Scaled to N = 2**20 by the O(N) cost of the method."""
     import oracle
     import workloads
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        cores = 1
     n = 1 << 17
     x = workloads.sphere_points(n, workloads.SEED_BASE + 1)
     s = workloads.sphere_density(x, workloads.SEED_BASE + 101)
     tree = oracle.build_tree(x, LEAF)
     ops = oracle.build_operators(P, EPS, LEAF, mode="dense")
-    t0 = time.perf_counter()
-    oracle.fmm(x, s, P, EPS, LEAF, ops=ops, tree=tree)
-    secs = time.perf_counter() - t0
-    return {"value": secs * 1e3 * (N / n), "unit": "ms", "cores": cores, "kind": "oracle",
-            "sample": f"oracle dense-M2L KIFMM (FP64 numpy) on a {n}-point sphere of the same recipe "
-                      f"(p=6, eps=1e-6, leaf 64): {secs:.2f} s, scaled x{N // n} to N=2^20 by the O(N) cost"}
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        oracle.fmm(x, s, P, EPS, LEAF, ops=ops, tree=tree)
+        secs = time.perf_counter() - t0
+    return {"value": secs * 1e3 * (N / n), "unit": "ms", "cores": 1, "kind": "oracle",
+            "sample": f"oracle dense-M2L KIFMM (FP64 numpy, one thread) on a {n}-point sphere of the same "
+                      f"recipe (p=6, eps=1e-6, leaf 64, depth {tree.depth}): {secs:.2f} s, scaled x{N // n} "
+                      f"to N=2^20 by the O(N) cost",
+            "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -100,6 +134,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["svd", "dense64", "dense32", "svd_bf16x3", "svd_stage2"], default=None,
                     help="time one plan only (profiling runs); prints no JSON line")
+    ap.add_argument("--m2l-shape", type=int, default=-1,
+                    help="force the M2L kernel shape (profiling runs; -1 = autotuned)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MB (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -149,7 +185,8 @@ def main():
         if args.only and name != args.only:
             continue
         log(f"plan {name}")
-        plan = K.Plan(x, p=P, eps=EPS, leaf_size=LEAF, precision=prec, dense_m2l=dense, c2=c2)
+        plan = K.Plan(x, p=P, eps=EPS, leaf_size=LEAF, precision=prec, dense_m2l=dense, c2=c2,
+                      m2l_shape=args.m2l_shape if args.only else -1)
         if prec == "fp64":
             sd_run = sd.double()
             out_run = torch.empty_like(sd_run)
@@ -160,12 +197,13 @@ def main():
             f"plan {info['plan_seconds']:.1f}s, M2L tile <= {info['m2l_tile_targets']} targets, "
             f"{info['m2l_tiles']} tiles, kernel shape {info['m2l_variant']}; "
             f"timing {args.steps} steps")
-        ms, wall, stages = time_plan(plan, sd_run, out_run, args.steps, args.warmup)
+        timing, wall, stages = time_plan(plan, sd_run, out_run, args.steps, args.warmup)
+        ms = timing["mean"]
         got = out_run.double().cpu().numpy()[idx]
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         err_direct = float(np.linalg.norm(got - ref_direct) / np.linalg.norm(ref_direct))
         log(f"{name}: {ms:.3f} ms/step, err vs FP64 oracle {err:.2e}, stages {stages}")
-        res[name] = dict(ms=ms, wall=wall, stages=stages, info=info, err=err, err_direct=err_direct)
+        res[name] = dict(ms=ms, timing=timing, wall=wall, stages=stages, info=info, err=err, err_direct=err_direct)
         if c2 > 0:
             # per-class ranks of the stage-2 factors (the distribution of Fig. 1)
             ranks = np.bincount(plan.export_operator(7).astype(np.int64))
@@ -189,9 +227,14 @@ def main():
     info = svd["info"]
     m2l_ms = svd["stages"]["m2l"]
     achieved = info["flops"]["m2l"] / (m2l_ms * 1e-3) / 1e12
-    d32, d64 = res["dense32"], res["dense64"]
+    d32, d64, b3 = res["dense32"], res["dense64"], res["svd_bf16x3"]
     dense_m2l = d32["info"]["flops"]["m2l"] / (d32["stages"]["m2l"] * 1e-3) / 1e12
     dense64_m2l = d64["info"]["flops"]["m2l"] / (d64["stages"]["m2l"] * 1e-3) / 1e12
+    b3_tflops = b3["info"]["flops"]["m2l"] / (b3["stages"]["m2l"] * 1e-3) / 1e12
+
+    def tim(r):
+        return {k: round(v, 4) for k, v in r["timing"].items()}
+
     line = {
         "metric": METRIC,
         "value": round(svd["ms"], 4),
@@ -209,27 +252,37 @@ def main():
                    "n": N, "p": P, "eps": EPS, "leaf_size": LEAF, "depth": info["depth"], "k": info["k"],
                    "n_eq": info["n_eq"], "v_pairs": info["v_pairs"],
                    "p2p_interactions": info["p2p_interactions"]},
-        "dense_m2l_same_acc": {"precision": "fp64", "ms_per_step": round(d64["ms"], 4),
+        "timing_ms": tim(svd),
+        # No FP32 formulation of the uncompressed operators reaches the 1e-5 bar
+        # (their rounding is amplified by the pseudo-inverses), so the
+        # same-accuracy dense baseline runs in FP64: this ratio crosses
+        # precisions. The same-precision (FP32 vs FP32) ratios follow it.
+        "dense_m2l_same_acc": {"precision": "fp64", "ms_per_step": round(d64["ms"], 4), "timing_ms": tim(d64),
                                "err_vs_fp64_dense_oracle": d64["err"],
                                "m2l_tflops": round(dense64_m2l, 3), "stage_ms": {k: round(v, 4) for k, v in d64["stages"].items()}},
-        "speedup_vs_dense_m2l_same_acc": round(d64["ms"] / svd["ms"], 3),
+        "speedup_vs_dense_m2l_fp64_same_acc_cross_precision": round(d64["ms"] / svd["ms"], 3),
         "dense_m2l_fp32": {"ms_per_step": round(d32["ms"], 4), "err_vs_fp64_dense_oracle": d32["err"],
                            "m2l_mfma_util": round(dense_m2l / PEAK_FP32_MFMA_TFLOPS, 4),
                            "stage_ms": {k: round(v, 4) for k, v in d32["stages"].items()}},
-        "m2l_speedup_vs_dense_m2l_fp32": round(d32["stages"]["m2l"] / m2l_ms, 3),
-        "svd_bf16x3": {"ms_per_step": round(res["svd_bf16x3"]["ms"], 4),
-                       "err_vs_fp64_dense_oracle": res["svd_bf16x3"]["err"],
-                       "m2l_ms": round(res["svd_bf16x3"]["stages"]["m2l"], 4)},
+        "speedup_vs_dense_m2l_fp32_same_precision": round(d32["ms"] / svd["ms"], 3),
+        "m2l_speedup_vs_dense_m2l_fp32_same_precision": round(d32["stages"]["m2l"] / m2l_ms, 3),
+        "svd_bf16x3": {"ms_per_step": round(b3["ms"], 4), "timing_ms": tim(b3),
+                       "err_vs_fp64_dense_oracle": b3["err"],
+                       "m2l_ms": round(b3["stages"]["m2l"], 4),
+                       "m2l_speedup_vs_fp32": round(m2l_ms / b3["stages"]["m2l"], 3),
+                       "roofline": {"bound": "mfma", "achieved": round(b3_tflops, 3), "peak": PEAK_BF16_MFMA_TFLOPS,
+                                    "unit": "TFLOP/s", "frac": round(b3_tflops / PEAK_BF16_MFMA_TFLOPS, 4),
+                                    "frac_counting_three_products": round(3 * b3_tflops / PEAK_BF16_MFMA_TFLOPS, 4)}},
         "svd_stage2": stage2_record(res["svd_stage2"]),
         "m2l_mfma_util": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
         "stage_ms": {k: round(v, 4) for k, v in svd["stages"].items()},
         "err_vs_fp64_dense_oracle": svd["err"],
         "fmm_err_vs_direct_sum": {"svd_fp32": svd["err_direct"], "dense_fp64": d64["err_direct"]},
-        "roofline": {"bound": "mfma", "kernel": "gg_kernel (M2L, compressed, FP32 MFMA)",
+        "roofline": {"bound": "mfma", "kernel": M2L_KERNEL,
                      "achieved": round(achieved, 3), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
                      "flops_per_launch": info["flops"]["m2l"], "avg_launch_ms": round(m2l_ms, 4),
-                     "traffic": traffic_record(info)},
+                     "traffic": traffic_record(info), "trace": trace_record(info["flops"]["m2l"])},
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores")

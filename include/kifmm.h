@@ -80,9 +80,9 @@ typedef struct {
                            this many bytes; 0 = no limit */
     int tile_targets;   /* target boxes per M2L work tile; 0 = autotune on the device */
     int m2l_shape;      /* M2L kernel shape (see kifmm_info_t.m2l_variant); -1 = autotuned
-                           (default), 0..3 forces one shape (the tile count is still tuned
+                           (default), 0..5 forces one shape (the tile count is still tuned
                            unless tile_targets > 0); KIFMM_EINVAL if the shape does not
-                           exist in the requested precision */
+                           exist in the requested precision or for the compressed dimension */
     double c2;          /* stage-2 low rank of the compressed M2L matrices (Sec. 3.2): each
                            K~^(t) is replaced by U^ V^ from its SVD, keeping the singular
                            values >= eps2 * Sigma_00 with eps2 = c2 * eps / k (the paper's
@@ -119,9 +119,12 @@ typedef struct {
     int m2l_tile_targets;   /* tile size in use */
     double sigma0;          /* largest singular value of K_fat (svd mode), else 0 */
     double plan_seconds;    /* wall time of the plan call */
-    int m2l_variant;        /* M2L kernel shape in use: 0 = 8 waves x 16 rows per workgroup,
-                               1 = 4 waves x 16 rows, 2 = 4 waves x 16 rows at two workgroups per CU,
-                               3 = 4 waves x 32 rows (FP32 only) */
+    int m2l_variant;        /* M2L kernel shape in use. Gathered columns staged in LDS and shared
+                               by the waves: 0 = 8 waves x 16 rows per workgroup, 1 = 4 waves x 16
+                               rows, 2 = 4 waves x 16 rows at two workgroups per CU, 3 = 4 waves x
+                               32 rows (FP32 only). Row slabs, every wave loading its own operands
+                               (FP32 and BF16X3, k_pad <= 160): 4 = 4 waves x 32 rows, 5 = 8 waves
+                               x 16 rows */
     int m2l_tiles;          /* M2L target tiles (workgroups = tiles x row groups) */
     int m2l_rank_max;       /* stage 2: largest rank of the factored M2L matrices, else 0 */
     double m2l_rank_mean;   /* stage 2: mean rank over the 316 classes, else 0 */

@@ -68,6 +68,7 @@ struct kifmm_plan_s {
     std::vector<DevSched> d_up, d_down;
     // device data
     void* pts = nullptr;
+    void* qpts = nullptr;   // FP32 plans: fixed-point leaf-unit coordinates (near field)
     void* surf = nullptr;
     int32_t* perm = nullptr;
     int32_t* leaf_ptr = nullptr;
@@ -337,6 +338,16 @@ int upload_tables(kifmm_plan_s* pl, Uploader& up) {
     for (int64_t i = 0; i < pl->tree.n; ++i)
         for (int a = 0; a < 3; ++a) pts[4 * i + a] = (T)pl->tree.u[3 * i + a];
     pl->pts = up.put(pts);
+    if (sizeof(T) == 4) {
+        // fixed point for the near field: q = round(u 2^28), |u| <= 1
+        std::vector<int32_t> q(4 * (size_t)pl->tree.n, 0);
+        for (int64_t i = 0; i < pl->tree.n; ++i)
+            for (int a = 0; a < 3; ++a) {
+                const double v = std::nearbyint(pl->tree.u[3 * i + a] * 268435456.0);
+                q[4 * i + a] = (int32_t)std::min(268435456.0, std::max(-268435456.0, v));
+            }
+        pl->qpts = up.put(q);
+    }
     return up.err;
 }
 
@@ -671,7 +682,7 @@ void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
     }
     if (!cached) {
         for (int v = 0; v < kGGVariants; ++v)
-            if ((shape < 0 || v == shape) && gg_variant_supported(v, pl->elt))
+            if ((shape < 0 || v == shape) && gg_variant_supported(v, pl->elt, pl->kp / 16))
                 for (int r = 0; r < 3; ++r) cands.push_back({v, r});
     }
     if (cands.size() == 1) {
@@ -727,6 +738,26 @@ void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
     pl->d_m2l = upload_sched(up, pl->h_m2l, pl->elt);
 }
 
+// Device workspace of one apply: the permuted densities, the check and
+// equivalent surface values of the leaves, the upward (Q~) and downward (P~)
+// coefficients of every box and, in stage-2 plans, the per-pair products.
+// Every element an apply reads is written earlier in the same apply, except
+// the rows of W past a class's rank, which must hold zeros.
+struct Work {
+    void *sig_s = nullptr, *C = nullptr, *E = nullptr, *Q = nullptr, *P = nullptr, *W = nullptr;
+};
+
+Work plan_work(const kifmm_plan_s* pl) {
+    Work w;
+    w.sig_s = pl->sig_s;
+    w.C = pl->C;
+    w.E = pl->E;
+    w.Q = pl->Q;
+    w.P = pl->P;
+    w.W = pl->W;
+    return w;
+}
+
 int check_plan_for_apply(kifmm_plan_t plan) {
     if (!plan) return fail(KIFMM_EINVAL, "plan is NULL");
     if (!plan->on_device) return fail(KIFMM_ESTATE, "plan was built host-only (opts.device = -1)");
@@ -739,7 +770,7 @@ int check_plan_for_apply(kifmm_plan_t plan) {
         if (e_ != hipSuccess) return fail(KIFMM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld, bool adjoint,
+int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int nrhs, int64_t ld, bool adjoint,
                hipStream_t st) {
     const HostTree& t = pl->tree;
     const int L = t.depth;
@@ -772,7 +803,7 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
     };
     // Stages without work still record both events so that every pair is valid.
     KIFMM_HIP(mark(KIFMM_STAGE_PERM, 0));
-    KIFMM_HIP(launch_permute_in(elt, R, t.n, pl->perm, in, ld, nrhs, pl->sig_s, st));
+    KIFMM_HIP(launch_permute_in(elt, R, t.n, pl->perm, in, ld, nrhs, w.sig_s, st));
     KIFMM_HIP(mark(KIFMM_STAGE_PERM, 1));
     const bool far = L >= 2;
     const double rL = t.half_width(L);
@@ -788,7 +819,7 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
         KIFMM_HIP(hipEventRecord(pl->ev_fork, st));
         KIFMM_HIP(hipStreamWaitEvent(ns, pl->ev_fork, 0));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P], ns));
-        KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->near_ptr,
+        KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
                                       pl->near_leaf, pl->near_code, nullptr, pl->surf, pl->ops.n_eq, nep,
                                       1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, ns));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P + 1], ns));
@@ -797,20 +828,20 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 0));
     if (far) {
         // upward (forward) / L2T^T (adjoint): surface evaluation and the leaf GEMM
-        KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->surf, pl->ops.n_eq, nep,
-                                      pl->C, st));
-        KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->k, pl->ops.n_eq, pl->C, nep,
-                            adjoint ? pl->P : pl->Q, kp, R, 0, st));
+        KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, w.sig_s, pl->leaf_ptr, pl->surf, pl->ops.n_eq, nep,
+                                      w.C, st));
+        KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->k, pl->ops.n_eq, w.C, nep,
+                            adjoint ? w.P : w.Q, kp, R, 0, st));
     }
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 0));
     if (far) {
         if (!adjoint) {
             for (int l = L - 1; l >= 2; --l)   // M2M
-                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->Mt, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->Q, kp, R, 0, st));
+                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->Mt, MBk, KPk, pl->k, pl->k, w.Q, kp, w.Q, kp, R, 0, st));
         } else {
             for (int l = L - 1; l >= 2; --l)   // L2L^T: parents at l from children at l+1
-                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->LtT, MBk, KPk, pl->k, pl->k, pl->P, kp, pl->P, kp, R, 0, st));
+                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->LtT, MBk, KPk, pl->k, pl->k, w.P, kp, w.P, kp, R, 0, st));
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 1));
@@ -819,40 +850,40 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
         // stage 2 (Sec. 3.2): w = V^ q per pair, then p += r_l^-1 U^ w
         const int MBr = pl->rp / 16;
         KIFMM_HIP(launch_gg(pl->d_s2a, elt, adjoint ? pl->U2tT : pl->V2t, MBr, KPk, pl->rp, pl->k,
-                            adjoint ? pl->P : pl->Q, kp, pl->W, pl->rp, R, 0, st));
+                            adjoint ? w.P : w.Q, kp, w.W, pl->rp, R, 0, st));
         for (size_t r = 0; r < pl->d_s2b.size(); ++r)
             KIFMM_HIP(launch_gg(pl->d_s2b[r], elt, adjoint ? pl->V2tT : pl->U2t, MBk, MBr, pl->k, pl->rp,
-                                static_cast<const char*>(pl->W) + pl->s2b_xoff[r], pl->rp,
-                                adjoint ? pl->Q : pl->P, kp, R, 0, st));
+                                static_cast<const char*>(w.W) + pl->s2b_xoff[r], pl->rp,
+                                adjoint ? w.Q : w.P, kp, R, 0, st));
     } else if (far) {
         if (!adjoint)
-            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->P, kp, R, 0, st, pl->b3));
+            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->k, pl->k, w.Q, kp, w.P, kp, R, 0, st, pl->b3));
         else
-            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->KtT, MBk, KPk, pl->k, pl->k, pl->P, kp, pl->Q, kp, R, 0, st, pl->b3));
+            KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->KtT, MBk, KPk, pl->k, pl->k, w.P, kp, w.Q, kp, R, 0, st, pl->b3));
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 0));
     if (far) {
         if (!adjoint) {
             for (int l = 3; l <= L; ++l)       // L2L
-                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->Lt, MBk, KPk, pl->k, pl->k, pl->P, kp, pl->P, kp, R, 1, st));
+                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->Lt, MBk, KPk, pl->k, pl->k, w.P, kp, w.P, kp, R, 1, st));
         } else {
             for (int l = 3; l <= L; ++l)       // M2M^T: children at l from parents at l-1
-                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->MtT, MBk, KPk, pl->k, pl->k, pl->Q, kp, pl->Q, kp, R, 1, st));
+                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->MtT, MBk, KPk, pl->k, pl->k, w.Q, kp, w.Q, kp, R, 1, st));
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_L2P, 0));
     if (far) {
         if (!adjoint)
-            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, pl->ops.n_eq, pl->k, pl->P, kp, pl->E, nep, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, pl->ops.n_eq, pl->k, w.P, kp, w.E, nep, R, 0, st));
         else
-            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, pl->ops.n_eq, pl->k, pl->Q, kp, pl->E, nep, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, pl->ops.n_eq, pl->k, w.Q, kp, w.E, nep, R, 0, st));
         if (fork) {
             // far field at the points (L2T), added to the near field
             KIFMM_HIP(hipStreamWaitEvent(st, pl->ev_join, 0));
-            KIFMM_HIP(launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->near_ptr,
-                                          pl->near_leaf, pl->near_code, pl->E, pl->surf, pl->ops.n_eq, nep,
+            KIFMM_HIP(launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
+                                          pl->near_leaf, pl->near_code, w.E, pl->surf, pl->ops.n_eq, nep,
                                           1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
         }
     }
@@ -860,8 +891,8 @@ int run_passes(kifmm_plan_s* pl, const void* in, void* out, int nrhs, int64_t ld
     if (!fork) {
         // near field and (when there is one) far field in one kernel
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
-        KIFMM_HIP(launch_eval_targets(3, elt, R, nleaf, pl->pts, pl->sig_s, pl->leaf_ptr, pl->near_ptr,
-                                      pl->near_leaf, pl->near_code, far ? pl->E : nullptr, pl->surf,
+        KIFMM_HIP(launch_eval_targets(3, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
+                                      pl->near_leaf, pl->near_code, far ? w.E : nullptr, pl->surf,
                                       pl->ops.n_eq, nep, 1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out,
                                       ld, nrhs, st));
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
@@ -935,7 +966,7 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     if (o.device < -1) return fail(KIFMM_EINVAL, "device must be >= -1");
     if (o.m2l_shape < -1 || o.m2l_shape >= kGGVariants)
         return fail(KIFMM_EINVAL, "m2l_shape must be -1 or in [0, " + std::to_string(kGGVariants - 1) + "]");
-    if (o.m2l_shape >= 0 && !gg_variant_supported(o.m2l_shape, o.precision == KIFMM_FP64 ? 8 : 4))
+    if (o.m2l_shape >= 0 && !gg_variant_supported(o.m2l_shape, o.precision == KIFMM_FP64 ? 8 : 4, 1))
         return fail(KIFMM_EINVAL, "m2l_shape " + std::to_string(o.m2l_shape) + " is not available in this precision");
     if (!(o.c2 >= 0.0) || !std::isfinite(o.c2)) return fail(KIFMM_EINVAL, "c2 must be finite and >= 0");
     if (o.c2 > 0.0 && (o.dense_m2l || o.precision == KIFMM_BF16X3))
@@ -973,6 +1004,11 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     if (pl->kp > 19 * 16 || pl->nep > 19 * 16) {
         delete pl;
         return fail(KIFMM_EINVAL, "n_eq too large for the device kernels (p <= 8 supported)");
+    }
+    if (o.m2l_shape >= 0 && !gg_variant_supported(o.m2l_shape, pl->elt, pl->kp / 16)) {
+        delete pl;
+        return fail(KIFMM_EINVAL, "m2l_shape " + std::to_string(o.m2l_shape) +
+                                      " does not support the compressed dimension " + std::to_string(pl->kp));
     }
     if (o.device >= 0) {
         int ndev = 0;
@@ -1049,7 +1085,7 @@ int kifmm_apply(kifmm_plan_t plan, const void* sigma, void* phi, void* stream) {
     if (rc) return rc;
     if (!sigma || !phi) return fail(KIFMM_EINVAL, "sigma and phi must be non-NULL");
     if (sigma == phi) return fail(KIFMM_EINVAL, "sigma and phi must not alias");
-    return run_passes(plan, sigma, phi, 1, plan->tree.n, false, (hipStream_t)stream);
+    return run_passes(plan, plan_work(plan), sigma, phi, 1, plan->tree.n, false, (hipStream_t)stream);
 }
 
 int kifmm_apply_adjoint(kifmm_plan_t plan, const void* g, void* out, void* stream) {
@@ -1057,7 +1093,7 @@ int kifmm_apply_adjoint(kifmm_plan_t plan, const void* g, void* out, void* strea
     if (rc) return rc;
     if (!g || !out) return fail(KIFMM_EINVAL, "g and out must be non-NULL");
     if (g == out) return fail(KIFMM_EINVAL, "g and out must not alias");
-    return run_passes(plan, g, out, 1, plan->tree.n, true, (hipStream_t)stream);
+    return run_passes(plan, plan_work(plan), g, out, 1, plan->tree.n, true, (hipStream_t)stream);
 }
 
 int kifmm_apply_batched(kifmm_plan_t plan, const void* sigma, void* phi, int nrhs, int64_t ld, void* stream) {
@@ -1068,7 +1104,7 @@ int kifmm_apply_batched(kifmm_plan_t plan, const void* sigma, void* phi, int nrh
     if (nrhs < 1 || nrhs > plan->opts.max_nrhs)
         return fail(KIFMM_EINVAL, "nrhs must be in [1, opts.max_nrhs] (" + std::to_string(plan->opts.max_nrhs) + ")");
     if (ld < plan->tree.n) return fail(KIFMM_EINVAL, "ld must be >= n");
-    return run_passes(plan, sigma, phi, nrhs, ld, false, (hipStream_t)stream);
+    return run_passes(plan, plan_work(plan), sigma, phi, nrhs, ld, false, (hipStream_t)stream);
 }
 
 int kifmm_plan_info(kifmm_plan_t plan, kifmm_info_t* info) {
@@ -1218,7 +1254,7 @@ int kifmm_group_apply(kifmm_group_t g, const void* const* sigma, void* const* ph
         hipEventRecord(g->fork, cap);
         for (int i = 0; i < np && rc == KIFMM_OK; ++i) {
             hipStreamWaitEvent(g->side[i], g->fork, 0);
-            rc = run_passes(g->plans[i], sigma[i], phi[i], 1, g->plans[i]->tree.n, false, g->side[i]);
+            rc = run_passes(g->plans[i], plan_work(g->plans[i]), sigma[i], phi[i], 1, g->plans[i]->tree.n, false, g->side[i]);
             hipEventRecord(g->join[i], g->side[i]);
             hipStreamWaitEvent(cap, g->join[i], 0);
         }

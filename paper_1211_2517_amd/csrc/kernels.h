@@ -47,15 +47,24 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
                      const void* X, int ldx, void* Y, int ldy, int R, int accumulate, hipStream_t st,
                      bool b3 = false);
 
-// Kernel shapes (one 16-row block per wave; chunks hold 32 / R pairs):
+// Kernel shapes (chunks hold 32 / R pairs). Staged forms (gg_kernel: the
+// gathered columns are staged in LDS and shared by the waves, one barrier per
+// chunk), one 16-row block per wave unless stated:
 //   0 = 8 waves (128 output rows per workgroup), all of a CU's LDS;
 //   1 = 4 waves (64 rows), all of a CU's LDS;
 //   2 = 4 waves (64 rows), half of a CU's LDS, so two workgroups share a CU;
 //   3 = 4 waves with two 16-row blocks each (128 rows), all of a CU's LDS,
 //       one wave per SIMD (FP32 only).
-constexpr int kGGVariants = 4;
-// Whether shape `variant` exists for element size `elt` (4 or 8 bytes).
-bool gg_variant_supported(int variant, int elt);
+// Row-slab forms (rs_kernel: every wave loads its operands itself and owns
+// its rows of the accumulator, no barrier; FP32 data, K up to 160):
+//   4 = 4 waves with two 16-row blocks each (128 rows), one wave per SIMD;
+//   5 = 8 waves (128 rows), two waves per SIMD.
+constexpr int kGGVariants = 6;
+// Whether shape `variant` exists for element size `elt` (4 or 8 bytes) and
+// K dimension kp16 * 16.
+bool gg_variant_supported(int variant, int elt, int kp16);
+// Whether the shape stages the gathered columns in LDS.
+bool gg_variant_staged(int variant);
 // Output rows per workgroup of a shape (0 for an unknown shape).
 int gg_variant_rows(int variant);
 // Workgroups of a shape that run on one CU at a time.
@@ -82,7 +91,11 @@ hipError_t launch_eval_surface(int elt, int R, int64_t n_leaf, const void* pts, 
 //   far(i)  = far_scale  * sum_a E[(leaf*R+r)*nep + a] / |u_i - surf_a|
 // mode 1: out[perm[i] + r*ld] = near(i); mode 2: out[...] += far(i) (E must
 // not be null); mode 3: out[...] = near(i) + far(i) (far omitted if E is null).
-hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const void* pts, const void* sig_s,
+// pts: leaf-unit coordinates (4 values per point, the last unused); qpts (FP32
+// only, modes 1 and 3): the same coordinates in fixed point, 4 int32 per point,
+// round(u * 2^28), for exact near-field differences.
+hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const void* pts, const void* qpts,
+                               const void* sig_s,
                                const int32_t* leaf_ptr, const int32_t* near_ptr,
                                const int32_t* near_leaf, const int32_t* near_code, const void* E,
                                const void* surf, int n_eq, int nep, double near_scale,

@@ -712,6 +712,306 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
     }
 }
 
+// 2-wide load through a buffer resource (the last K-chunk of the trimmed form).
+__device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    typedef int i32x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// Row-slab grouped gather GEMM (FP32 data; FP32 MFMA, or split BF16 with B3):
+// the product of gg_kernel, Y[t] (+)= scale * sum_chunks A[cls] X[src], on the
+// same tiles, chunks and workgroup-to-XCD mapping, organised so that the waves
+// of a workgroup never wait for each other.
+//
+// Wave w owns MBW 16-row blocks of the row group and, in the LDS accumulator,
+// those rows of every target column of the tile; it walks the tile's chunks
+// on its own. For each chunk it takes its rows of A[cls] and the chunk's
+// gathered source columns straight from memory into MFMA operand registers
+// (no staging in LDS), and adds its 16*MBW x 32 product into its own rows of
+// the accumulator. Waves share no LDS words, so the kernel has no barrier; the
+// four waves' gathers of a chunk meet in the CU's vector L1.
+//
+// Pipeline: the operands of chunk c+1 are loaded while the MFMAs of chunk c
+// run, K-chunk by K-chunk into the registers that K-chunk t of chunk c has just
+// finished with (one register set). Chunk metadata, source rows and target
+// columns are vector loads issued one to three chunks ahead, in two register
+// sets by chunk parity, so every value stays in the register its load wrote
+// and every iteration issues the same loads in the same order (the waits then
+// retire exactly the loads that are needed).
+//
+// Operand layout (v_mfma_f32_16x16x4f32): lane l = 16 g + j supplies A[j][kk]
+// and B[kk][j]; in K-chunk t the lane's 4-vector holds k = 16 t + 4 g + e for
+// the MFMA steps e = 0..3. TAIL8: the data end within 8 of the last K-chunk's
+// start, so that K-chunk is read as 2-vectors (k = 16 t + 2 g + e, e = 0, 1)
+// and takes two MFMA steps instead of four.
+// B3: A holds per row and 32-wide K-chunk c the 32 high BF16 parts, then the
+// 32 low parts; register K-chunks (2c, 2c+1) are (hi, lo) of A's chunk c, and
+// the lane's 8 gathered FP32 values k = 32 c + 8 g + i (i = 0..7, two
+// 4-vectors) are split into BF16 high and low parts in registers; each 32-wide
+// chunk is three v_mfma_f32_16x16x32_bf16 (hi*hi + hi*lo + lo*hi).
+template <int KP16, int WAVES, int MBW, bool B3, bool TAIL8>
+__global__ void __launch_bounds__(64 * WAVES, 1) rs_kernel(GGParams p) {
+    static_assert(!B3 || (KP16 % 2 == 0 && !TAIL8), "split BF16 needs 32-wide K-chunks");
+    using V4 = f32x4;
+    constexpr int ROWS = WAVES * MBW * 16;
+    constexpr int LDL = ROWS + 4;                // LDS stride of one accumulator column
+    constexpr int KF = TAIL8 ? KP16 - 1 : KP16;  // K-chunks read as 4-vectors
+    const int bid = blockIdx.x;
+    const int kx = bid >> 3;
+    const int rg = kx % p.n_rg;
+    const int qq = kx / p.n_rg;
+    const int tile = ((qq / p.xcd_run) * 8 + (bid & 7)) * p.xcd_run + qq % p.xcd_run;
+    if (tile >= p.n_tiles) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float* acc = reinterpret_cast<float*>(smem_raw);   // [ncol][LDL]
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int mb_lo = rg * WAVES * MBW;
+    const int nmb = min(WAVES * MBW, p.MB - mb_lo);
+    // waves without output rows have nothing to do (there is no barrier)
+    if (wave * MBW >= nmb) return;
+    const int wr0 = wave * MBW * 16;                   // first row of this wave in the group
+    const int wrows = min(MBW * 16, nmb * 16 - wr0);   // its rows that hold output
+    const int R = p.R;
+    const int cp = p.cp;
+    const int t0 = uload<int32_t>(p.tile_tgt0, tile);
+    const int ncol = uload<int32_t>(p.tile_ntgt, tile) * R;
+    const int cb = uload<int32_t>(p.tile_chunk0, tile);
+    const int ce = uload<int32_t>(p.tile_chunk0, tile + 1);
+    float* __restrict__ Y = static_cast<float*>(p.Y);
+    const int64_t ybase = (int64_t)t0 * R;
+    const int row0 = mb_lo * 16;
+    const int pieces = wrows / 4;
+    for (int idx = lane; idx < ncol * pieces; idx += 64) {
+        const int col = idx / pieces;
+        const int r = wr0 + 4 * (idx - col * pieces);
+        V4 v = V4{0, 0, 0, 0};
+        if (p.accumulate) v = *reinterpret_cast<const V4*>(Y + (ybase + col) * p.ldy + row0 + r);
+        *reinterpret_cast<V4*>(acc + col * LDL + r) = v;
+    }
+
+    if (cb < ce) {
+        const int j = lane & 15;
+        const int g = lane >> 4;
+        const __amdgpu_buffer_rsrc_t rx = make_rsrc(p.X, p.x_bytes);
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(p.A, p.a_bytes);
+        const __amdgpu_buffer_rsrc_t rm = make_rsrc(p.chunk_meta, p.meta_bytes);
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(p.chunk_src, p.list_bytes);
+        const __amdgpu_buffer_rsrc_t rc = make_rsrc(p.chunk_col, p.list_bytes);
+        // lane byte offsets of K-chunk t: A (both forms) and B (gathered columns)
+        auto koff_a = [&](int t) -> uint32_t { return (uint32_t)(64 * t + 16 * g); };
+        auto koff_b = [&](int t) -> uint32_t {
+            return B3 ? (uint32_t)(128 * (t >> 1) + 32 * g + 16 * (t & 1)) : (uint32_t)(64 * t + 16 * g);
+        };
+        // K pieces wholly past a_cols hold zeros in A and X: not read
+        auto kvalid = [&](int t) { return B3 ? true : (16 * t + 4 * g < p.a_cols); };
+        const uint32_t ktail = (uint32_t)(64 * (KP16 - 1) + 8 * g);
+        const bool tvalid = 16 * (KP16 - 1) + 2 * g < p.a_cols;
+        uint32_t arow[MBW];
+#pragma unroll
+        for (int m = 0; m < MBW; ++m) {
+            const int row = row0 + wr0 + 16 * m + j;
+            arow[m] = row < p.a_rows ? (uint32_t)(row * p.lda * 4) : kOffNone;
+        }
+        const uint32_t a_cls_bytes = (uint32_t)(p.a_stride * 4);
+        const uint32_t xrow_bytes = (uint32_t)(R * p.ldx * 4);
+        // column 16 bb + j of a chunk: pair pj[bb] of the chunk, right-hand side rh[bb]
+        int pj[2], rh[2];
+        uint32_t xcol[2];
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+            pj[bb] = (16 * bb + j) / R;
+            rh[bb] = 16 * bb + j - pj[bb] * R;
+            xcol[bb] = (uint32_t)(rh[bb] * p.ldx * 4);
+        }
+        struct Ring {
+            int src[2];   // source rows of a chunk (columns 16 bb + j)
+            int col[2];   // target columns of a chunk
+            int meta;     // metadata word (lane & 3) of a chunk
+        };
+        Ring ring[2];
+        auto clampc = [&](int ch) { return min(max(ch, cb), ce - 1); };
+        auto load_src = [&](int ch, int (&dst)[2]) {
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) dst[bb] = bload1(rs, 4 * pj[bb], 4 * ch * cp);
+        };
+        auto load_col = [&](int ch, int (&dst)[2]) {
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) dst[bb] = bload1(rc, 4 * pj[bb], 4 * ch * cp);
+        };
+        auto load_meta = [&](int ch) { return bload1(rm, 4 * (lane & 3), 16 * ch); };
+        int cls_n, nb_c, nb_n;
+        float sc_c, sc_n;
+        auto unpack = [&](int v, int& cls, int& nb, float& sc) {
+            cls = __builtin_amdgcn_readlane(v, 0);
+            nb = __builtin_amdgcn_readlane(v, 1);
+            sc = __int_as_float(__builtin_amdgcn_readlane(v, 2));
+        };
+        // operand registers of the chunk whose MFMAs run next
+        V4 a[MBW][KF];
+        V4 bq[2][KF];
+        float2 at[TAIL8 ? MBW : 1], bt[TAIL8 ? 2 : 1];
+        // pipeline fill: the loop starts two chunks early (those iterations
+        // load and compute nothing new; chunk indices are clamped into the tile)
+        {
+            int v0 = load_meta(cb);
+            ring[0].meta = v0;
+            ring[1].meta = 0;
+            load_src(cb, ring[1].src);
+            ring[0].src[0] = ring[0].src[1] = -1;
+            ring[0].col[0] = ring[0].col[1] = ring[1].col[0] = ring[1].col[1] = -1;
+            __builtin_amdgcn_s_waitcnt(0x0F70);
+            unpack(v0, cls_n, nb_n, sc_n);
+            nb_c = 0;
+            sc_c = 0.f;
+        }
+        // one iteration: the MFMAs of chunk ch (operands in a/bq), the loads of
+        // chunk ch+1's operands, then the accumulation of chunk ch.
+        auto step = [&](int ch, Ring& cur, Ring& oth) {
+            const bool on = ch >= cb && ch < ce;
+            const bool two = on && (nb_c & 0xff) > 1;
+            const float scale = sc_c;
+            V4 d[MBW][2][2];
+#pragma unroll
+            for (int m = 0; m < MBW; ++m)
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb) d[m][bb][0] = d[m][bb][1] = V4{0, 0, 0, 0};
+            const uint32_t aso = (uint32_t)cls_n * a_cls_bytes;   // class of chunk ch+1
+            uint32_t bro[2];
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb)
+                bro[bb] = oth.src[bb] < 0 ? kOffNone : (uint32_t)__umul24((uint32_t)oth.src[bb], xrow_bytes) + xcol[bb];
+            auto small_loads = [&]() {
+                load_src(clampc(ch + 2), cur.src);
+                load_col(clampc(ch + 1), oth.col);
+                oth.meta = load_meta(clampc(ch + 3));
+            };
+            if constexpr (B3) {
+#pragma unroll
+                for (int c2 = 0; c2 < KP16 / 2; ++c2) {
+                    const int t = 2 * c2;
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (on) {
+                        f32x4 bh[2], bl[2];
+#pragma unroll
+                        for (int bb = 0; bb < 2; ++bb) {
+                            uint2 h0, l0, h1, l1;
+                            split_bf16(bq[bb][t], h0, l0);
+                            split_bf16(bq[bb][t + 1], h1, l1);
+                            bh[bb] = __builtin_bit_cast(f32x4, uint4{h0.x, h0.y, h1.x, h1.y});
+                            bl[bb] = __builtin_bit_cast(f32x4, uint4{l0.x, l0.y, l1.x, l1.y});
+                        }
+                        if (two) {
+#pragma unroll
+                            for (int m = 0; m < MBW; ++m) {
+                                mfma_b3x(a[m][t], a[m][t + 1], bh[0], bl[0], d[m][0][0], d[m][0][1]);
+                                mfma_b3x(a[m][t], a[m][t + 1], bh[1], bl[1], d[m][1][0], d[m][1][1]);
+                            }
+                        } else {
+#pragma unroll
+                            for (int m = 0; m < MBW; ++m)
+                                mfma_b3x(a[m][t], a[m][t + 1], bh[0], bl[0], d[m][0][0], d[m][0][1]);
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int u = t; u < t + 2; ++u) {
+#pragma unroll
+                        for (int m = 0; m < MBW; ++m) a[m][u] = bload4<float>(ra, arow[m] + koff_a(u), aso);
+#pragma unroll
+                        for (int bb = 0; bb < 2; ++bb) bq[bb][u] = bload4<float>(rx, bro[bb] + koff_b(u), 0);
+                    }
+                    if (c2 == 0) small_loads();
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < KF; ++t) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (two) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+#pragma unroll
+                            for (int m = 0; m < MBW; ++m) {
+                                d[m][0][e & 1] = Mfma<float>::step(a[m][t][e], bq[0][t][e], d[m][0][e & 1]);
+                                d[m][1][e & 1] = Mfma<float>::step(a[m][t][e], bq[1][t][e], d[m][1][e & 1]);
+                            }
+                    } else if (on) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+#pragma unroll
+                            for (int m = 0; m < MBW; ++m)
+                                d[m][0][e & 1] = Mfma<float>::step(a[m][t][e], bq[0][t][e], d[m][0][e & 1]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    const bool kv = kvalid(t);
+#pragma unroll
+                    for (int m = 0; m < MBW; ++m)
+                        a[m][t] = bload4<float>(ra, kv ? arow[m] + koff_a(t) : kOffNone, aso);
+#pragma unroll
+                    for (int bb = 0; bb < 2; ++bb) bq[bb][t] = bload4<float>(rx, kv ? bro[bb] + koff_b(t) : kOffNone, 0);
+                    if (t == 0) small_loads();
+                }
+                if constexpr (TAIL8) {
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (two) {
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+#pragma unroll
+                            for (int m = 0; m < MBW; ++m) {
+                                d[m][0][e] = Mfma<float>::step(at[m][e], bt[0][e], d[m][0][e]);
+                                d[m][1][e] = Mfma<float>::step(at[m][e], bt[1][e], d[m][1][e]);
+                            }
+                    } else if (on) {
+#pragma unroll
+                        for (int e = 0; e < 2; ++e)
+#pragma unroll
+                            for (int m = 0; m < MBW; ++m) d[m][0][e] = Mfma<float>::step(at[m][e], bt[0][e], d[m][0][e]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int m = 0; m < MBW; ++m) at[m] = bload2(ra, tvalid ? arow[m] + ktail : kOffNone, aso);
+#pragma unroll
+                    for (int bb = 0; bb < 2; ++bb) bt[bb] = bload2(rx, tvalid ? bro[bb] + ktail : kOffNone, 0);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // chunk ch into this wave's rows of the accumulator; empty slots
+            // (column -1) are skipped
+            if (on) {
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb) {
+                    if (bb == 1 && !two) break;
+                    const int col = cur.col[bb];
+                    if (col >= 0) {
+                        float* pc = acc + (col * R + rh[bb]) * LDL + wr0 + 4 * g;
+#pragma unroll
+                        for (int m = 0; m < MBW; ++m) {
+                            V4* q4 = reinterpret_cast<V4*>(pc + 16 * m);
+                            const V4 o = *q4;
+                            V4 r;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) r[e] = __builtin_fmaf(scale, d[m][bb][0][e] + d[m][bb][1][e], o[e]);
+                            *q4 = r;
+                        }
+                    }
+                }
+            }
+            nb_c = nb_n;
+            sc_c = sc_n;
+            unpack(cur.meta, cls_n, nb_n, sc_n);   // chunk ch+2
+        };
+        for (int ch = cb - 2; ch < ce; ch += 2) {
+            step(ch, ring[0], ring[1]);
+            step(ch + 1, ring[1], ring[0]);
+        }
+    }
+    for (int idx = lane; idx < ncol * pieces; idx += 64) {
+        const int col = idx / pieces;
+        const int r = wr0 + 4 * (idx - col * pieces);
+        *reinterpret_cast<V4*>(Y + (ybase + col) * p.ldy + row0 + r) = *reinterpret_cast<const V4*>(acc + col * LDL + r);
+    }
+}
+
 // Grouped GEMM of a schedule in which every target has exactly one pair (the
 // leaf S~ and T~ products, L2L and, in the adjoint, the transposed M2M):
 // nothing is summed across chunks, so a workgroup computes one chunk for all
@@ -931,9 +1231,16 @@ __global__ void __launch_bounds__(256) eval_surface_kernel(int64_t n_leaf, const
 // staged point is one independent load: a batch costs one memory latency. For the far field the wave stages the
 // leaf's downward equivalent surface as (x, y, z, E) vectors the same way
 // (one right-hand side), or reads E from global memory (several).
+// FP32 near field: the points are also given in fixed point, q = round(u 2^28)
+// (int32; |u| <= 1 in leaf units), and the staged sources carry q - 2^29 d, so
+// every coordinate difference of a near pair is an exact integer that is
+// converted to FP32 once: the distance of a nearly coincident pair keeps full
+// FP32 relative accuracy (with FP32 leaf-unit coordinates it would lose the
+// digits the two coordinates share). The 2^28 scale is taken out in the
+// near-field factor.
 template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(256) eval_targets_kernel(
-    int64_t n_leaf, const P4<T>* __restrict__ pts, const T* __restrict__ sig,
+    int64_t n_leaf, const P4<T>* __restrict__ pts, const P4<int32_t>* __restrict__ qpts, const T* __restrict__ sig,
     const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ near_ptr,
     const int32_t* __restrict__ near_leaf, const int32_t* __restrict__ near_code,
     const T* __restrict__ E, const T* __restrict__ surf, int n_eq, int nep, T near_scale,
@@ -941,14 +1248,18 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     constexpr int WPB = 4;
     constexpr int CAP = (R >= 8 ? 64 : R >= 2 ? 128 : 256) / (int)(sizeof(T) / 4);
     constexpr int MAXEQ = 19 * 16;
-    __shared__ P4<T> sp[(MODE & 1) ? WPB : 1][(MODE & 1) ? CAP : 1];
+    constexpr bool FIX = sizeof(T) == 4;   // fixed-point near-field differences
+    using SP = typename std::conditional<FIX, P4<int32_t>, P4<T>>::type;
+    __shared__ SP sp[(MODE & 1) ? WPB : 1][(MODE & 1) ? CAP : 1];
     __shared__ T ss[(MODE & 1) ? WPB : 1][(MODE & 1) && R > 1 ? CAP * R : 1];
     __shared__ P4<T> fs[(MODE & 2) && R == 1 ? WPB : 1][(MODE & 2) && R == 1 ? MAXEQ : 1];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t leaf = (int64_t)blockIdx.x * WPB + wave;
     if (leaf >= n_leaf) return;
-    P4<T>* st = sp[(MODE & 1) ? wave : 0];
+    SP* st = sp[(MODE & 1) ? wave : 0];
+    // fixed-point differences are in units of 2^-28 leaf half-widths
+    const T nscale = (FIX && (MODE & 1)) ? near_scale * T(268435456.0f) : near_scale;
     T* sst = ss[(MODE & 1) ? wave : 0];
     const int p0 = leaf_ptr[leaf];
     const int ne = leaf_ptr[leaf + 1] - p0;
@@ -989,6 +1300,8 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
         const bool valid = tl < ne;
         const int i = p0 + (valid ? tl : 0);
         const P4<T> ui = pts[i];
+        P4<int32_t> qi{0, 0, 0, 0};
+        if constexpr (FIX && (MODE & 1)) qi = qpts[i];
         T acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0;
@@ -997,12 +1310,23 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
             __builtin_amdgcn_wave_barrier();
 #pragma unroll 4
             for (int jj = sub; jj < n; jj += lpt) {
-                const P4<T> f = st[jj];
-                const T dx = ui.x - f.x, dy = ui.y - f.y, dz = ui.z - f.z;
+                const SP f = st[jj];
+                T dx, dy, dz, fw;
+                if constexpr (FIX) {
+                    dx = (T)(qi.x - f.x);
+                    dy = (T)(qi.y - f.y);
+                    dz = (T)(qi.z - f.z);
+                    fw = __int_as_float(f.w);
+                } else {
+                    dx = ui.x - f.x;
+                    dy = ui.y - f.y;
+                    dz = ui.z - f.z;
+                    fw = f.w;
+                }
                 const T r2 = dx * dx + dy * dy + dz * dz;
                 const T rinv = r2 > T(0) ? rsq(r2) : T(0);
                 if constexpr (R == 1) {
-                    acc[0] += f.w * rinv;
+                    acc[0] += fw * rinv;
                 } else {
 #pragma unroll
                     for (int r = 0; r < R; ++r) acc[r] += sst[jj * R + r] * rinv;
@@ -1032,8 +1356,7 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
                 if (slot < cnt) {
                     const int jj = b0 + (sidx - ex);
                     // source shifted into target-leaf units: s - 2 d, d = target - source cube
-                    const T shx = T(2 * (code / 9 - 1)), shy = T(2 * ((code / 3) % 3 - 1)), shz = T(2 * (code % 3 - 1));
-                    const P4<T> sv = pts[jj];
+                    const int dxc = code / 9 - 1, dyc = (code / 3) % 3 - 1, dzc = code % 3 - 1;
                     T w0 = T(0);
                     if constexpr (R == 1) {
                         w0 = sig[jj];
@@ -1041,7 +1364,13 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
 #pragma unroll
                         for (int r = 0; r < R; ++r) sst[slot * R + r] = sig[(int64_t)jj * R + r];
                     }
-                    st[slot] = P4<T>{sv.x - shx, sv.y - shy, sv.z - shz, w0};
+                    if constexpr (FIX) {
+                        const P4<int32_t> sq = qpts[jj];
+                        st[slot] = SP{sq.x - dxc * (1 << 29), sq.y - dyc * (1 << 29), sq.z - dzc * (1 << 29), __float_as_int(w0)};
+                    } else {
+                        const P4<T> sv = pts[jj];
+                        st[slot] = SP{sv.x - T(2 * dxc), sv.y - T(2 * dyc), sv.z - T(2 * dzc), w0};
+                    }
                 }
             }
             consume(cnt);
@@ -1080,11 +1409,11 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
             for (int r = 0; r < R; ++r) {
                 if (r < nrhs) {
                     if constexpr (MODE == 1)
-                        out[dst + r * ld] = near_scale * acc[r];
+                        out[dst + r * ld] = nscale * acc[r];
                     else if constexpr (MODE == 2)
                         out[dst + r * ld] += far_scale * far[r];
                     else
-                        out[dst + r * ld] = near_scale * acc[r] + far_scale * far[r];
+                        out[dst + r * ld] = nscale * acc[r] + far_scale * far[r];
                 }
             }
         }
@@ -1161,9 +1490,46 @@ hipError_t gg_dispatch(int KP16, const GGParams& p, int blocks, size_t lds, hipS
     }
 }
 
+template <int KP16, int WAVES, int MBW, bool B3, bool TAIL8>
+hipError_t rs_launch_t(const GGParams& p, int blocks, size_t lds, hipStream_t st) {
+    if constexpr ((B3 && (KP16 % 2 != 0 || TAIL8)) || (TAIL8 && KP16 < 2)) {
+        return hipErrorInvalidValue;
+    } else {
+        hipError_t e = ensure_lds(reinterpret_cast<const void*>(&rs_kernel<KP16, WAVES, MBW, B3, TAIL8>), lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((rs_kernel<KP16, WAVES, MBW, B3, TAIL8>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
+        return hipGetLastError();
+    }
+}
+
+template <int WAVES, int MBW>
+hipError_t rs_dispatch(int KP16, bool b3, bool tail8, const GGParams& p, int blocks, size_t lds, hipStream_t st) {
+    switch (KP16) {
+#define KIFMM_RS_CASE(K)                                                                  \
+    case K:                                                                               \
+        if (b3) return rs_launch_t<K, WAVES, MBW, true, false>(p, blocks, lds, st);       \
+        if (tail8) return rs_launch_t<K, WAVES, MBW, false, true>(p, blocks, lds, st);    \
+        return rs_launch_t<K, WAVES, MBW, false, false>(p, blocks, lds, st);
+        KIFMM_RS_CASE(1) KIFMM_RS_CASE(2) KIFMM_RS_CASE(3) KIFMM_RS_CASE(4) KIFMM_RS_CASE(5)
+        KIFMM_RS_CASE(6) KIFMM_RS_CASE(7) KIFMM_RS_CASE(8) KIFMM_RS_CASE(9) KIFMM_RS_CASE(10)
+#undef KIFMM_RS_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t gg_variant(int variant, int KP16, const GGParams& p, int blocks, size_t lds, hipStream_t st,
                       bool b3) {
+    if (variant == 4 || variant == 5) {
+        // row-slab form: FP32 data only, K up to 160
+        if constexpr (sizeof(T) == 4) {
+            const bool tail8 = !b3 && KP16 >= 2 && p.a_cols <= 16 * (KP16 - 1) + 8;
+            if (variant == 4) return rs_dispatch<4, 2>(KP16, b3, tail8, p, blocks, lds, st);
+            return rs_dispatch<8, 1>(KP16, b3, tail8, p, blocks, lds, st);
+        }
+        return hipErrorInvalidValue;
+    }
     if (b3) {
         if constexpr (sizeof(T) == 4) {
             switch (variant) {
@@ -1196,19 +1562,27 @@ int gg_variant_rows(int variant) {
         case 1:
         case 2: return 4 * 16;
         case 3: return 4 * 2 * 16;
+        case 4: return 4 * 2 * 16;
+        case 5: return 8 * 16;
         default: return 0;
     }
 }
 
-bool gg_variant_supported(int variant, int elt) {
-    return variant >= 0 && variant < kGGVariants && (variant != 3 || elt == 4);
+bool gg_variant_supported(int variant, int elt, int kp16) {
+    if (variant < 0 || variant >= kGGVariants) return false;
+    if (variant == 3) return elt == 4;
+    if (variant == 4 || variant == 5) return elt == 4 && kp16 <= 10;
+    return true;
 }
+
+bool gg_variant_staged(int variant) { return variant < 4; }
 
 int gg_variant_wgs_per_cu(int variant) { return variant == 2 ? 2 : 1; }
 
 size_t gg_lds_limit(int variant) { return (160 * 1024) / gg_variant_wgs_per_cu(variant); }
 
 int gg_nbuf(int elt, int variant, int KP16) {
+    if (!gg_variant_staged(variant)) return 0;
     const size_t stage = (size_t)32 * (KP16 * 16 + 4) * elt;
     return 2 * stage <= gg_lds_limit(variant) / 2 ? 2 : 1;
 }
@@ -1263,7 +1637,7 @@ hipError_t launch_gg(const DevSched& s, int elt, const void* A, int MB, int KP16
     p.accumulate = accumulate;
     p.n_tiles = s.n_tiles;
     const int mbg = gg_variant_rows(s.variant) / 16;
-    if (!gg_variant_supported(s.variant, elt) || s.cp * R != 32 || s.max_tile < 1) return hipErrorInvalidValue;
+    if (!gg_variant_supported(s.variant, elt, KP16) || s.cp * R != 32 || s.max_tile < 1) return hipErrorInvalidValue;
     p.n_rg = (MB + mbg - 1) / mbg;
     p.nbuf = gg_nbuf(elt, s.variant, KP16);
     p.trash_col = s.max_tile;
@@ -1334,17 +1708,19 @@ hipError_t launch_eval_surface(int elt, int R, int64_t n_leaf, const void* pts, 
     return hipGetLastError();
 }
 
-hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const void* pts, const void* sig_s,
+hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const void* pts, const void* qpts,
+                               const void* sig_s,
                                const int32_t* leaf_ptr, const int32_t* near_ptr, const int32_t* near_leaf,
                                const int32_t* near_code, const void* E, const void* surf, int n_eq, int nep,
                                double near_scale, double far_scale, const int32_t* perm, void* out,
                                int64_t ld, int nrhs, hipStream_t st) {
     if (n_leaf == 0) return hipSuccess;
     if (mode < 1 || mode > 3 || (mode == 2 && E == nullptr)) return hipErrorInvalidValue;
+    if (elt == 4 && (mode & 1) && qpts == nullptr) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n_leaf + 3) / 4));
 #define KIFMM_EVT(TT, M)                                                                                  \
     KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_targets_kernel<TT, RR, M>), grid, dim3(256), 0, st, n_leaf, \
-                                         (const P4<TT>*)pts, (const TT*)sig_s, leaf_ptr, near_ptr, near_leaf, \
+                                         (const P4<TT>*)pts, (const P4<int32_t>*)qpts, (const TT*)sig_s, leaf_ptr, near_ptr, near_leaf, \
                                          near_code, (const TT*)E, (const TT*)surf, n_eq, nep, (TT)near_scale, \
                                          (TT)far_scale, perm, (TT*)out, ld, nrhs))
     if (elt == 4) {

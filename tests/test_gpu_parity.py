@@ -120,6 +120,50 @@ def test_bf16x3_svd_vs_dense_oracle_cube(p):
     assert e < 2e-5
 
 
+# Every M2L kernel shape that exists for FP32 data, forced: the staged shapes
+# (0: 8 waves, 3: 4 waves x 32 rows) and the row-slab shapes (4: 4 waves x 32
+# rows, 5: 8 waves x 16 rows), in FP32 (p = 4 and 6; p = 6 takes the trimmed
+# last K-chunk, k = 119 <= 120) and split BF16, forward and adjoint, one and
+# eight right-hand sides, against the FP64 dense oracle (bars as above).
+@pytest.mark.parametrize("shape", [0, 3, 4, 5])
+@pytest.mark.parametrize("precision,p,tol", [("fp32", 4, 1e-5), ("fp32", 6, 1e-5), ("bf16x3", 6, 2e-5)])
+def test_m2l_shapes_vs_oracle(shape, precision, p, tol):
+    torch = _torch()
+    K = _k()
+    x, s = cube()
+    want = oracle_phi("cube", 4096, p, 1e-6, 64, "dense")
+    plan = K.Plan(x, p=p, eps=1e-6, leaf_size=64, precision=precision, m2l_shape=shape, max_nrhs=8)
+    assert plan.info()["m2l_variant"] == shape
+    sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
+    fwd = plan.apply(sd).double().cpu().numpy()
+    adj = plan.apply_adjoint(sd).double().cpu().numpy()
+    S = workloads.uniform_density(4096, 40 + shape, nrhs=7)
+    wantS = oracle.fmm(x, S, p, 1e-6, 64, ops=oracle_ops(p, 1e-6, 64, "dense"))[0]
+    gotS = plan.apply_batched(torch.tensor(S, dtype=torch.float32, device="cuda:0")).double().cpu().numpy()
+    eb = max(max(rel(gotS[:, j], wantS[:, j]), maxrel(gotS[:, j], wantS[:, j])) for j in range(7))
+    print(f"shape {shape} {precision} p={p}: forward {rel(fwd, want):.3e} (max {maxrel(fwd, want):.3e}), "
+          f"adjoint {rel(adj, want):.3e}, 7 rhs {eb:.3e}")
+    assert rel(fwd, want) < tol and maxrel(fwd, want) < tol
+    assert rel(adj, want) < tol
+    assert eb < tol
+
+
+def test_m2l_row_slab_shapes_sphere_ragged_and_stage2():
+    # many tiles with a ragged tail (tile_targets = 96), and the stage-2 second
+    # phase (K = 48) on the row-slab shapes
+    torch = _torch()
+    K = _k()
+    x, s = sphere(20000)
+    want = oracle_phi("sphere", 20000, 6, 1e-6, 32, "dense")
+    for shape in (4, 5):
+        for c2 in (0.0, 10.0):
+            plan = K.Plan(x, p=6, eps=1e-6, leaf_size=32, tile_targets=96, m2l_shape=shape, c2=c2)
+            got = plan.apply(torch.tensor(s, dtype=torch.float32, device="cuda:0")).double().cpu().numpy()
+            e = rel(got, want)
+            print(f"sphere 20000 shape {shape} c2={c2}: {e:.3e}")
+            assert e < 1e-5 and maxrel(got, want) < 1e-5
+
+
 def test_fp64_dense_gpu_vs_dense_oracle_cube_p6():
     # The uncompressed operators amplify rounding (pseudo-inverse of the
     # check-to-equivalent systems): only FP64 reaches the oracle's accuracy.
@@ -325,9 +369,10 @@ def test_batched_columns_match_single_applies():
 
 # Several right-hand sides per launch at every padded width R (2, 4, 8; a
 # ragged count below the width) and in every precision, each column against
-# the FP64 dense-M2L oracle evaluated on all columns at once. Bounds as for
-# single applies: FP64 1e-8 (operator rounding of the two sides, as in the
-# dense FP64 test), FP32 1e-5, BF16X3 2e-5.
+# the FP64 oracle evaluated on all columns at once: the FP64 plan against the
+# oracle's compressed (svd) mode with the same operators (1e-8: operator
+# rounding of the two sides, as in the dense FP64 test), FP32 (1e-5) and
+# BF16X3 (2e-5) against the dense mode.
 @pytest.mark.parametrize("precision,max_nrhs,nrhs,tol", [
     ("fp32", 2, 2, 1e-5), ("fp32", 8, 5, 1e-5), ("fp32", 8, 8, 1e-5),
     ("fp64", 4, 3, 1e-8), ("bf16x3", 8, 6, 2e-5), ("bf16x3", 2, 1, 2e-5)])
@@ -336,7 +381,8 @@ def test_batched_widths_and_precisions_vs_oracle(precision, max_nrhs, nrhs, tol)
     K = _k()
     x, _ = cube()
     S = workloads.uniform_density(4096, 31 + nrhs, nrhs=nrhs)
-    want = oracle.fmm(x, S, 6, 1e-6, 64, ops=oracle_ops(6, 1e-6, 64, "dense"))[0]
+    mode = "svd" if precision == "fp64" else "dense"
+    want = oracle.fmm(x, S, 6, 1e-6, 64, ops=oracle_ops(6, 1e-6, 64, mode))[0]
     plan = K.Plan(x, p=6, eps=1e-6, leaf_size=64, precision=precision, max_nrhs=max_nrhs)
     dt = torch.float64 if precision == "fp64" else torch.float32
     got = plan.apply_batched(torch.tensor(S, dtype=dt, device="cuda:0")).double().cpu().numpy()
