@@ -153,6 +153,22 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
  *   sigma, phi: device, n elements each, caller order; must not alias. */
 int kifmm_apply(kifmm_plan_t plan, const void* sigma, void* phi, void* stream);
 
+/* As kifmm_apply, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the apply's
+ * workspace - permuted densities, surface values, upward and downward
+ * coefficients, the device memory kifmm_apply takes from the plan - comes
+ * from a static device array of the library (64 MiB, one copy per GPU, held
+ * until the process ends), and the call allocates nothing.
+ *   sigma, phi: device, n elements each, caller order; must not alias.
+ * Every call on one GPU shares that GPU's array, so calls that overlap in time
+ * on one GPU (any plans, any streams) race: serialise them. The array keeps
+ * the last call's contents; nothing in it needs to start at zero.
+ * Errors: KIFMM_EINVAL if the plan's workspace exceeds 64 MiB (see
+ * kifmm_plan_info's n, n_leaf, n_box: about 190 bytes per point at p = 6 and
+ * max_nrhs = 1) or the plan uses stage 2 (c2 > 0); KIFMM_ESTATE if profiling
+ * is on; as kifmm_apply otherwise. */
+int kifmm_apply_noalloc(kifmm_plan_t plan, const void* sigma, void* phi, void* stream);
+
 /* out = F^T g by the transposed passes (L2T^T, L2L^T up the tree, M2L with
  * the transposed class matrices, M2M^T down the tree, S2M^T, S2T^T).
  *   g, out: device, n elements each, caller order; must not alias. */

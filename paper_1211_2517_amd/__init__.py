@@ -28,7 +28,7 @@ EXPORTED_SYMBOLS = (
     "kifmm_opts_default", "kifmm_plan", "kifmm_plan_ex", "kifmm_apply", "kifmm_apply_adjoint",
     "kifmm_apply_batched", "kifmm_group_create", "kifmm_group_apply", "kifmm_group_destroy",
     "kifmm_plan_info", "kifmm_plan_export_tree", "kifmm_plan_export_operator", "kifmm_profile",
-    "kifmm_profile_read", "kifmm_destroy", "kifmm_last_error",
+    "kifmm_profile_read", "kifmm_destroy", "kifmm_last_error", "kifmm_apply_noalloc",
 )
 
 
@@ -80,6 +80,7 @@ def load_library():
     lib.kifmm_plan_ex.argtypes = [P, I64, I, D, I, ctypes.POINTER(_Opts), ctypes.POINTER(V)]
     lib.kifmm_apply.argtypes = [V, P, P, P]
     lib.kifmm_apply_adjoint.argtypes = [V, P, P, P]
+    lib.kifmm_apply_noalloc.argtypes = [V, P, P, P]
     lib.kifmm_apply_batched.argtypes = [V, P, P, I, I64, P]
     lib.kifmm_group_create.argtypes = [ctypes.POINTER(V), I, ctypes.POINTER(V)]
     lib.kifmm_group_apply.argtypes = [V, ctypes.POINTER(P), ctypes.POINTER(P), P]
@@ -228,6 +229,19 @@ class Plan:
         if out.data_ptr() == sigma.data_ptr():
             raise ValueError("out must not alias sigma")
         _check(self._lib.kifmm_apply(self._h, sigma.data_ptr(), out.data_ptr(), self._stream()))
+        return out
+
+    def apply_noalloc(self, sigma, out):
+        """phi = F sigma through kifmm_apply_noalloc: the library allocates
+        nothing (its workspace is a static device array shared by every such
+        call on the GPU). `out` is the caller's preallocated result."""
+        sigma = self._check_vec(sigma, "sigma")
+        if sigma.shape != (self.n,):
+            raise ValueError(f"sigma must have shape ({self.n},)")
+        self._check_out(out, "out", (self.n,))
+        if out.data_ptr() == sigma.data_ptr():
+            raise ValueError("out must not alias sigma")
+        _check(self._lib.kifmm_apply_noalloc(self._h, sigma.data_ptr(), out.data_ptr(), self._stream()))
         return out
 
     def apply_adjoint(self, g, out=None):

@@ -25,6 +25,23 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// Workspace of kifmm_apply_noalloc: a device array of the library, one copy on
+// every GPU the library runs on, held until the process ends. In host code
+// `scratch` names a host-side stand-in, never the device memory: its device
+// address is looked up once per device (scratch_address) and only that
+// address is used.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex& scratch_mutex() {
+    static std::mutex m;
+    return m;
+}
+std::map<int, void*>& scratch_ptrs() {
+    static std::map<int, void*> m;   // device ordinal -> device address of `scratch`
+    return m;
+}
+
 int fail(int code, const std::string& msg) {
     g_last_error = msg;
     return code;
@@ -758,6 +775,47 @@ Work plan_work(const kifmm_plan_s* pl) {
     return w;
 }
 
+// Device address of `scratch` on device `dev`, which must be the current
+// device; looked up with hipGetSymbolAddress on the first call per device.
+int scratch_address(int dev, void** out) {
+    std::lock_guard<std::mutex> lock(scratch_mutex());
+    auto it = scratch_ptrs().find(dev);
+    if (it != scratch_ptrs().end()) {
+        *out = it->second;
+        return KIFMM_OK;
+    }
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+        return fail(KIFMM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    scratch_ptrs()[dev] = ptr;
+    *out = ptr;
+    return KIFMM_OK;
+}
+
+// Workspace of a plan carved out of `base` (256-byte aligned pieces); returns
+// the bytes it needs. With base == nullptr only the size is computed.
+size_t carve_work(const kifmm_plan_s* pl, char* base, Work* w) {
+    const HostTree& t = pl->tree;
+    const size_t elt = pl->elt, R = pl->R;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~size_t(255);
+        return p;
+    };
+    Work v;
+    v.sig_s = take((size_t)t.n * R * elt);
+    if (t.depth >= 2) {
+        v.C = take((size_t)t.n_leaf() * R * pl->nep * elt);
+        v.E = take((size_t)t.n_leaf() * R * pl->nep * elt);
+        v.Q = take((size_t)t.n_box() * R * pl->kp * elt);
+        v.P = take((size_t)t.n_box() * R * pl->kp * elt);
+    }
+    if (w) *w = v;
+    return off;
+}
+
 int check_plan_for_apply(kifmm_plan_t plan) {
     if (!plan) return fail(KIFMM_EINVAL, "plan is NULL");
     if (!plan->on_device) return fail(KIFMM_ESTATE, "plan was built host-only (opts.device = -1)");
@@ -1073,6 +1131,18 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
             return fail(code, msg);
         }
         pl->on_device = true;
+        // the static workspace of kifmm_apply_noalloc on this device
+        int cur2 = 0;
+        hipGetDevice(&cur2);
+        hipSetDevice(o.device);
+        void* sp = nullptr;
+        const int src = scratch_address(o.device, &sp);
+        hipSetDevice(cur2);
+        if (src != KIFMM_OK) {
+            const std::string msg = g_last_error;
+            kifmm_destroy(pl);
+            return fail(src, msg);
+        }
     }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     fill_info(pl, secs);
@@ -1086,6 +1156,30 @@ int kifmm_apply(kifmm_plan_t plan, const void* sigma, void* phi, void* stream) {
     if (!sigma || !phi) return fail(KIFMM_EINVAL, "sigma and phi must be non-NULL");
     if (sigma == phi) return fail(KIFMM_EINVAL, "sigma and phi must not alias");
     return run_passes(plan, plan_work(plan), sigma, phi, 1, plan->tree.n, false, (hipStream_t)stream);
+}
+
+int kifmm_apply_noalloc(kifmm_plan_t plan, const void* sigma, void* phi, void* stream) {
+    int rc = check_plan_for_apply(plan);
+    if (rc) return rc;
+    if (!sigma || !phi) return fail(KIFMM_EINVAL, "sigma and phi must be non-NULL");
+    if (sigma == phi) return fail(KIFMM_EINVAL, "sigma and phi must not alias");
+    if (plan->st2)
+        return fail(KIFMM_EINVAL, "stage-2 plans (c2 > 0) keep per-pair products that must start at zero: use kifmm_apply");
+    if (plan->profiling) return fail(KIFMM_ESTATE, "profiled applies create timing events: use kifmm_apply");
+    const size_t need = carve_work(plan, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return fail(KIFMM_EINVAL, "the plan's workspace (" + std::to_string(need) + " bytes) exceeds the " +
+                                      std::to_string(kScratchBytes) + "-byte static workspace of kifmm_apply_noalloc");
+    int cur = 0;
+    KIFMM_HIP(hipGetDevice(&cur));
+    if (cur != plan->device) KIFMM_HIP(hipSetDevice(plan->device));
+    void* base = nullptr;
+    rc = scratch_address(plan->device, &base);
+    if (cur != plan->device) KIFMM_HIP(hipSetDevice(cur));
+    if (rc) return rc;
+    Work w;
+    carve_work(plan, static_cast<char*>(base), &w);
+    return run_passes(plan, w, sigma, phi, 1, plan->tree.n, false, (hipStream_t)stream);
 }
 
 int kifmm_apply_adjoint(kifmm_plan_t plan, const void* g, void* out, void* stream) {
