@@ -100,6 +100,133 @@ def trace_record(flops):
             "source": "profiles/m2l_trace_sphere1m_p6.json"}
 
 
+def timed_ms(fn, steps, warmup):
+    """Mean ms of `fn` over `steps` calls after `warmup`, by events on torch's
+    current stream (the stream the library launches on)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def rel(a, b):
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def bench_batching(K, steps, warmup):
+    """The batching workload: 24 independent surfaces (sphere, cube surface,
+    torus; N log-uniform in [2^12, 2^19]) at p = 6, eps = 1e-6, leaf 64, as 24
+    eager applies in a row and as one group graph, plus 16 right-hand sides on
+    the largest set; errors against the oracle's sampled potentials."""
+    import numpy as np
+    import torch
+    import workloads
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "batch_samples.json")))
+    sets = workloads.batch_sets(24)
+    big = g["big"]
+    t0 = time.perf_counter()
+    plans = [K.Plan(x, p=6, eps=1e-6, leaf_size=64, max_nrhs=16 if i == big else 1) for i, (x, _) in enumerate(sets)]
+    plan_s = time.perf_counter() - t0
+    sig = [torch.tensor(workloads.uniform_density(x.shape[0], 100 + i), dtype=torch.float32, device="cuda:0")
+           for i, (x, _) in enumerate(sets)]
+    outs = [torch.empty_like(s_) for s_ in sig]
+
+    def eager():
+        for p_, s_, o_ in zip(plans, sig, outs):
+            p_.apply(s_, o_)
+    eager_ms = timed_ms(eager, steps, warmup)
+    grp = K.Group(plans)
+    graph_ms = timed_ms(lambda: grp.apply(sig, outs), steps, warmup)
+    errs = [rel(outs[i].double().cpu().numpy()[np.asarray(gs["sample"])], gs["phi_dense"])
+            for i, gs in enumerate(g["sets"])]
+    S = torch.tensor(workloads.uniform_density(sets[big][0].shape[0], 7, nrhs=16).T.copy(), dtype=torch.float32,
+                     device="cuda:0")   # (16, N): column-major N x 16
+    O = torch.empty_like(S)
+    rhs_ms = timed_ms(lambda: plans[big].apply_batched_colmajor(S, O), steps, warmup)
+    single_ms = timed_ms(lambda: plans[big].apply(sig[big], outs[big]), steps, warmup)
+    out16 = O.t().double().cpu().numpy()[np.asarray(g["sets"][big]["sample"])]
+    want16 = np.asarray(g["sets"][big]["phi_rhs"])
+    err16 = max(rel(out16[:, j], want16[:, j]) for j in range(16))
+    grp.close()
+    for p_ in plans:
+        p_.close()
+    n_total = int(sum(x.shape[0] for x, _ in sets))
+    return {"sets": 24, "points_total": n_total, "plan_seconds_total": round(plan_s, 2),
+            "eager_ms_24_applies": round(eager_ms, 4), "graph_ms": round(graph_ms, 4),
+            "graph_speedup_vs_eager": round(eager_ms / graph_ms, 3),
+            "points_per_s_graph": round(n_total / (graph_ms * 1e-3), 1),
+            "max_err_vs_fp64_dense_oracle": max(errs),
+            "rhs16": {"n": int(sets[big][0].shape[0]), "ms_16_rhs": round(rhs_ms, 4),
+                      "ms_per_rhs": round(rhs_ms / 16, 4), "ms_single_apply": round(single_ms, 4),
+                      "per_rhs_speedup": round(single_ms / (rhs_ms / 16), 3),
+                      "max_err_vs_fp64_dense_oracle": err16}}
+
+
+def bench_precision(K, steps, warmup):
+    """The precision workload: the 2^20 sphere and 2:1:0.5 ellipsoid at p = 8,
+    eps = 1e-8, leaf 64, in FP64, FP32 and split BF16; matvec ms and error
+    against the oracle's sampled potentials."""
+    import numpy as np
+    import torch
+    import workloads
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "p8_samples.json")))
+    out = {}
+    for shape, gen in (("sphere", workloads.sphere_points), ("ellipsoid", workloads.ellipsoid_points)):
+        x = gen(g["n"], g["seed"])
+        sig = workloads.sphere_density(x, g["seed"] + 100)
+        idx = np.asarray(g[shape]["sample"])
+        rec = {}
+        for prec in ("fp64", "fp32", "bf16x3"):
+            dt = torch.float64 if prec == "fp64" else torch.float32
+            plan = K.Plan(x, p=g["p"], eps=g["eps"], leaf_size=g["leaf_size"], precision=prec)
+            sd = torch.tensor(sig, dtype=dt, device="cuda:0")
+            o = torch.empty_like(sd)
+            ms = timed_ms(lambda: plan.apply(sd, o), steps, warmup)
+            e = rel(o.double().cpu().numpy()[idx], g[shape]["phi_dense"])
+            rec[prec] = {"ms_per_matvec": round(ms, 4), "err_vs_fp64_dense_oracle": e, "k": plan.info()["k"]}
+            log(f"p=8 {shape} {prec}: {ms:.3f} ms, err {e:.2e}")
+            plan.close()
+        out[shape] = rec
+    return out
+
+
+def bench_gradient(K, steps, warmup):
+    """The differentiation workload: torus surface N = 262,144 (512 x 256 grid
+    triangle centroids), p = 6, FP32; one gradient of 0.5 |F s - b|^2 is one
+    forward apply and one adjoint apply."""
+    import numpy as np
+    import torch
+    import workloads
+    x = workloads.torus_grid_centroids(512, 256)
+    plan = K.Plan(x, p=6, eps=1e-6, leaf_size=64)
+    rng = np.random.default_rng(11)
+    s0 = torch.tensor(rng.uniform(-1, 1, x.shape[0]), dtype=torch.float32, device="cuda:0")
+    b = plan.apply(torch.tensor(rng.uniform(-1, 1, x.shape[0]), dtype=torch.float32, device="cuda:0"))
+    f = torch.empty_like(s0)
+    gr = torch.empty_like(s0)
+
+    def grad():
+        plan.apply(s0, f)
+        plan.apply_adjoint(f - b, gr)
+    fwd_ms = timed_ms(lambda: plan.apply(s0, f), steps, warmup)
+    adj_ms = timed_ms(lambda: plan.apply_adjoint(s0, gr), steps, warmup)
+    grad_ms = timed_ms(grad, steps, warmup)
+    plan.close()
+    return {"n": int(x.shape[0]), "forward_ms": round(fwd_ms, 4), "adjoint_ms": round(adj_ms, 4),
+            "gradient_ms": round(grad_ms, 4)}
+
+
 def cpu_baseline():
     """The oracle (FP64, numpy) as it stands, timed on a bounded sample of the
     workload: the same sphere recipe at N = 2**17 points (one level shallower
@@ -132,6 +259,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the batching, p = 8 precision and gradient workloads")
     ap.add_argument("--only", choices=["svd", "dense64", "dense32", "svd_bf16x3", "svd_stage2"], default=None,
                     help="time one plan only (profiling runs); prints no JSON line")
     ap.add_argument("--m2l-shape", type=int, default=-1,
@@ -284,6 +413,14 @@ def main():
                      "flops_per_launch": info["flops"]["m2l"], "avg_launch_ms": round(m2l_ms, 4),
                      "traffic": traffic_record(info), "trace": trace_record(info["flops"]["m2l"])},
     }
+    if not args.no_configs:
+        cs, cw = max(3, args.steps // 4), 2
+        log("batching workload (24 surfaces, 16 right-hand sides)")
+        line["batching"] = bench_batching(K, cs, cw)
+        log("precision workload (p = 8, three precisions)")
+        line["precision_p8"] = bench_precision(K, cs, cw)
+        log("differentiation workload (torus gradient)")
+        line["gradient_torus"] = bench_gradient(K, cs, cw)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline()

@@ -281,6 +281,23 @@ class Plan:
             return out
         return res.contiguous()
 
+    def apply_batched_colmajor(self, sigma_cm, out_cm):
+        """Several right-hand sides without layout copies: sigma_cm and out_cm
+        are (nrhs, N) contiguous tensors, i.e. column-major N x nrhs; row j
+        of out_cm receives F sigma_cm[j]."""
+        sigma_cm = self._check_vec(sigma_cm, "sigma_cm")
+        if sigma_cm.dim() != 2 or sigma_cm.shape[1] != self.n:
+            raise ValueError(f"sigma_cm must have shape (nrhs, {self.n})")
+        nrhs = sigma_cm.shape[0]
+        if not 1 <= nrhs <= self.max_nrhs:
+            raise ValueError(f"nrhs must be in [1, {self.max_nrhs}] (max_nrhs of the plan)")
+        self._check_out(out_cm, "out_cm", (nrhs, self.n))
+        if out_cm.data_ptr() == sigma_cm.data_ptr():
+            raise ValueError("out_cm must not alias sigma_cm")
+        _check(self._lib.kifmm_apply_batched(self._h, sigma_cm.data_ptr(), out_cm.data_ptr(), nrhs, self.n,
+                                             self._stream()))
+        return out_cm
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             self._lib.kifmm_destroy(self._h)

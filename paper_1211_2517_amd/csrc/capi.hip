@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -56,13 +57,35 @@ struct DevBuf {
 
 }  // namespace
 
+// Device copies of a plan's operator tables. Plans whose operators, element
+// type, split-BF16 choice and device agree share one copy (see
+// shared_tables); the memory is freed with the last plan that uses it.
+struct DevTables {
+    int device = 0;
+    size_t bytes = 0;
+    std::shared_ptr<const HostOps> ops;   // keeps the cache key's operators alive
+    std::vector<void*> allocs;
+    void *Kt = nullptr, *KtT = nullptr, *Mt = nullptr, *MtT = nullptr, *Lt = nullptr, *LtT = nullptr;
+    void *Sop = nullptr, *SopT = nullptr, *Top = nullptr, *TopT = nullptr;
+    void *V2t = nullptr, *U2t = nullptr, *U2tT = nullptr, *V2tT = nullptr, *surf = nullptr;
+    ~DevTables() {
+        if (allocs.empty()) return;
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(device);
+        for (void* p : allocs) (void)hipFree(p);
+        (void)hipSetDevice(cur);
+    }
+};
+
 struct kifmm_plan_s {
     kifmm_opts_t opts{};
     int p = 0;
     double eps = 0;
     int leaf_size = 0;
     HostTree tree;
-    HostOps ops;
+    std::shared_ptr<const HostOps> ops_sp;   // cached FP64 operators (shared by plans with equal parameters)
+    const HostOps& ops() const { return *ops_sp; }
     int k = 0, kp = 0, nep = 0, R = 1, elt = 4;
     bool b3 = false;    // M2L in split BF16 (KIFMM_BF16X3); all other stages FP32
     bool st2 = false;   // stage-2 low-rank M2L (opts.c2 > 0)
@@ -98,6 +121,7 @@ struct kifmm_plan_s {
     void* W = nullptr;   // stage-2 per-slot products w = V^ q (n_chunks x 32 rows of rp)
     void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
     std::vector<void*> allocs;
+    std::shared_ptr<DevTables> tables;   // operator tables (possibly shared with other plans)
     size_t device_bytes = 0;
     // the near field runs on a stream of its own, forked from and joined back
     // into the caller's stream, so that it overlaps the far-field passes
@@ -151,6 +175,7 @@ struct Uploader {
     int err = KIFMM_OK;
     std::string msg;
     std::vector<void*>* scratch = nullptr;   // when set, allocations go here instead of the plan
+    size_t scratch_bytes = 0;                // bytes allocated into `scratch`
     void* alloc(size_t bytes) {
         if (err != KIFMM_OK) return nullptr;
         if (bytes == 0) bytes = 16;
@@ -169,6 +194,7 @@ struct Uploader {
         }
         if (scratch) {
             scratch->push_back(p);
+            scratch_bytes += bytes;
         } else {
             pl->allocs.push_back(p);
             pl->device_bytes += bytes;
@@ -315,27 +341,27 @@ std::vector<uint16_t> split_blocks(int nblk, int rows, int cols, int rows_pad, i
 }
 
 template <typename T>
-int upload_tables(kifmm_plan_s* pl, Uploader& up) {
-    const HostOps& o = pl->ops;
+void upload_op_tables(const kifmm_plan_s* pl, Uploader& up, DevTables& d) {
+    const HostOps& o = pl->ops();
     const int k = o.k, ne = o.n_eq, kp = pl->kp, nep = pl->nep;
     auto K = [&](int c, int i, int j) { return o.K[((size_t)c * k + i) * k + j]; };
     if (pl->b3) {
-        pl->Kt = up.put(split_blocks(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(c, i, j); }));
-        pl->KtT = up.put(split_blocks(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(neg_class(c), j, i); }));
+        d.Kt = up.put(split_blocks(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(c, i, j); }));
+        d.KtT = up.put(split_blocks(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(neg_class(c), j, i); }));
     } else {
-        pl->Kt = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(c, i, j); }));
-        pl->KtT = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(neg_class(c), j, i); }));
+        d.Kt = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(c, i, j); }));
+        d.KtT = up.put(pad_blocks<T>(NCLASS, k, k, kp, kp, [&](int c, int i, int j) { return K(neg_class(c), j, i); }));
     }
     auto Mf = [&](int b, int i, int j) { return o.M[((size_t)b * k + i) * k + j]; };
     auto Lf = [&](int b, int i, int j) { return o.L[((size_t)b * k + i) * k + j]; };
-    pl->Mt = up.put(pad_blocks<T>(8, k, k, kp, kp, Mf));
-    pl->MtT = up.put(pad_blocks<T>(8, k, k, kp, kp, [&](int b, int i, int j) { return Mf(b, j, i); }));
-    pl->Lt = up.put(pad_blocks<T>(8, k, k, kp, kp, Lf));
-    pl->LtT = up.put(pad_blocks<T>(8, k, k, kp, kp, [&](int b, int i, int j) { return Lf(b, j, i); }));
-    pl->Sop = up.put(pad_blocks<T>(1, k, ne, kp, nep, [&](int, int i, int a) { return o.S[(size_t)i * ne + a]; }));
-    pl->SopT = up.put(pad_blocks<T>(1, ne, k, nep, kp, [&](int, int a, int i) { return o.S[(size_t)i * ne + a]; }));
-    pl->Top = up.put(pad_blocks<T>(1, ne, k, nep, kp, [&](int, int a, int i) { return o.T[(size_t)a * k + i]; }));
-    pl->TopT = up.put(pad_blocks<T>(1, k, ne, kp, nep, [&](int, int i, int a) { return o.T[(size_t)a * k + i]; }));
+    d.Mt = up.put(pad_blocks<T>(8, k, k, kp, kp, Mf));
+    d.MtT = up.put(pad_blocks<T>(8, k, k, kp, kp, [&](int b, int i, int j) { return Mf(b, j, i); }));
+    d.Lt = up.put(pad_blocks<T>(8, k, k, kp, kp, Lf));
+    d.LtT = up.put(pad_blocks<T>(8, k, k, kp, kp, [&](int b, int i, int j) { return Lf(b, j, i); }));
+    d.Sop = up.put(pad_blocks<T>(1, k, ne, kp, nep, [&](int, int i, int a) { return o.S[(size_t)i * ne + a]; }));
+    d.SopT = up.put(pad_blocks<T>(1, ne, k, nep, kp, [&](int, int a, int i) { return o.S[(size_t)i * ne + a]; }));
+    d.Top = up.put(pad_blocks<T>(1, ne, k, nep, kp, [&](int, int a, int i) { return o.T[(size_t)a * k + i]; }));
+    d.TopT = up.put(pad_blocks<T>(1, k, ne, kp, nep, [&](int, int i, int a) { return o.T[(size_t)a * k + i]; }));
     if (pl->st2) {
         // stage-2 factors (Sec. 3.2), zero-padded to rp: phase A multiplies by V^
         // (rp x kp per class), phase B by U^ (kp x rp); the adjoint applies the
@@ -343,14 +369,78 @@ int upload_tables(kifmm_plan_s* pl, Uploader& up) {
         const int rm = o.r2max, rp = pl->rp;
         auto U2 = [&](int c, int i, int j) { return j < rm ? o.U2[((size_t)c * k + i) * rm + j] : 0.0; };
         auto V2 = [&](int c, int j, int i) { return j < rm ? o.V2[((size_t)c * rm + j) * k + i] : 0.0; };
-        pl->V2t = up.put(pad_blocks<T>(NCLASS, rm, k, rp, kp, V2));
-        pl->U2t = up.put(pad_blocks<T>(NCLASS, k, rm, kp, rp, U2));
-        pl->U2tT = up.put(pad_blocks<T>(NCLASS, rm, k, rp, kp, [&](int c, int j, int i) { return U2(neg_class(c), i, j); }));
-        pl->V2tT = up.put(pad_blocks<T>(NCLASS, k, rm, kp, rp, [&](int c, int i, int j) { return V2(neg_class(c), j, i); }));
+        d.V2t = up.put(pad_blocks<T>(NCLASS, rm, k, rp, kp, V2));
+        d.U2t = up.put(pad_blocks<T>(NCLASS, k, rm, kp, rp, U2));
+        d.U2tT = up.put(pad_blocks<T>(NCLASS, rm, k, rp, kp, [&](int c, int j, int i) { return U2(neg_class(c), i, j); }));
+        d.V2tT = up.put(pad_blocks<T>(NCLASS, k, rm, kp, rp, [&](int c, int i, int j) { return V2(neg_class(c), j, i); }));
     }
     std::vector<T> surf(3 * ne);
     for (int i = 0; i < 3 * ne; ++i) surf[i] = (T)o.outer[i];
-    pl->surf = up.put(surf);
+    d.surf = up.put(surf);
+}
+
+// The operator tables of the plan from the process-wide cache of device
+// tables, uploading them when no live plan on this device has them.
+template <typename T>
+std::shared_ptr<DevTables> shared_tables(const kifmm_plan_s* pl, Uploader& up) {
+    using Key = std::tuple<const HostOps*, int, bool, int, int, int, int>;
+    static std::mutex mu;
+    static std::map<Key, std::weak_ptr<DevTables>> cache;
+    const Key key{pl->ops_sp.get(), pl->elt, pl->b3, pl->device, pl->kp, pl->nep, pl->rp};
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            if (auto d = it->second.lock()) return d;
+            cache.erase(it);
+        }
+    }
+    auto d = std::make_shared<DevTables>();
+    d->device = pl->device;
+    d->ops = pl->ops_sp;
+    std::vector<void*>* saved = up.scratch;
+    const size_t saved_bytes = up.scratch_bytes;
+    up.scratch = &d->allocs;
+    up.scratch_bytes = 0;
+    upload_op_tables<T>(pl, up, *d);
+    d->bytes = up.scratch_bytes;
+    up.scratch = saved;
+    up.scratch_bytes = saved_bytes;
+    if (up.err != KIFMM_OK) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end())
+        if (auto other = it->second.lock()) return other;   // another thread uploaded them meanwhile
+    cache[key] = d;
+    return d;
+}
+
+template <typename T>
+int upload_tables(kifmm_plan_s* pl, Uploader& up) {
+    pl->tables = shared_tables<T>(pl, up);
+    if (!pl->tables) return up.err;
+    const DevTables& d = *pl->tables;
+    pl->device_bytes += d.bytes;
+    if (up.limit && pl->device_bytes > up.limit) {
+        up.err = KIFMM_ENOMEM;
+        up.msg = "opts.mem_limit exceeded by the operator tables (" + std::to_string(pl->device_bytes) + " bytes)";
+        return up.err;
+    }
+    pl->Kt = d.Kt;
+    pl->KtT = d.KtT;
+    pl->Mt = d.Mt;
+    pl->MtT = d.MtT;
+    pl->Lt = d.Lt;
+    pl->LtT = d.LtT;
+    pl->Sop = d.Sop;
+    pl->SopT = d.SopT;
+    pl->Top = d.Top;
+    pl->TopT = d.TopT;
+    pl->V2t = d.V2t;
+    pl->U2t = d.U2t;
+    pl->U2tT = d.U2tT;
+    pl->V2tT = d.V2tT;
+    pl->surf = d.surf;
     std::vector<T> pts(4 * (size_t)pl->tree.n, T(0));
     for (int64_t i = 0; i < pl->tree.n; ++i)
         for (int a = 0; a < 3; ++a) pts[4 * i + a] = (T)pl->tree.u[3 * i + a];
@@ -382,7 +472,7 @@ void upload_stage2(kifmm_plan_s* pl, Uploader& up) {
     const GGSched& s = pl->h_m2l;
     const int nch = s.n_chunks();
     if (nch == 0) return;
-    const HostOps& o = pl->ops;
+    const HostOps& o = pl->ops();
     const int64_t row_bytes = (int64_t)pl->rp * pl->elt;          // one W row (slot x rhs)
     const int64_t slot_bytes = (int64_t)pl->R * row_bytes;
     const int64_t wbytes = (int64_t)nch * s.cp * slot_bytes;
@@ -453,8 +543,8 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
     const HostTree& t = pl->tree;
     std::memset(&in, 0, sizeof(in));
     in.depth = t.depth;
-    in.k = pl->ops.k;
-    in.n_eq = pl->ops.n_eq;
+    in.k = pl->ops().k;
+    in.n_eq = pl->ops().n_eq;
     in.k_pad = pl->kp;
     in.precision = pl->opts.precision;
     in.dense_m2l = pl->opts.dense_m2l;
@@ -475,7 +565,7 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
         in.v_pairs += in.v_pairs_level[l];
     }
     in.r0 = t.r0;
-    const double k = pl->ops.k, ne = pl->ops.n_eq, nl = (double)t.n_leaf(), N = (double)t.n;
+    const double k = pl->ops().k, ne = pl->ops().n_eq, nl = (double)t.n_leaf(), N = (double)t.n;
     const double elt = pl->elt;
     int64_t nbox_up = 0;
     for (int l = 2; l < t.depth; ++l) nbox_up += t.level_count(l + 1);
@@ -488,10 +578,10 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
     if (pl->st2) {
         // two thin products per pair: 2 k r (w = V^ q) + 2 k r (U^ w), r the class rank
         double f = 0.0, rs = 0.0;
-        for (int32_t c : t.v_cls) f += 4.0 * k * pl->ops.rank2[c];
-        for (int32_t r : pl->ops.rank2) rs += r;
+        for (int32_t c : t.v_cls) f += 4.0 * k * pl->ops().rank2[c];
+        for (int32_t r : pl->ops().rank2) rs += r;
         in.flops[KIFMM_STAGE_M2L] = f;
-        in.m2l_rank_max = pl->ops.r2max;
+        in.m2l_rank_max = pl->ops().r2max;
         in.m2l_rank_mean = rs / NCLASS;
     }
     in.flops[KIFMM_STAGE_L2L] = far ? 2.0 * k * k * (double)nbox_up : 0;
@@ -508,7 +598,7 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
     in.bytes[KIFMM_STAGE_PERM] = N * (2 * elt + 4);
     in.device_bytes = pl->device_bytes;
     in.m2l_tile_targets = pl->h_m2l.max_tile;
-    in.sigma0 = pl->ops.sigma0;
+    in.sigma0 = pl->ops().sigma0;
     in.plan_seconds = seconds;
     in.m2l_variant = pl->h_m2l.variant;
     in.m2l_tiles = pl->h_m2l.n_tiles();
@@ -878,7 +968,7 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         KIFMM_HIP(hipStreamWaitEvent(ns, pl->ev_fork, 0));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P], ns));
         KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                      pl->near_leaf, pl->near_code, nullptr, pl->surf, pl->ops.n_eq, nep,
+                                      pl->near_leaf, pl->near_code, nullptr, pl->surf, pl->ops().n_eq, nep,
                                       1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, ns));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P + 1], ns));
         KIFMM_HIP(hipEventRecord(pl->ev_join, ns));
@@ -886,9 +976,9 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 0));
     if (far) {
         // upward (forward) / L2T^T (adjoint): surface evaluation and the leaf GEMM
-        KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, w.sig_s, pl->leaf_ptr, pl->surf, pl->ops.n_eq, nep,
+        KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, w.sig_s, pl->leaf_ptr, pl->surf, pl->ops().n_eq, nep,
                                       w.C, st));
-        KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->k, pl->ops.n_eq, w.C, nep,
+        KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->k, pl->ops().n_eq, w.C, nep,
                             adjoint ? w.P : w.Q, kp, R, 0, st));
     }
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 1));
@@ -934,14 +1024,14 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     KIFMM_HIP(mark(KIFMM_STAGE_L2P, 0));
     if (far) {
         if (!adjoint)
-            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, pl->ops.n_eq, pl->k, w.P, kp, w.E, nep, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, pl->ops().n_eq, pl->k, w.P, kp, w.E, nep, R, 0, st));
         else
-            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, pl->ops.n_eq, pl->k, w.Q, kp, w.E, nep, R, 0, st));
+            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, pl->ops().n_eq, pl->k, w.Q, kp, w.E, nep, R, 0, st));
         if (fork) {
             // far field at the points (L2T), added to the near field
             KIFMM_HIP(hipStreamWaitEvent(st, pl->ev_join, 0));
             KIFMM_HIP(launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                          pl->near_leaf, pl->near_code, w.E, pl->surf, pl->ops.n_eq, nep,
+                                          pl->near_leaf, pl->near_code, w.E, pl->surf, pl->ops().n_eq, nep,
                                           1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
         }
     }
@@ -951,7 +1041,7 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
         KIFMM_HIP(launch_eval_targets(3, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
                                       pl->near_leaf, pl->near_code, far ? w.E : nullptr, pl->surf,
-                                      pl->ops.n_eq, nep, 1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out,
+                                      pl->ops().n_eq, nep, 1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out,
                                       ld, nrhs, st));
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
     }
@@ -1044,8 +1134,7 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         if (p < 2 || p > 16) throw PlanError{KIFMM_EINVAL, "p must be in [2, 16]"};
         if (!(eps >= 0.0 && eps < 1.0)) throw PlanError{KIFMM_EINVAL, "eps must be in [0, 1)"};
         pl->tree = build_host_tree(points, n, leaf_size, o.depth, o.max_depth);
-        pl->ops = build_host_ops(p, eps, leaf_size, o.cd, o.pinv_rcond, o.dense_m2l != 0);
-        if (o.c2 > 0.0) build_stage2(pl->ops, o.c2);
+        pl->ops_sp = host_ops_shared(p, eps, leaf_size, o.cd, o.pinv_rcond, o.dense_m2l != 0, o.c2);
     } catch (const PlanError& e) {
         delete pl;
         return fail(e.code, e.msg);
@@ -1053,12 +1142,12 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         delete pl;
         return fail(KIFMM_ENOMEM, "host allocation failed");
     }
-    pl->k = pl->ops.k;
+    pl->k = pl->ops().k;
     pl->st2 = o.c2 > 0.0;
-    pl->rp = pl->st2 ? (pl->ops.r2max + 15) / 16 * 16 : 0;
+    pl->rp = pl->st2 ? (pl->ops().r2max + 15) / 16 * 16 : 0;
     // split-BF16 M2L works on 32-wide K-chunks
     pl->kp = pl->b3 ? (pl->k + 31) / 32 * 32 : (pl->k + 15) / 16 * 16;
-    pl->nep = (pl->ops.n_eq + 15) / 16 * 16;
+    pl->nep = (pl->ops().n_eq + 15) / 16 * 16;
     if (pl->kp > 19 * 16 || pl->nep > 19 * 16) {
         delete pl;
         return fail(KIFMM_EINVAL, "n_eq too large for the device kernels (p <= 8 supported)");
@@ -1215,7 +1304,7 @@ int kifmm_plan_export_tree(kifmm_plan_t plan, int32_t* leaf_coords) {
 
 int kifmm_plan_export_operator(kifmm_plan_t plan, int which, double* out, int64_t* count) {
     if (!plan) return fail(KIFMM_EINVAL, "plan is NULL");
-    const HostOps& o = plan->ops;
+    const HostOps& o = plan->ops();
     const std::vector<double>* v = nullptr;
     switch (which) {
         case 0: v = &o.sing; break;

@@ -132,6 +132,16 @@ __device__ __forceinline__ f64x4 bload4<double>(__amdgpu_buffer_rsrc_t r, uint32
     return __builtin_bit_cast(f64x4, v);
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// 2-wide load through a buffer resource (the last K-chunk of the trimmed form).
+__device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+// A 2-vector as the first two elements of a 4-vector (the other two undefined).
+__device__ __forceinline__ f32x4 widen2(f32x2 v) { return __builtin_shufflevector(v, v, 0, 1, -1, -1); }
+
 __device__ __forceinline__ int bload1(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
 }
@@ -251,9 +261,11 @@ __device__ __forceinline__ double meta_scale<double>(int lo, int hi) {
 // K-chunks); the staging converts the gathered FP32 columns into the same
 // layout in LDS. Register sets and LDS addresses are those of the FP32 form;
 // K-chunk pair (2c, 2c+1) of the FP32 form is (hi, lo) of 32-wide chunk c.
-template <typename T, int KP16, int WAVES, int MBW, bool B3 = false>
+template <typename T, int KP16, int WAVES, int MBW, bool B3 = false, bool TAIL8 = false>
 __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGParams p) {
     static_assert(!B3 || (sizeof(T) == 4 && KP16 % 2 == 0), "split BF16 needs FP32 data and 32-wide K-chunks");
+    static_assert(!TAIL8 || (!B3 && sizeof(T) == 4 && KP16 >= 2 && KP16 * 4 <= 32),
+                  "the trimmed last K-chunk exists in the FP32 pipelined form only");
     using M = Mfma<T>;
     using V4 = typename M::V4;
     constexpr int NT = 64 * WAVES;
@@ -329,9 +341,24 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         const int blk = min(wave * MBW + m, nmb - 1);
         const int row = row0 + blk * 16 + j;
         aoff[m] = row < p.a_rows ? (uint32_t)((row * p.lda + 4 * grp) * (int)sizeof(T)) : kOffNone;
-        aofl[m] = (row < p.a_rows && (B3 || 16 * (KP16 - 1) + 4 * grp < p.a_cols))
-                      ? aoff[m] + 16 * (KP16 - 1) * (int)sizeof(T) : kOffNone;
+        if constexpr (TAIL8)
+            aofl[m] = (row < p.a_rows && 16 * (KP16 - 1) + 2 * grp < p.a_cols)
+                          ? (uint32_t)((row * p.lda + 16 * (KP16 - 1) + 2 * grp) * (int)sizeof(T)) : kOffNone;
+        else
+            aofl[m] = (row < p.a_rows && (B3 || 16 * (KP16 - 1) + 4 * grp < p.a_cols))
+                          ? aoff[m] + 16 * (KP16 - 1) * (int)sizeof(T) : kOffNone;
     }
+    // TAIL8: the data end within 8 of the last K-chunk's start, so that
+    // K-chunk is read as 2-vectors (k = 16 (KP16-1) + 2 g + e, e = 0, 1, in
+    // the first two elements; the other two are never read) and takes two
+    // MFMA steps instead of four: lane group g supplies the same k for A and B.
+    auto a_last = [&](uint32_t off, uint32_t so) -> V4 {
+        if constexpr (TAIL8) {
+            return widen2(__builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(ra, off, so, 0)));
+        } else {
+            return bload4<T>(ra, off, so);
+        }
+    };
     const uint32_t a_cls_bytes = (uint32_t)(p.a_stride * (int64_t)sizeof(T));
     const uint32_t xrow_bytes = (uint32_t)(R * p.ldx * (int)sizeof(T));
 
@@ -423,7 +450,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         for (int m = 0; m < MBW; ++m) {
 #pragma unroll
             for (int t = 0; t < KP16 - 1; ++t) dst[m][t] = bload4<T>(ra, aoff[m] + 16 * t * (int)sizeof(T), so);
-            dst[m][KP16 - 1] = bload4<T>(ra, aofl[m], so);
+            dst[m][KP16 - 1] = a_last(aofl[m], so);
         }
     };
     auto tcol = [&](int ch, int& c0, int& c1) {
@@ -479,10 +506,19 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         const int kc = (KP16 <= 6 && (nb_c >> 8)) ? (nb_c >> 8) : KP16;
         if constexpr (PRE2) {
             V4 b0[KP16], b1[KP16];
+            // B operand of K-chunk t for column block cb (the trimmed last
+            // K-chunk: 2-vectors at k = 16 (KP16-1) + 2 g, as for A)
+            auto ldsb = [&](int cbk, int t) -> V4 {
+                if constexpr (TAIL8) {
+                    if (t == KP16 - 1)
+                        return widen2(*reinterpret_cast<const f32x2*>(bcol + cbk * 16 * LDB + 16 * t - 2 * grp));
+                }
+                return *reinterpret_cast<const V4*>(bcol + cbk * 16 * LDB + 16 * t);
+            };
 #pragma unroll
             for (int t = 0; t < LA && t < KP16; ++t) {
-                b0[t] = *reinterpret_cast<const V4*>(bcol + 16 * t);
-                b1[t] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * t);
+                b0[t] = ldsb(0, t);
+                b1[t] = ldsb(1, t);
             }
             V4 d[MBW][4];
 #pragma unroll
@@ -508,9 +544,10 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                 } else {
                     // two accumulation chains per block (step parity), so that
                     // consecutive MFMAs of a block are independent
+                    constexpr int NE = TAIL8 ? 2 : 4;   // MFMA steps of the last K-chunk
                     if (two && t < kc) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
+                        for (int e = 0; e < (t == KP16 - 1 ? NE : 4); ++e) {
 #pragma unroll
                             for (int m = 0; m < MBW; ++m) {
                                 d[m][e & 1] = M::step(a[m][t][e], b0[t][e], d[m][e & 1]);
@@ -519,7 +556,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                         }
                     } else if (on && t < kc) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
+                        for (int e = 0; e < (t == KP16 - 1 ? NE : 4); ++e) {
 #pragma unroll
                             for (int m = 0; m < MBW; ++m) d[m][e & 1] = M::step(a[m][t][e], b0[t][e], d[m][e & 1]);
                         }
@@ -527,8 +564,8 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 if (t + LA < KP16) {
-                    b0[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * (t + LA));
-                    b1[t + LA] = *reinterpret_cast<const V4*>(bcol + 16 * LDB + 16 * (t + LA));
+                    b0[t + LA] = ldsb(0, t + LA);
+                    b1[t + LA] = ldsb(1, t + LA);
                 }
                 hook(t);
             }
@@ -625,7 +662,7 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
                 const uint32_t so = (uint32_t)cls_n * a_cls_bytes;
 #pragma unroll
                 for (int m = 0; m < MBW; ++m)
-                    an[m][t] = bload4<T>(ra, t == KP16 - 1 ? aofl[m] : aoff[m] + 16 * t * (int)sizeof(T), so);
+                    an[m][t] = t == KP16 - 1 ? a_last(aofl[m], so) : bload4<T>(ra, aoff[m] + 16 * t * (int)sizeof(T), so);
             }
             // the gathers and the small loads (source rows, metadata, target
             // columns) go out right after the first K-chunks' MFMAs, so they
@@ -710,12 +747,6 @@ __global__ void __launch_bounds__(64 * WAVES, MBW == 1 ? 2 : 1) gg_kernel(GGPara
         const int row = idx - col * rows;
         Y[(ybase + col) * p.ldy + row0 + row] = acc[col * ldl + row];
     }
-}
-
-// 2-wide load through a buffer resource (the last K-chunk of the trimmed form).
-__device__ __forceinline__ float2 bload2(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    typedef int i32x2 __attribute__((ext_vector_type(2)));
-    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
 }
 
 // Row-slab grouped gather GEMM (FP32 data; FP32 MFMA, or split BF16 with B3):
@@ -1467,6 +1498,17 @@ hipError_t gg_launch_t(const GGParams& p, int blocks, size_t lds, hipStream_t st
     if constexpr (B3 && (KP16 % 2 != 0 || sizeof(T) != 4)) {
         return hipErrorInvalidValue;
     } else {
+        // FP32 pipelined form with the data ending within 8 of the last
+        // K-chunk's start: the trimmed last K-chunk
+        constexpr bool can_trim = !B3 && sizeof(T) == 4 && KP16 >= 2 && KP16 * 4 <= 32;
+        if constexpr (can_trim) {
+            if (p.a_cols <= 16 * (KP16 - 1) + 8) {
+                hipError_t e = ensure_lds(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES, MBW, false, true>), lds);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES, MBW, false, true>), dim3(blocks), dim3(64 * WAVES), lds, st, p);
+                return hipGetLastError();
+            }
+        }
         hipError_t e = ensure_lds(reinterpret_cast<const void*>(&gg_kernel<T, KP16, WAVES, MBW, B3>), lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((gg_kernel<T, KP16, WAVES, MBW, B3>), dim3(blocks), dim3(64 * WAVES), lds, st, p);

@@ -2,6 +2,10 @@
 // (Sec. 2.2, 3.1, 3.3, 4.1) and grouped-GEMM work schedules.
 #include "plan.h"
 
+#include <list>
+#include <mutex>
+#include <tuple>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -426,6 +430,33 @@ HostOps build_host_ops(int p, double eps, int leaf_size, double cd, double rcond
         std::copy(Kr.begin(), Kr.end(), o.K.begin() + c * k * k);
     });
     return o;
+}
+
+std::shared_ptr<const HostOps> host_ops_shared(int p, double eps, int leaf_size, double cd, double rcond,
+                                               bool dense, double c2) {
+    using Key = std::tuple<int, double, int, double, double, bool, double>;
+    static std::mutex mu;
+    static std::list<std::pair<Key, std::shared_ptr<const HostOps>>> lru;   // most recent first
+    constexpr size_t kKeep = 4;
+    const Key key{p, eps, leaf_size, cd, rcond, dense, c2};
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        for (auto it = lru.begin(); it != lru.end(); ++it)
+            if (it->first == key) {
+                lru.splice(lru.begin(), lru, it);
+                return lru.front().second;
+            }
+    }
+    // built outside the lock (seconds); two threads asking for one new key
+    // both build it and the first to finish is cached
+    auto ops = std::make_shared<HostOps>(build_host_ops(p, eps, leaf_size, cd, rcond, dense));
+    if (c2 > 0.0) build_stage2(*ops, c2);
+    std::lock_guard<std::mutex> lock(mu);
+    for (auto it = lru.begin(); it != lru.end(); ++it)
+        if (it->first == key) return it->second;
+    lru.emplace_front(key, ops);
+    if (lru.size() > kKeep) lru.pop_back();
+    return ops;
 }
 
 void build_stage2(HostOps& o, double c2) {

@@ -2,6 +2,7 @@
 // work schedules of the grouped GEMM kernel. Nothing here touches the GPU.
 #pragma once
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -72,6 +73,16 @@ struct HostOps {
 };
 
 HostOps build_host_ops(int p, double eps, int leaf_size, double cd, double rcond, bool dense);
+
+// The operators of (p, eps, leaf_size, cd, rcond, dense, c2) from a
+// process-wide cache: they are fixed by the equivalent and check surfaces
+// alone, not by the points or the boundary (the remark on the translating
+// matrices in Sec. 5.1), so plans with equal parameters
+// share one FP64 copy instead of repeating the SVD of K_fat. The most recently
+// used parameter sets stay cached; c2 > 0 adds the stage-2 factors. Safe to
+// call from several threads. Throws PlanError as build_host_ops.
+std::shared_ptr<const HostOps> host_ops_shared(int p, double eps, int leaf_size, double cd, double rcond,
+                                               bool dense, double c2);
 
 // Stage-2 low rank of the compressed M2L matrices (Sec. 3.2): per class the SVD
 // K~ = U S Q^T, keeping the singular values not below C2 eps / k * sigma0.
