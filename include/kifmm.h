@@ -89,6 +89,17 @@ typedef struct {
                            eps2 = C2 eps1 / k); M2L then runs as two thin products per pair
                            (w = V^ q into a per-pair buffer, then p += U^ w). 0 = off
                            (default). KIFMM_EINVAL with dense_m2l or KIFMM_BF16X3 */
+    int adaptive;       /* 1 = adaptive octree (Sec. 2.1 read cube by cube): a cube holding more
+                           than leaf_size points is split into its nonempty children, down to
+                           max_depth, and the tree is 2:1 balanced (in rounds, every leaf sharing a
+                           vertex with a leaf two or more levels finer is split) so that leaves sit
+                           at several levels. Near fields then join leaves of neighbouring levels,
+                           and the far field between leaves of different levels runs through the
+                           W and X lists of the kernel-independent FMM: the upward equivalent
+                           densities U~ q~ of a cube evaluated at a coarser leaf's points (M2T),
+                           and a coarser leaf's points giving a cube's downward check potential,
+                           projected by U~^T (S2L). 0 = uniform depth (default). KIFMM_EINVAL with
+                           depth > 0 */
 } kifmm_opts_t;
 
 /* Per-stage counters; index with the KIFMM_STAGE_* values. */
@@ -128,6 +139,12 @@ typedef struct {
     int m2l_tiles;          /* M2L target tiles (workgroups = tiles x row groups) */
     int m2l_rank_max;       /* stage 2: largest rank of the factored M2L matrices, else 0 */
     double m2l_rank_mean;   /* stage 2: mean rank over the 316 classes, else 0 */
+    int adaptive;           /* opts.adaptive of the plan */
+    int leaf_level_min;     /* coarsest leaf level (depth for uniform plans) */
+    int64_t w_pairs;        /* adaptive: (leaf, cube) W-list pairs = X-list pairs */
+    int64_t w_cubes;        /* adaptive: cubes in some W list (their U~ q~ is formed once) */
+    double m2t_flops;       /* adaptive: M2T (U~ products and point evaluations) per apply */
+    double s2l_flops;       /* adaptive: S2L (point evaluations and U~^T products) per apply */
 } kifmm_info_t;
 
 /* Fill `o` with the defaults listed above. Returns KIFMM_EINVAL if o is NULL. */
@@ -194,8 +211,29 @@ void kifmm_group_destroy(kifmm_group_t group); /* NULL-safe */
 int kifmm_plan_info(kifmm_plan_t plan, kifmm_info_t* info);
 
 /* Leaf cube of every point (caller order) as integer coordinates at level
- * info.depth: leaf_coords is a host array of n x 3 int32. */
+ * info.depth: leaf_coords is a host array of n x 3 int32. (In an adaptive
+ * plan: the level-depth cube holding the point, not its leaf.) */
 int kifmm_plan_export_tree(kifmm_plan_t plan, int32_t* leaf_coords);
+
+/* Leaf of every point (caller order) as (level, i, j, k), the cube's integer
+ * coordinates at its own level: out is a host array of n x 4 int32. */
+int kifmm_plan_export_point_leaves(kifmm_plan_t plan, int32_t* out);
+
+/* The cubes of the tree (Sec. 2.1) in the plan's global order, 5 int32 per
+ * cube: level, i, j, k (integer coordinates at that level) and the leaf index
+ * (-1 for a split cube). With out == NULL only *count (cubes) is set; else
+ * out must hold 5 * count values. count must not be NULL. */
+int kifmm_plan_export_boxes(kifmm_plan_t plan, int32_t* out, int64_t* count);
+
+/* The interaction lists as (target, source) pairs of global cube indices (the
+ * order of kifmm_plan_export_boxes), 2 int32 per pair. which:
+ *   0 U: near field (Sec. 2.1), target leaf and source leaf
+ *   1 V: interaction field (Sec. 2.1), target and source cube, levels >= 2
+ *   2 W (adaptive plans; empty otherwise): target leaf, source cube
+ *   3 X (adaptive plans; empty otherwise): target cube, source leaf
+ * With out == NULL only *count (pairs) is set; else out must hold 2 * count
+ * values. KIFMM_EINVAL for another `which` or count == NULL. */
+int kifmm_plan_export_list(kifmm_plan_t plan, int which, int32_t* out, int64_t* count);
 
 /* Host FP64 copies of the plan's operators (for checks). `which`:
  *   0 singular values of K_fat (n_eq values; dense plans: zeros)

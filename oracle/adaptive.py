@@ -26,9 +26,12 @@ Readings taken here and by the GPU library (which has its own implementation):
   q >> (21 - l);
 * a cube holding more than s points is split, down to `max_depth` (larger
   leaves are allowed there); empty children are not created;
-* 2:1 balance: a leaf that shares a vertex with a leaf two or more levels
-  finer is split too, repeatedly, until no such pair is left (a unique fixed
-  point, since splitting only ever adds cubes);
+* 2:1 balance, in rounds: every leaf of the current tree that shares a
+  vertex with a leaf two or more levels finer is split, all of them at once;
+  rounds repeat until no such pair is left. (The rounds fix the result: a
+  leaf split in the same round as the finer leaf it touches might not have
+  needed it had that leaf been split first, since empty children are not
+  created.)
 * the downward pass runs at levels >= 2 as in the uniform tree (V is empty
   at levels 0 and 1); a leaf above level 2 takes its far field from W only.
 
@@ -217,7 +220,8 @@ def build_adaptive_tree(x: np.ndarray, leaf_size: int, max_depth: int = 16, bala
 
 def fmm_adaptive(x: np.ndarray, sigma: np.ndarray, ops, tree: AdaptiveTree) -> np.ndarray:
     """Potential at every point by the KIFMM on the adaptive tree, FP64, with
-    the operators `ops` (oracle.operators.build_operators: dense or svd mode).
+    the operators `ops` (oracle.operators.build_operators: dense, svd or svd2
+    mode; svd2 applies each M2L matrix as its stage-2 factors).
 
     Upward: S2M at every leaf at its own level, M2M for every split cube
     (finest level first). Downward, levels >= 2: L2L from the parent, M2L from
@@ -270,7 +274,11 @@ def fmm_adaptive(x: np.ndarray, sigma: np.ndarray, ops, tree: AdaptiveTree) -> n
                 acc += ops.L[o] @ down[par]
             for c in tree.V(box):                                                    # M2L
                 tvec = tuple(b[d] - c[1][d] for d in range(3))
-                acc += (ops.K[tvec] @ up[c]) / r
+                if ops.K2 is not None:                                               # stage 2, Sec. 3.2
+                    Uh, Vh = ops.K2[tvec]
+                    acc += (Uh @ (Vh @ up[c])) / r
+                else:
+                    acc += (ops.K[tvec] @ up[c]) / r
             if box in X:                                                             # S2L
                 dc = tree.box_centre(box) + r * ops.DC
                 for src in X[box]:

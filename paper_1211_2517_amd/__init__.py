@@ -29,6 +29,7 @@ EXPORTED_SYMBOLS = (
     "kifmm_apply_batched", "kifmm_group_create", "kifmm_group_apply", "kifmm_group_destroy",
     "kifmm_plan_info", "kifmm_plan_export_tree", "kifmm_plan_export_operator", "kifmm_profile",
     "kifmm_profile_read", "kifmm_destroy", "kifmm_last_error", "kifmm_apply_noalloc",
+    "kifmm_plan_export_point_leaves", "kifmm_plan_export_boxes", "kifmm_plan_export_list",
 )
 
 
@@ -42,7 +43,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cd", ctypes.c_double), ("pinv_rcond", ctypes.c_double),
                 ("depth", ctypes.c_int), ("max_depth", ctypes.c_int), ("dense_m2l", ctypes.c_int),
                 ("max_nrhs", ctypes.c_int), ("device", ctypes.c_int), ("mem_limit", ctypes.c_size_t),
-                ("tile_targets", ctypes.c_int), ("m2l_shape", ctypes.c_int), ("c2", ctypes.c_double)]
+                ("tile_targets", ctypes.c_int), ("m2l_shape", ctypes.c_int), ("c2", ctypes.c_double),
+                ("adaptive", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -55,7 +57,9 @@ class _Info(ctypes.Structure):
                 ("device_bytes", ctypes.c_size_t), ("m2l_tile_targets", ctypes.c_int),
                 ("sigma0", ctypes.c_double), ("plan_seconds", ctypes.c_double),
                 ("m2l_variant", ctypes.c_int), ("m2l_tiles", ctypes.c_int),
-                ("m2l_rank_max", ctypes.c_int), ("m2l_rank_mean", ctypes.c_double)]
+                ("m2l_rank_max", ctypes.c_int), ("m2l_rank_mean", ctypes.c_double),
+                ("adaptive", ctypes.c_int), ("leaf_level_min", ctypes.c_int), ("w_pairs", ctypes.c_int64),
+                ("w_cubes", ctypes.c_int64), ("m2t_flops", ctypes.c_double), ("s2l_flops", ctypes.c_double)]
 
 
 _LIB = None
@@ -89,6 +93,9 @@ def load_library():
     lib.kifmm_plan_info.argtypes = [V, ctypes.POINTER(_Info)]
     lib.kifmm_plan_export_tree.argtypes = [V, P]
     lib.kifmm_plan_export_operator.argtypes = [V, I, P, ctypes.POINTER(I64)]
+    lib.kifmm_plan_export_point_leaves.argtypes = [V, P]
+    lib.kifmm_plan_export_boxes.argtypes = [V, P, ctypes.POINTER(I64)]
+    lib.kifmm_plan_export_list.argtypes = [V, I, P, ctypes.POINTER(I64)]
     lib.kifmm_profile.argtypes = [V, I]
     lib.kifmm_profile_read.argtypes = [V, P, ctypes.POINTER(I64)]
     lib.kifmm_destroy.argtypes = [V]
@@ -117,7 +124,8 @@ class Plan:
     def __init__(self, points, p: int = 6, eps: float = 1e-6, leaf_size: int = 64, *,
                  precision: str = "fp32", dense_m2l: bool = False, max_nrhs: int = 1, device: int = 0,
                  depth: int = 0, max_depth: int = 16, cd: float = 0.5, pinv_rcond: float = 1e-10,
-                 mem_limit: int = 0, tile_targets: int = 0, m2l_shape: int = -1, c2: float = 0.0):
+                 mem_limit: int = 0, tile_targets: int = 0, m2l_shape: int = -1, c2: float = 0.0,
+                 adaptive: bool = False):
         lib = load_library()
         pts = np.ascontiguousarray(np.asarray(points.cpu().numpy() if hasattr(points, "cpu") else points,
                                               dtype=np.float64))
@@ -137,6 +145,7 @@ class Plan:
         o.tile_targets = int(tile_targets)
         o.m2l_shape = int(m2l_shape)
         o.c2 = float(c2)
+        o.adaptive = int(bool(adaptive))
         h = ctypes.c_void_p()
         _check(lib.kifmm_plan_ex(pts.ctypes.data, pts.shape[0], int(p), float(eps), int(leaf_size),
                                  ctypes.byref(o), ctypes.byref(h)))
@@ -162,6 +171,30 @@ class Plan:
     def export_tree(self) -> np.ndarray:
         out = np.empty((self.n, 3), dtype=np.int32)
         _check(self._lib.kifmm_plan_export_tree(self._h, out.ctypes.data))
+        return out
+
+    def export_point_leaves(self) -> np.ndarray:
+        """(level, i, j, k) of every point's leaf, caller order."""
+        out = np.empty((self.n, 4), dtype=np.int32)
+        _check(self._lib.kifmm_plan_export_point_leaves(self._h, out.ctypes.data))
+        return out
+
+    def export_boxes(self) -> np.ndarray:
+        """Cubes in the plan's global order: (level, i, j, k, leaf index or -1)."""
+        cnt = ctypes.c_int64()
+        _check(self._lib.kifmm_plan_export_boxes(self._h, None, ctypes.byref(cnt)))
+        out = np.empty((cnt.value, 5), dtype=np.int32)
+        _check(self._lib.kifmm_plan_export_boxes(self._h, out.ctypes.data, ctypes.byref(cnt)))
+        return out
+
+    def export_list(self, which: str) -> np.ndarray:
+        """(target, source) global cube indices of list "U", "V", "W" or "X"."""
+        w = {"U": 0, "V": 1, "W": 2, "X": 3}[which]
+        cnt = ctypes.c_int64()
+        _check(self._lib.kifmm_plan_export_list(self._h, w, None, ctypes.byref(cnt)))
+        out = np.empty((cnt.value, 2), dtype=np.int32)
+        if cnt.value:
+            _check(self._lib.kifmm_plan_export_list(self._h, w, out.ctypes.data, ctypes.byref(cnt)))
         return out
 
     def export_operator(self, which: int) -> np.ndarray:

@@ -68,6 +68,7 @@ struct DevTables {
     void *Kt = nullptr, *KtT = nullptr, *Mt = nullptr, *MtT = nullptr, *Lt = nullptr, *LtT = nullptr;
     void *Sop = nullptr, *SopT = nullptr, *Top = nullptr, *TopT = nullptr;
     void *V2t = nullptr, *U2t = nullptr, *U2tT = nullptr, *V2tT = nullptr, *surf = nullptr;
+    void *Ut = nullptr, *UtT = nullptr, *surf_in = nullptr;   // U~, U~^T and the (1+d) surface (M2T, S2L)
     ~DevTables() {
         if (allocs.empty()) return;
         int cur = 0;
@@ -119,7 +120,23 @@ struct kifmm_plan_s {
     void *Sop = nullptr, *SopT = nullptr, *Top = nullptr, *TopT = nullptr;
     void *V2t = nullptr, *U2t = nullptr, *U2tT = nullptr, *V2tT = nullptr;   // stage-2 factors
     void* W = nullptr;   // stage-2 per-slot products w = V^ q (n_chunks x 32 rows of rp)
+    // Adaptive trees. The cubes that appear in some W list are exactly those
+    // with a nonempty X list; they are numbered as "W cubes" in box order.
+    // M2T: Psi[w] = U~ q~ of W cube w (h_m2t), evaluated at the points of the
+    // leaves that list it (m2t_*); S2L: CX[w] = check potential of W cube w
+    // from the points of its X leaves (s2l_*), then P += U~^T CX / (4 pi r)
+    // (h_s2l). The adjoint runs the same steps with the roles of Q and P swapped.
+    std::vector<int32_t> w_cube_box;     // W cube -> global box
+    GGSched h_m2t, h_s2l;
+    DevSched d_m2t, d_s2l;
+    int64_t n_m2t_leaf = 0;              // leaves with a nonempty W list
+    int32_t* leaf_level = nullptr;
+    int32_t *m2t_leaf = nullptr, *m2t_ptr = nullptr, *m2t_cube = nullptr;
+    int32_t *s2l_ptr = nullptr, *s2l_leaf = nullptr;
+    void *m2t_geo = nullptr, *s2l_geo = nullptr;   // per entry (rho, ox, oy, oz) in the element type
+    void *Ut = nullptr, *UtT = nullptr, *surf_in = nullptr;
     void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
+    void *CX = nullptr, *Psi = nullptr;   // adaptive: per W cube, S2L check potentials and U~ q~
     std::vector<void*> allocs;
     std::shared_ptr<DevTables> tables;   // operator tables (possibly shared with other plans)
     size_t device_bytes = 0;
@@ -238,7 +255,10 @@ std::vector<T> pad_blocks(int nblk, int rows, int cols, int rows_pad, int cols_p
     return out;
 }
 
-DevSched upload_sched(Uploader& up, const GGSched& s, int elt) {
+// With row_map, the schedule's target rows are indices into row_map, which
+// gives the rows the kernel writes; the schedule must then have one pair per
+// target (the direct form), or the upload fails.
+DevSched upload_sched(Uploader& up, const GGSched& s, int elt, const std::vector<int32_t>* row_map = nullptr) {
     DevSched d;
     d.n_tiles = s.n_tiles();
     d.n_chunks = s.n_chunks();
@@ -286,7 +306,7 @@ DevSched upload_sched(Uploader& up, const GGSched& s, int elt) {
                     direct = false;
                     break;
                 }
-                tgt[(size_t)c * s.cp + i] = (int32_t)g;
+                tgt[(size_t)c * s.cp + i] = row_map ? (*row_map)[(size_t)g] : (int32_t)g;
                 ++got;
             }
         }
@@ -294,6 +314,9 @@ DevSched upload_sched(Uploader& up, const GGSched& s, int elt) {
     if (direct && got == need) {
         d.direct = true;
         d.chunk_tgt = (const int32_t*)up.put(tgt);
+    } else if (row_map && up.err == KIFMM_OK) {
+        up.err = KIFMM_EINVAL;
+        up.msg = "internal: a row-mapped schedule must have one pair per target";
     }
     return d;
 }
@@ -377,6 +400,14 @@ void upload_op_tables(const kifmm_plan_s* pl, Uploader& up, DevTables& d) {
     std::vector<T> surf(3 * ne);
     for (int i = 0; i < 3 * ne; ++i) surf[i] = (T)o.outer[i];
     d.surf = up.put(surf);
+    // M2T and S2L (adaptive trees): U~, U~^T and the upward-equivalent /
+    // downward-check surface (1 + d) E
+    auto Uf = [&](int, int a, int i) { return o.U[(size_t)a * k + i]; };
+    d.Ut = up.put(pad_blocks<T>(1, ne, k, nep, kp, Uf));
+    d.UtT = up.put(pad_blocks<T>(1, k, ne, kp, nep, [&](int, int i, int a) { return o.U[(size_t)a * k + i]; }));
+    std::vector<T> sin(3 * ne);
+    for (int i = 0; i < 3 * ne; ++i) sin[i] = (T)((1.0 + o.d) * o.E[i]);
+    d.surf_in = up.put(sin);
 }
 
 // The operator tables of the plan from the process-wide cache of device
@@ -441,6 +472,9 @@ int upload_tables(kifmm_plan_s* pl, Uploader& up) {
     pl->U2tT = d.U2tT;
     pl->V2tT = d.V2tT;
     pl->surf = d.surf;
+    pl->Ut = d.Ut;
+    pl->UtT = d.UtT;
+    pl->surf_in = d.surf_in;
     std::vector<T> pts(4 * (size_t)pl->tree.n, T(0));
     for (int64_t i = 0; i < pl->tree.n; ++i)
         for (int a = 0; a < 3; ++a) pts[4 * i + a] = (T)pl->tree.u[3 * i + a];
@@ -456,6 +490,66 @@ int upload_tables(kifmm_plan_s* pl, Uploader& up) {
         pl->qpts = up.put(q);
     }
     return up.err;
+}
+
+// Device lists of an adaptive plan: leaf levels, the M2T entries of every
+// leaf with a W list and the S2L entries of every W cube, each with the
+// geometry (rho, o) that maps the source into the target's units: for M2T the
+// W cube's surface point s becomes rho s + o in the units of the target leaf
+// (rho = r_cube / r_leaf), for S2L a point u of the source leaf becomes
+// rho u + o in the units of the W cube (rho = r_leaf / r_cube); rho is a power
+// of two and o a multiple of rho or an integer, so both are exact.
+template <typename T>
+void upload_adaptive(kifmm_plan_s* pl, Uploader& up) {
+    const HostTree& t = pl->tree;
+    pl->leaf_level = (int32_t*)up.put(t.leaf_level);
+    const int64_t nw = (int64_t)pl->w_cube_box.size();
+    if (nw == 0) return;
+    std::vector<int32_t> cube_of_box(t.n_box(), -1);
+    for (int64_t w = 0; w < nw; ++w) cube_of_box[pl->w_cube_box[w]] = (int32_t)w;
+    std::vector<int32_t> mleaf, mptr(1, 0), mcube, sptr(1, 0), sleaf;
+    std::vector<T> mgeo, sgeo;
+    for (int64_t e = 0; e < t.n_leaf(); ++e) {
+        if (t.w_ptr[e + 1] == t.w_ptr[e]) continue;
+        int64_t c[3], ec[3];
+        const int l = box_cube(t, t.leaf_box[e], c);
+        mleaf.push_back((int32_t)e);
+        for (int32_t k = t.w_ptr[e]; k < t.w_ptr[e + 1]; ++k) {
+            const int m = box_cube(t, t.w_src[k], ec);
+            const double rho = std::ldexp(1.0, l - m);
+            mcube.push_back(cube_of_box[t.w_src[k]]);
+            mgeo.push_back((T)rho);
+            for (int a = 0; a < 3; ++a) mgeo.push_back((T)((2.0 * ec[a] + 1.0) * rho - (2.0 * c[a] + 1.0)));
+        }
+        mptr.push_back((int32_t)mcube.size());
+    }
+    for (int64_t w = 0; w < nw; ++w) {
+        const int64_t g = pl->w_cube_box[w];
+        int64_t c[3], ec[3];
+        const int m = box_cube(t, g, ec);
+        for (int32_t k = t.x_ptr[g]; k < t.x_ptr[g + 1]; ++k) {
+            const int32_t e = t.x_src[k];
+            const int l = box_cube(t, t.leaf_box[e], c);
+            const double rho = std::ldexp(1.0, m - l);
+            sleaf.push_back(e);
+            sgeo.push_back((T)rho);
+            for (int a = 0; a < 3; ++a) sgeo.push_back((T)((2.0 * c[a] + 1.0) * rho - (2.0 * ec[a] + 1.0)));
+        }
+        sptr.push_back((int32_t)sleaf.size());
+    }
+    pl->n_m2t_leaf = (int64_t)mleaf.size();
+    pl->m2t_leaf = (int32_t*)up.put(mleaf);
+    pl->m2t_ptr = (int32_t*)up.put(mptr);
+    pl->m2t_cube = (int32_t*)up.put(mcube);
+    pl->m2t_geo = up.put(mgeo);
+    pl->s2l_ptr = (int32_t*)up.put(sptr);
+    pl->s2l_leaf = (int32_t*)up.put(sleaf);
+    pl->s2l_geo = up.put(sgeo);
+    pl->d_m2t = upload_sched(up, pl->h_m2t, pl->elt);
+    pl->d_s2l = upload_sched(up, pl->h_s2l, pl->elt, &pl->w_cube_box);
+    const size_t bytes = (size_t)nw * pl->R * pl->nep * pl->elt;
+    pl->CX = up.zeros(bytes);
+    pl->Psi = up.zeros(bytes);
 }
 
 // Device schedules and buffer of the stage-2 M2L (Sec. 3.2), from the M2L
@@ -602,6 +696,22 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
     in.plan_seconds = seconds;
     in.m2l_variant = pl->h_m2l.variant;
     in.m2l_tiles = pl->h_m2l.n_tiles();
+    in.adaptive = t.adaptive ? 1 : 0;
+    in.leaf_level_min = t.depth;
+    if (t.adaptive) {
+        for (int32_t l : t.leaf_level) in.leaf_level_min = std::min(in.leaf_level_min, (int)l);
+        in.w_pairs = (int64_t)t.w_src.size();
+        in.w_cubes = (int64_t)pl->w_cube_box.size();
+        // M2T: U~ q~ per W cube, then every (point, surface point) of the W
+        // entries of its leaf; S2L: every (source point, surface point) of the
+        // X entries, then U~^T per W cube
+        double pts_w = 0.0, pts_x = 0.0;
+        for (int64_t e = 0; e < t.n_leaf(); ++e)
+            pts_w += (double)(t.leaf_ptr[e + 1] - t.leaf_ptr[e]) * (t.w_ptr[e + 1] - t.w_ptr[e]);
+        for (int32_t e : t.x_src) pts_x += (double)(t.leaf_ptr[e + 1] - t.leaf_ptr[e]);
+        in.m2t_flops = 2.0 * k * ne * (double)in.w_cubes + 11.0 * ne * pts_w;
+        in.s2l_flops = 11.0 * ne * pts_x + 2.0 * k * ne * (double)in.w_cubes;
+    }
 }
 
 // Largest tile (targets) whose LDS accumulator (plus the R spare columns of
@@ -664,6 +774,104 @@ int m2l_tiles_for(const kifmm_plan_s* pl, int variant, int extra_rounds) {
     return (rounds + extra_rounds) * slots;
 }
 
+void build_uniform_passes(kifmm_plan_s* pl, const std::function<int(int64_t)>& level_tile);
+
+// Schedules of the upward and downward passes of an adaptive tree (the M2L
+// schedule is the uniform tree's: every cube of levels >= 2). S2M at the
+// leaves of levels >= 2 (a level's leaves come first among its cubes), M2M
+// into its split cubes, L2L into every cube of levels >= 3, L2T at the leaves
+// of levels >= 2 (coarser leaves take their far field from W alone), and the
+// M2T / S2L products of the W cubes.
+void build_adaptive_passes(kifmm_plan_s* pl, const std::function<int(int64_t)>& level_tile) {
+    const HostTree& t = pl->tree;
+    const int L = t.depth;
+    const int64_t nleaf = t.n_leaf();
+    const std::vector<double> one{1.0}, inv4pi{1.0 / kFourPi};
+    int64_t n_up = 0;
+    for (int l = 2; l <= L; ++l) n_up += t.level_leaves[l];
+    const int per_cu = (int)std::max<int64_t>(1, (n_up + pl->num_cu - 1) / pl->num_cu);
+    const int tile_up = std::min(std::max(16 / pl->R + 1, per_cu), max_tile_for(pl, 0, pl->nep));
+    const int tile_dn = std::min(std::max(16 / pl->R + 1, per_cu), max_tile_for(pl, 0, pl->kp));
+    for (int l = 2; l <= L; ++l) {
+        const int64_t b0 = t.level_begin[l], nl = t.level_leaves[l];
+        if (nl == 0) continue;
+        std::vector<int32_t> ptr(nl + 1), src(nl), cls(nl, 0);
+        for (int64_t e = 0; e <= nl; ++e) ptr[e] = (int32_t)e;
+        for (int64_t e = 0; e < nl; ++e) src[e] = t.box_leaf[b0 + e];
+        gg_build(pl->h_leafup, b0, nl, ptr.data(), src.data(), cls.data(), nullptr, inv4pi, uniform_cuts(nl, tile_up));
+    }
+    for (int64_t e0 = 0; e0 < nleaf;) {
+        if (t.leaf_level[e0] < 2) {
+            ++e0;
+            continue;
+        }
+        int64_t e1 = e0;
+        while (e1 < nleaf && t.leaf_level[e1] >= 2) ++e1;
+        const int64_t nr = e1 - e0;
+        std::vector<int32_t> ptr(nr + 1), src(nr), cls(nr, 0);
+        for (int64_t e = 0; e <= nr; ++e) ptr[e] = (int32_t)e;
+        for (int64_t e = 0; e < nr; ++e) src[e] = t.leaf_box[e0 + e];
+        gg_build(pl->h_leafdown, e0, nr, ptr.data(), src.data(), cls.data(), nullptr, one, uniform_cuts(nr, tile_dn));
+        e0 = e1;
+    }
+    for (int l = 2; l < L; ++l) {
+        const int64_t b0 = t.level_begin[l] + t.level_leaves[l], nb = t.level_begin[l + 1] - b0;
+        if (nb == 0) continue;
+        std::vector<int32_t> ptr(1, 0), src, cls;
+        for (int64_t b = 0; b < nb; ++b) {
+            for (int o = 0; o < 8; ++o) {
+                const int32_t ch = t.box_child[8 * (b0 + b) + o];
+                if (ch >= 0) {
+                    src.push_back(ch);
+                    cls.push_back(o);
+                }
+            }
+            ptr.push_back((int32_t)src.size());
+        }
+        gg_build(pl->h_up[l], b0, nb, ptr.data(), src.data(), cls.data(), nullptr, one,
+                 uniform_cuts(nb, level_tile(nb)));
+    }
+    for (int l = 3; l <= L; ++l) {
+        const int64_t b0 = t.level_begin[l], nb = t.level_count(l);
+        std::vector<int32_t> ptr(nb + 1), src(nb), cls(nb);
+        for (int64_t b = 0; b < nb; ++b) {
+            ptr[b] = (int32_t)b;
+            src[b] = t.box_parent[b0 + b];
+            cls[b] = (int32_t)(t.box_key[b0 + b] & 7);
+        }
+        ptr[nb] = (int32_t)nb;
+        gg_build(pl->h_down[l], b0, nb, ptr.data(), src.data(), cls.data(), nullptr, one,
+                 uniform_cuts(nb, level_tile(nb)));
+    }
+    // W cubes: Psi = U~ q~ (one product each) and P += U~^T CX / (4 pi r_l)
+    pl->w_cube_box.clear();
+    for (int64_t g = 0; g < t.n_box(); ++g)
+        if (t.x_ptr[g + 1] > t.x_ptr[g]) pl->w_cube_box.push_back((int32_t)g);
+    const int64_t nw = (int64_t)pl->w_cube_box.size();
+    pl->h_m2t = GGSched();
+    pl->h_s2l = GGSched();
+    for (GGSched* s : {&pl->h_m2t, &pl->h_s2l}) {
+        s->cp = 32 / pl->R;
+        s->rhs = pl->R;
+    }
+    if (nw > 0) {
+        std::vector<int32_t> ptr(nw + 1), src(nw), cls(nw, 0), grp(nw);
+        for (int64_t w = 0; w <= nw; ++w) ptr[w] = (int32_t)w;
+        std::vector<double> scale(L + 1);
+        for (int l = 0; l <= L; ++l) scale[l] = 1.0 / (kFourPi * t.half_width(l));
+        for (int64_t w = 0; w < nw; ++w) {
+            const int64_t g = pl->w_cube_box[w];
+            src[w] = (int32_t)g;
+            int l = 0;
+            while (t.level_begin[l + 1] <= g) ++l;
+            grp[w] = l;
+        }
+        gg_build(pl->h_m2t, 0, nw, ptr.data(), src.data(), cls.data(), nullptr, one, uniform_cuts(nw, 64));
+        for (int64_t w = 0; w < nw; ++w) src[w] = (int32_t)w;
+        gg_build(pl->h_s2l, 0, nw, ptr.data(), src.data(), cls.data(), grp.data(), scale, uniform_cuts(nw, 64));
+    }
+}
+
 int build_schedules(kifmm_plan_s* pl, int m2l_tile, int m2l_shape) {
     const HostTree& t = pl->tree;
     const int L = t.depth;
@@ -686,6 +894,32 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile, int m2l_shape) {
         s.rhs = pl->R;
     }
     if (L < 2) return KIFMM_OK;
+    // tiles of a per-level launch: about one workgroup per CU for the large
+    // levels (a workgroup's fixed costs - pipeline fill, accumulator load and
+    // store - then amortise over many chunks), small ones for small levels so
+    // that they still spread over the chip
+    auto level_tile = [&](int64_t nb) {
+        const int64_t per_cu = (nb + pl->num_cu - 1) / pl->num_cu;
+        const int64_t tl = std::max<int64_t>(16 / pl->R + 1, per_cu);
+        return (int)std::min<int64_t>(tl, max_tile_for(pl, 0, pl->kp));
+    };
+    if (t.adaptive) {
+        build_adaptive_passes(pl, level_tile);
+    } else {
+        build_uniform_passes(pl, level_tile);
+    }
+    // M2L: default shape (the device autotuner may replace it)
+    if (m2l_tile > 0)
+        pl->h_m2l = build_m2l_sched(pl, m2l_shape, 0, m2l_tile);
+    else
+        pl->h_m2l = build_m2l_sched(pl, m2l_shape, m2l_tiles_for(pl, m2l_shape, 0), 0);
+    return KIFMM_OK;
+}
+
+// Schedules of the upward and downward passes of a uniform tree.
+void build_uniform_passes(kifmm_plan_s* pl, const std::function<int(int64_t)>& level_tile) {
+    const HostTree& t = pl->tree;
+    const int L = t.depth;
     const int64_t nleaf = t.n_leaf();
     const int64_t lb = t.level_begin[L];
     const std::vector<double> one{1.0}, inv4pi{1.0 / kFourPi};
@@ -702,16 +936,6 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile, int m2l_shape) {
         gg_build(pl->h_leafdown, 0, nleaf, ptr.data(), src.data(), cls.data(), nullptr, one,
                  uniform_cuts(nleaf, tile_dn));
     }
-    // small levels get small tiles so that their launches still spread over the chip
-    // tiles of a per-level launch: about one workgroup per CU for the large
-    // levels (a workgroup's fixed costs - pipeline fill, accumulator load and
-    // store - then amortise over many chunks), small ones for small levels so
-    // that they still spread over the chip
-    auto level_tile = [&](int64_t nb) {
-        const int64_t per_cu = (nb + pl->num_cu - 1) / pl->num_cu;
-        const int64_t tl = std::max<int64_t>(16 / pl->R + 1, per_cu);
-        return (int)std::min<int64_t>(tl, max_tile_for(pl, 0, pl->kp));
-    };
     for (int l = 2; l < L; ++l) {
         // targets at level l, sources their children at level l+1 (class = octant)
         const int64_t b0 = t.level_begin[l], nb = t.level_count(l);
@@ -742,12 +966,6 @@ int build_schedules(kifmm_plan_s* pl, int m2l_tile, int m2l_shape) {
         gg_build(pl->h_down[l], b0, nb, ptr.data(), src.data(), cls.data(), nullptr, one,
                  uniform_cuts(nb, level_tile(nb)));
     }
-    // M2L: default shape (the device autotuner may replace it)
-    if (m2l_tile > 0)
-        pl->h_m2l = build_m2l_sched(pl, m2l_shape, 0, m2l_tile);
-    else
-        pl->h_m2l = build_m2l_sched(pl, m2l_shape, m2l_tiles_for(pl, m2l_shape, 0), 0);
-    return KIFMM_OK;
 }
 
 // M2L tile-shape autotuner: time the M2L launch for a few (row blocks per
@@ -852,6 +1070,7 @@ void autotune_m2l(kifmm_plan_s* pl, Uploader& up) {
 // the rows of W past a class's rank, which must hold zeros.
 struct Work {
     void *sig_s = nullptr, *C = nullptr, *E = nullptr, *Q = nullptr, *P = nullptr, *W = nullptr;
+    void *CX = nullptr, *Psi = nullptr;
 };
 
 Work plan_work(const kifmm_plan_s* pl) {
@@ -862,6 +1081,8 @@ Work plan_work(const kifmm_plan_s* pl) {
     w.Q = pl->Q;
     w.P = pl->P;
     w.W = pl->W;
+    w.CX = pl->CX;
+    w.Psi = pl->Psi;
     return w;
 }
 
@@ -901,6 +1122,10 @@ size_t carve_work(const kifmm_plan_s* pl, char* base, Work* w) {
         v.E = take((size_t)t.n_leaf() * R * pl->nep * elt);
         v.Q = take((size_t)t.n_box() * R * pl->kp * elt);
         v.P = take((size_t)t.n_box() * R * pl->kp * elt);
+        if (!pl->w_cube_box.empty()) {
+            v.CX = take(pl->w_cube_box.size() * R * pl->nep * elt);
+            v.Psi = take(pl->w_cube_box.size() * R * pl->nep * elt);
+        }
     }
     if (w) *w = v;
     return off;
@@ -955,6 +1180,19 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     KIFMM_HIP(mark(KIFMM_STAGE_PERM, 1));
     const bool far = L >= 2;
     const double rL = t.half_width(L);
+    // adaptive trees: leaf-level scales from the root's, and the W/X steps
+    const bool ad = t.adaptive;
+    const int64_t nw = (int64_t)pl->w_cube_box.size();
+    const double near_scale = ad ? 1.0 / (kFourPi * t.r0) : 1.0 / (kFourPi * rL);
+    const int32_t* lev = ad ? pl->leaf_level : nullptr;
+    const int n_eq = pl->ops().n_eq;
+    // M2T at the points (after the far field, adding to it)
+    auto m2t_eval = [&]() -> hipError_t {
+        if (!far || !ad || pl->n_m2t_leaf == 0) return hipSuccess;
+        return launch_eval_m2t(elt, R, pl->n_m2t_leaf, pl->m2t_leaf, pl->pts, pl->leaf_ptr, pl->leaf_level,
+                               pl->m2t_ptr, pl->m2t_cube, pl->m2t_geo, w.Psi, pl->surf_in, n_eq, nep,
+                               1.0 / (kFourPi * t.r0), pl->perm, out, ld, nrhs, st);
+    };
     // The near field (S2T) runs on the plan's own stream, concurrent with the
     // far-field passes, and the far-field evaluation waits for it. Under
     // stream capture everything stays on the capturing stream instead (near
@@ -968,8 +1206,8 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         KIFMM_HIP(hipStreamWaitEvent(ns, pl->ev_fork, 0));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P], ns));
         KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                      pl->near_leaf, pl->near_code, nullptr, pl->surf, pl->ops().n_eq, nep,
-                                      1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, ns));
+                                      pl->near_leaf, pl->near_code, lev, nullptr, pl->surf, n_eq, nep,
+                                      near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, ns));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P + 1], ns));
         KIFMM_HIP(hipEventRecord(pl->ev_join, ns));
     }
@@ -994,6 +1232,11 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 0));
+    if (far && ad && nw > 0) {
+        // M2T: U~ q~ of every W cube (the adjoint: of the upward pass of its transpose, in P)
+        KIFMM_HIP(launch_gg(pl->d_m2t, elt, pl->Ut, MBe, KPk, n_eq, pl->k, adjoint ? w.P : w.Q, kp, w.Psi, nep, R,
+                            0, st));
+    }
     if (far && pl->st2) {
         // stage 2 (Sec. 3.2): w = V^ q per pair, then p += r_l^-1 U^ w
         const int MBr = pl->rp / 16;
@@ -1008,6 +1251,15 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
             KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->Kt, MBk, KPk, pl->k, pl->k, w.Q, kp, w.P, kp, R, 0, st, pl->b3));
         else
             KIFMM_HIP(launch_gg(pl->d_m2l, elt, pl->KtT, MBk, KPk, pl->k, pl->k, w.P, kp, w.Q, kp, R, 0, st, pl->b3));
+    }
+    if (far && ad && nw > 0) {
+        // S2L: check potentials of the W cubes from the points of their X
+        // leaves, projected by U~^T and added to the M2L result (the adjoint:
+        // the transpose of M2T, into Q)
+        KIFMM_HIP(launch_eval_s2l(elt, R, nw, pl->pts, w.sig_s, pl->leaf_ptr, pl->s2l_ptr, pl->s2l_leaf, pl->s2l_geo,
+                                  pl->surf_in, n_eq, nep, w.CX, st));
+        KIFMM_HIP(launch_gg(pl->d_s2l, elt, pl->UtT, MBk, KPe, pl->k, n_eq, w.CX, nep, adjoint ? w.Q : w.P, kp, R,
+                            1, st));
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 0));
@@ -1031,8 +1283,9 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
             // far field at the points (L2T), added to the near field
             KIFMM_HIP(hipStreamWaitEvent(st, pl->ev_join, 0));
             KIFMM_HIP(launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                          pl->near_leaf, pl->near_code, w.E, pl->surf, pl->ops().n_eq, nep,
-                                          1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
+                                          pl->near_leaf, pl->near_code, lev, w.E, pl->surf, n_eq, nep,
+                                          near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
+            KIFMM_HIP(m2t_eval());
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_L2P, 1));
@@ -1040,9 +1293,9 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         // near field and (when there is one) far field in one kernel
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
         KIFMM_HIP(launch_eval_targets(3, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                      pl->near_leaf, pl->near_code, far ? w.E : nullptr, pl->surf,
-                                      pl->ops().n_eq, nep, 1.0 / (kFourPi * rL), 1.0 / kFourPi, pl->perm, out,
-                                      ld, nrhs, st));
+                                      pl->near_leaf, pl->near_code, lev, far ? w.E : nullptr, pl->surf,
+                                      n_eq, nep, near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
+        KIFMM_HIP(m2t_eval());
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
     }
     if (cur != pl->device) KIFMM_HIP(hipSetDevice(cur));
@@ -1119,6 +1372,8 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     if (!(o.c2 >= 0.0) || !std::isfinite(o.c2)) return fail(KIFMM_EINVAL, "c2 must be finite and >= 0");
     if (o.c2 > 0.0 && (o.dense_m2l || o.precision == KIFMM_BF16X3))
         return fail(KIFMM_EINVAL, "c2 > 0 (stage-2 low rank) needs compressed operators in FP32 or FP64");
+    if (o.adaptive != 0 && o.adaptive != 1) return fail(KIFMM_EINVAL, "adaptive must be 0 or 1");
+    if (o.adaptive && o.depth > 0) return fail(KIFMM_EINVAL, "adaptive trees take no forced depth (opts.depth)");
     const auto t0 = std::chrono::steady_clock::now();
     kifmm_plan_s* pl = new (std::nothrow) kifmm_plan_s();
     if (!pl) return fail(KIFMM_ENOMEM, "host allocation failed");
@@ -1133,7 +1388,8 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     try {
         if (p < 2 || p > 16) throw PlanError{KIFMM_EINVAL, "p must be in [2, 16]"};
         if (!(eps >= 0.0 && eps < 1.0)) throw PlanError{KIFMM_EINVAL, "eps must be in [0, 1)"};
-        pl->tree = build_host_tree(points, n, leaf_size, o.depth, o.max_depth);
+        pl->tree = o.adaptive ? build_adaptive_host_tree(points, n, leaf_size, o.max_depth)
+                              : build_host_tree(points, n, leaf_size, o.depth, o.max_depth);
         pl->ops_sp = host_ops_shared(p, eps, leaf_size, o.cd, o.pinv_rcond, o.dense_m2l != 0, o.c2);
     } catch (const PlanError& e) {
         delete pl;
@@ -1141,6 +1397,16 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     } catch (const std::bad_alloc&) {
         delete pl;
         return fail(KIFMM_ENOMEM, "host allocation failed");
+    }
+    {
+        // the near-field kernel takes at most 64 entries per leaf (27 in a
+        // uniform tree, 57 in a 2:1-balanced one)
+        const HostTree& t = pl->tree;
+        for (int64_t e = 0; e < t.n_leaf(); ++e)
+            if (t.near_ptr[e + 1] - t.near_ptr[e] > 64) {
+                delete pl;
+                return fail(KIFMM_EINVAL, "internal: a leaf has more than 64 near-field leaves");
+            }
     }
     pl->k = pl->ops().k;
     pl->st2 = o.c2 > 0.0;
@@ -1202,6 +1468,12 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         for (size_t l = 0; l < pl->h_down.size(); ++l) pl->d_down[l] = upload_sched(up, pl->h_down[l], pl->elt);
         if (up.err == KIFMM_OK && tune) autotune_m2l(pl, up);
         if (up.err == KIFMM_OK && pl->st2 && t.depth >= 2) upload_stage2(pl, up);
+        if (up.err == KIFMM_OK && t.adaptive) {
+            if (pl->elt == 4)
+                upload_adaptive<float>(pl, up);
+            else
+                upload_adaptive<double>(pl, up);
+        }
         if (up.err == KIFMM_OK &&
             (hipStreamCreateWithFlags(&pl->near_stream, hipStreamNonBlocking) != hipSuccess ||
              hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -1299,6 +1571,63 @@ int kifmm_plan_info(kifmm_plan_t plan, kifmm_info_t* info) {
 int kifmm_plan_export_tree(kifmm_plan_t plan, int32_t* leaf_coords) {
     if (!plan || !leaf_coords) return fail(KIFMM_EINVAL, "plan and leaf_coords must be non-NULL");
     std::memcpy(leaf_coords, plan->tree.leaf_coords.data(), sizeof(int32_t) * 3 * plan->tree.n);
+    return KIFMM_OK;
+}
+
+int kifmm_plan_export_point_leaves(kifmm_plan_t plan, int32_t* out) {
+    if (!plan || !out) return fail(KIFMM_EINVAL, "plan and out must be non-NULL");
+    const HostTree& t = plan->tree;
+    for (int64_t e = 0; e < t.n_leaf(); ++e) {
+        int64_t c[3];
+        const int l = box_cube(t, box_of_leaf(t, e), c);
+        for (int32_t i = t.leaf_ptr[e]; i < t.leaf_ptr[e + 1]; ++i) {
+            int32_t* o = out + 4 * (int64_t)t.perm[i];
+            o[0] = l;
+            o[1] = (int32_t)c[0];
+            o[2] = (int32_t)c[1];
+            o[3] = (int32_t)c[2];
+        }
+    }
+    return KIFMM_OK;
+}
+
+int kifmm_plan_export_boxes(kifmm_plan_t plan, int32_t* out, int64_t* count) {
+    if (!plan || !count) return fail(KIFMM_EINVAL, "plan and count must be non-NULL");
+    const HostTree& t = plan->tree;
+    *count = t.n_box();
+    if (!out) return KIFMM_OK;
+    for (int64_t g = 0; g < t.n_box(); ++g) {
+        int64_t c[3];
+        int32_t* o = out + 5 * g;
+        o[0] = box_cube(t, g, c);
+        o[1] = (int32_t)c[0];
+        o[2] = (int32_t)c[1];
+        o[3] = (int32_t)c[2];
+        o[4] = (int32_t)leaf_of_box(t, g);
+    }
+    return KIFMM_OK;
+}
+
+int kifmm_plan_export_list(kifmm_plan_t plan, int which, int32_t* out, int64_t* count) {
+    if (!plan || !count) return fail(KIFMM_EINVAL, "plan and count must be non-NULL");
+    if (which < 0 || which > 3) return fail(KIFMM_EINVAL, "which must be in [0, 3]");
+    const HostTree& t = plan->tree;
+    // CSR over targets: U and W over leaves, V and X over boxes
+    const std::vector<int32_t>* ptr = nullptr;
+    const std::vector<int32_t>* src = nullptr;
+    bool tgt_leaf = false, src_leaf = false;
+    if (which == 0) { ptr = &t.near_ptr; src = &t.near_leaf; tgt_leaf = src_leaf = true; }
+    if (which == 1) { ptr = &t.v_ptr; src = &t.v_src; }
+    if (which == 2) { ptr = &t.w_ptr; src = &t.w_src; tgt_leaf = true; }
+    if (which == 3) { ptr = &t.x_ptr; src = &t.x_src; src_leaf = true; }
+    *count = (int64_t)src->size();
+    if (!out || src->empty()) return KIFMM_OK;
+    int64_t q = 0;
+    for (size_t i = 0; i + 1 < ptr->size(); ++i)
+        for (int32_t k = (*ptr)[i]; k < (*ptr)[i + 1]; ++k, ++q) {
+            out[2 * q] = (int32_t)(tgt_leaf ? box_of_leaf(t, (int64_t)i) : (int64_t)i);
+            out[2 * q + 1] = (int32_t)(src_leaf ? box_of_leaf(t, (*src)[k]) : (*src)[k]);
+        }
     return KIFMM_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <list>
 #include <mutex>
 #include <tuple>
+#include <unordered_map>
 
 #include <algorithm>
 #include <cmath>
@@ -126,14 +127,36 @@ void offset_of_class(int cls, int* t) {
     t[0] = t[1] = t[2] = 0;
 }
 
-HostTree build_host_tree(const double* pts, int64_t n, int leaf_size, int depth_override,
-                         int max_depth) {
+int box_cube(const HostTree& t, int64_t g, int64_t c[3]) {
+    int l = 0;
+    while (t.level_begin[l + 1] <= g) ++l;
+    unmorton(t.box_key[g], c);
+    return l;
+}
+
+int64_t leaf_of_box(const HostTree& t, int64_t g) {
+    if (t.adaptive) return t.box_leaf[g];
+    return g >= t.level_begin[t.depth] ? g - t.level_begin[t.depth] : -1;
+}
+
+int64_t box_of_leaf(const HostTree& t, int64_t e) {
+    return t.adaptive ? t.leaf_box[e] : t.level_begin[t.depth] + e;
+}
+
+namespace {
+
+// Checks of the arguments shared by both tree builders.
+void check_tree_args(int64_t n, int leaf_size, int max_depth) {
     if (n < 1) throw PlanError{-1, "n must be >= 1"};
     if (leaf_size < 1) throw PlanError{-1, "leaf_size must be >= 1"};
     if (max_depth < 0 || max_depth > MAX_LEVEL) throw PlanError{-1, "max_depth must be in [0, 20]"};
-    if (depth_override < 0 || depth_override > MAX_LEVEL) throw PlanError{-1, "depth must be in [0, 20]"};
     if (n > (int64_t)INT32_MAX / 2) throw PlanError{-1, "n too large"};
-    HostTree t;
+}
+
+// Root cube, integer coordinates (caller order, 3 per point, into q) and the
+// Morton order of the points: fills t.n, t.centre, t.r0 and t.perm and
+// returns the sorted Morton keys.
+std::vector<uint64_t> sort_points(const double* pts, int64_t n, HostTree& t, std::vector<int64_t>& q) {
     t.n = n;
     double lo[3], hi[3];
     for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
@@ -152,7 +175,7 @@ HostTree build_host_tree(const double* pts, int64_t n, int leaf_size, int depth_
     t.r0 = ext > 0 ? ext / 2.0 * (1.0 + std::ldexp(1.0, -20)) : 1.0;
     const double qmax = double((1 << QBITS) - 1);
     std::vector<uint64_t> key(n);
-    std::vector<int64_t> q(3 * n);
+    q.resize(3 * n);
     for (int64_t i = 0; i < n; ++i) {
         for (int a = 0; a < 3; ++a) {
             double base = t.centre[a] - t.r0;
@@ -167,6 +190,20 @@ HostTree build_host_tree(const double* pts, int64_t n, int leaf_size, int depth_
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
     std::vector<uint64_t> skey(n);
     for (int64_t i = 0; i < n; ++i) skey[i] = key[order[i]];
+    t.perm = std::move(order);
+    return skey;
+}
+
+}  // namespace
+
+HostTree build_host_tree(const double* pts, int64_t n, int leaf_size, int depth_override,
+                         int max_depth) {
+    check_tree_args(n, leaf_size, max_depth);
+    if (depth_override < 0 || depth_override > MAX_LEVEL) throw PlanError{-1, "depth must be in [0, 20]"};
+    HostTree t;
+    std::vector<int64_t> q;
+    const std::vector<uint64_t> skey = sort_points(pts, n, t, q);
+    const std::vector<int32_t>& order = t.perm;
 
     int L = depth_override;
     if (L == 0 && depth_override == 0) {
@@ -189,7 +226,6 @@ HostTree build_host_tree(const double* pts, int64_t n, int leaf_size, int depth_
         }
     }
     t.depth = L;
-    t.perm = order;
 
     // per-level unique keys, leaves first
     std::vector<std::vector<uint64_t>> lk(L + 1);
@@ -309,6 +345,319 @@ HostTree build_host_tree(const double* pts, int64_t n, int leaf_size, int depth_
         for (int64_t b = 0; b < nb; ++b) t.v_ptr[b + 1] = t.v_ptr[b] + (int32_t)vs[b].size();
         t.v_src.reserve(t.v_ptr[nb]);
         t.v_cls.reserve(t.v_ptr[nb]);
+        for (int64_t b = 0; b < nb; ++b) {
+            t.v_src.insert(t.v_src.end(), vs[b].begin(), vs[b].end());
+            t.v_cls.insert(t.v_cls.end(), vc[b].begin(), vc[b].end());
+        }
+    }
+    return t;
+}
+
+namespace {
+
+// Whether the closed cubes (la, ca) and (lb, cb), la <= lb, share a point.
+inline bool cubes_touch(int la, const int64_t* ca, int lb, const int64_t* cb) {
+    const int s = lb - la;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t lo = ca[a] << s, hi = (ca[a] + 1) << s;
+        if (cb[a] > hi || cb[a] + 1 < lo) return false;
+    }
+    return true;
+}
+
+struct ANode {
+    uint64_t key;    // Morton key at the node's level
+    int32_t b, e;    // range of sorted points
+    bool leaf;
+};
+
+}  // namespace
+
+HostTree build_adaptive_host_tree(const double* pts, int64_t n, int leaf_size, int max_depth) {
+    check_tree_args(n, leaf_size, max_depth);
+    HostTree t;
+    t.adaptive = true;
+    std::vector<int64_t> q;
+    const std::vector<uint64_t> skey = sort_points(pts, n, t, q);
+    std::vector<std::vector<ANode>> lv(max_depth + 1);
+    std::vector<std::unordered_map<uint64_t, int32_t>> at(max_depth + 1);
+    auto add = [&](int l, uint64_t key, int32_t b, int32_t e) {
+        at[l][key] = (int32_t)lv[l].size();
+        lv[l].push_back(ANode{key, b, e, true});
+    };
+    // the nonempty children of node idx at level l (a contiguous run of the
+    // sorted points each), all new leaves
+    auto split = [&](int l, int32_t idx) {
+        lv[l][idx].leaf = false;
+        const int32_t b = lv[l][idx].b, e = lv[l][idx].e;
+        const int shift = 3 * (QBITS - l - 1);
+        int32_t i = b;
+        while (i < e) {
+            const uint64_t ck = skey[i] >> shift;
+            int32_t j = i + 1;
+            while (j < e && (skey[j] >> shift) == ck) ++j;
+            add(l + 1, ck, i, j);
+            i = j;
+        }
+    };
+    add(0, 0, 0, (int32_t)n);
+    {
+        std::vector<std::pair<int, int32_t>> work{{0, 0}};
+        while (!work.empty()) {
+            const auto [l, idx] = work.back();
+            work.pop_back();
+            if (lv[l][idx].e - lv[l][idx].b > leaf_size && l < max_depth) {
+                const size_t first = lv[l + 1].size();
+                split(l, idx);
+                for (size_t c = first; c < lv[l + 1].size(); ++c) work.push_back({l + 1, (int32_t)c});
+            }
+        }
+    }
+    // 2:1 balance in rounds. A leaf A touching a leaf F two or more levels
+    // finer contains a same-level neighbour cube of F; it is the deepest
+    // existing cube holding that neighbour cube, so F's 26 neighbours find it.
+    for (;;) {
+        std::vector<std::pair<int, int32_t>> marks;
+        for (int l = 2; l <= max_depth; ++l) {
+            const int64_t side = int64_t(1) << l;
+            for (const ANode& f : lv[l]) {
+                if (!f.leaf) continue;
+                int64_t c[3];
+                unmorton(f.key, c);
+                for (int d = 0; d < 27; ++d) {
+                    if (d == 13) continue;
+                    const int64_t nb[3] = {c[0] + d / 9 - 1, c[1] + (d / 3) % 3 - 1, c[2] + d % 3 - 1};
+                    if (nb[0] < 0 || nb[1] < 0 || nb[2] < 0 || nb[0] >= side || nb[1] >= side || nb[2] >= side) continue;
+                    const uint64_t nk = morton(nb[0], nb[1], nb[2]);
+                    for (int m = l; m >= 0; --m) {
+                        auto it = at[m].find(nk >> (3 * (l - m)));
+                        if (it == at[m].end()) continue;
+                        if (m <= l - 2 && lv[m][it->second].leaf) marks.push_back({m, it->second});
+                        break;
+                    }
+                }
+            }
+        }
+        if (marks.empty()) break;
+        std::sort(marks.begin(), marks.end());
+        marks.erase(std::unique(marks.begin(), marks.end()), marks.end());
+        for (const auto& [m, idx] : marks) split(m, idx);
+    }
+    int D = 0;
+    for (int l = 0; l <= max_depth; ++l)
+        if (!lv[l].empty()) D = l;
+    t.depth = D;
+    // global numbering: per level the leaves, then the split cubes, each in Morton order
+    std::vector<std::vector<int32_t>> gid(D + 1);
+    t.level_begin.assign(D + 2, 0);
+    t.level_leaves.assign(D + 1, 0);
+    std::vector<std::pair<int, int32_t>> node_of;   // global box -> (level, node)
+    for (int l = 0; l <= D; ++l) {
+        std::vector<int32_t> idx(lv[l].size());
+        std::iota(idx.begin(), idx.end(), 0);
+        std::sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+            if (lv[l][a].leaf != lv[l][b].leaf) return lv[l][a].leaf;
+            return lv[l][a].key < lv[l][b].key;
+        });
+        gid[l].assign(lv[l].size(), -1);
+        for (int32_t i : idx) {
+            gid[l][i] = (int32_t)node_of.size();
+            node_of.push_back({l, i});
+            if (lv[l][i].leaf) ++t.level_leaves[l];
+        }
+        t.level_begin[l + 1] = (int64_t)node_of.size();
+    }
+    const int64_t nb = t.n_box();
+    t.box_key.resize(nb);
+    t.box_parent.assign(nb, -1);
+    t.box_child.assign(8 * nb, -1);
+    t.box_leaf.assign(nb, -1);
+    for (int64_t g = 0; g < nb; ++g) {
+        const auto [l, i] = node_of[g];
+        t.box_key[g] = lv[l][i].key;
+        if (l > 0) {
+            const int32_t p = gid[l - 1][at[l - 1].at(lv[l][i].key >> 3)];
+            t.box_parent[g] = p;
+            t.box_child[8 * (int64_t)p + (lv[l][i].key & 7)] = (int32_t)g;
+        }
+    }
+    // leaves in the order of their points
+    std::vector<int32_t> leaves;
+    for (int64_t g = 0; g < nb; ++g)
+        if (lv[node_of[g].first][node_of[g].second].leaf) leaves.push_back((int32_t)g);
+    auto first_point = [&](int32_t g) { return lv[node_of[g].first][node_of[g].second].b; };
+    std::sort(leaves.begin(), leaves.end(), [&](int32_t a, int32_t b) { return first_point(a) < first_point(b); });
+    const int64_t nleaf = (int64_t)leaves.size();
+    t.leaf_ptr.resize(nleaf + 1);
+    t.leaf_box = leaves;
+    t.leaf_level.resize(nleaf);
+    for (int64_t e = 0; e < nleaf; ++e) {
+        const auto [l, i] = node_of[leaves[e]];
+        t.leaf_ptr[e] = lv[l][i].b;
+        t.leaf_level[e] = l;
+        t.box_leaf[leaves[e]] = (int32_t)e;
+        if (e > 0 && lv[node_of[leaves[e - 1]].first][node_of[leaves[e - 1]].second].e != lv[l][i].b)
+            throw PlanError{-1, "internal: leaves do not partition the points"};
+    }
+    t.leaf_ptr[nleaf] = (int32_t)n;
+    // coordinates in the units of each point's own leaf
+    t.u.resize(3 * n);
+    for (int64_t e = 0; e < nleaf; ++e) {
+        const int l = t.leaf_level[e];
+        const double r = t.half_width(l);
+        int64_t c[3];
+        unmorton(t.box_key[t.leaf_box[e]], c);
+        for (int32_t i = t.leaf_ptr[e]; i < t.leaf_ptr[e + 1]; ++i)
+            for (int a = 0; a < 3; ++a) {
+                const double centre = (t.centre[a] - t.r0) + (2.0 * double(c[a]) + 1.0) * r;
+                t.u[3 * (int64_t)i + a] = (pts[3 * (int64_t)t.perm[i] + a] - centre) / r;
+            }
+    }
+    t.leaf_coords.resize(3 * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < 3; ++a) t.leaf_coords[3 * i + a] = (int32_t)(q[3 * i + a] >> (QBITS - D));
+    auto find = [&](int l, uint64_t key) -> int32_t {
+        if (l < 0 || l > D) return -1;
+        auto it = at[l].find(key);
+        return it == at[l].end() ? -1 : gid[l][it->second];
+    };
+    auto level_of = [&](int64_t g) {
+        int l = 0;
+        while (t.level_begin[l + 1] <= g) ++l;
+        return l;
+    };
+    // U (near field with codes) and W lists of every leaf
+    t.near_ptr.assign(nleaf + 1, 0);
+    t.w_ptr.assign(nleaf + 1, 0);
+    {
+        std::vector<std::vector<int32_t>> nl(nleaf), nc(nleaf), wl(nleaf);
+        std::vector<std::string> errs(nleaf);
+        parallel_for(nleaf, [&](int64_t e) {
+            const int l = t.leaf_level[e];
+            const int64_t side = int64_t(1) << l;
+            int64_t c[3];
+            unmorton(t.box_key[t.leaf_box[e]], c);
+            auto add_near = [&](int32_t g, int ls) {
+                const int32_t s = t.box_leaf[g];
+                for (int32_t v : nl[e])
+                    if (v == s) return;
+                int64_t sc[3];
+                unmorton(t.box_key[g], sc);
+                int m = 0, off[3];
+                for (int a = 0; a < 3; ++a) {
+                    if (ls == l) {
+                        off[a] = (int)(2 * (sc[a] - c[a]));
+                    } else if (ls == l + 1) {
+                        m = 1;
+                        off[a] = (int)((2 * sc[a] + 1) - (4 * c[a] + 2));
+                    } else if (ls == l - 1) {
+                        m = 2;
+                        off[a] = (int)((4 * sc[a] + 2) - (2 * c[a] + 1));
+                    } else {
+                        errs[e] = "internal: near-field leaves more than one level apart";
+                        return;
+                    }
+                    if (off[a] < -4 || off[a] > 4) {
+                        errs[e] = "internal: near-field offset out of range";
+                        return;
+                    }
+                }
+                nl[e].push_back(s);
+                nc[e].push_back(m * 729 + (off[0] + 4) * 81 + (off[1] + 4) * 9 + (off[2] + 4));
+            };
+            std::vector<std::pair<int32_t, int>> stack;
+            for (int d = 0; d < 27; ++d) {
+                const int64_t pc[3] = {c[0] + d / 9 - 1, c[1] + (d / 3) % 3 - 1, c[2] + d % 3 - 1};
+                if (pc[0] < 0 || pc[1] < 0 || pc[2] < 0 || pc[0] >= side || pc[1] >= side || pc[2] >= side) continue;
+                const uint64_t pk = morton(pc[0], pc[1], pc[2]);
+                const int32_t g = find(l, pk);
+                if (g >= 0) {
+                    // a same-level neighbour (or the leaf itself): its touching leaves
+                    // are near, its first descendants that do not touch are W
+                    stack.assign(1, {g, l});
+                    while (!stack.empty()) {
+                        const auto [h, lh] = stack.back();
+                        stack.pop_back();
+                        if (t.box_leaf[h] >= 0) {
+                            add_near(h, lh);
+                            continue;
+                        }
+                        for (int o = 0; o < 8; ++o) {
+                            const int32_t ch = t.box_child[8 * (int64_t)h + o];
+                            if (ch < 0) continue;
+                            int64_t cc[3];
+                            unmorton(t.box_key[ch], cc);
+                            if (cubes_touch(l, c, lh + 1, cc))
+                                stack.push_back({ch, lh + 1});
+                            else
+                                wl[e].push_back(ch);
+                        }
+                    }
+                } else {
+                    // the coarser leaf holding the neighbour cube, if any
+                    for (int m = l - 1; m >= 0; --m) {
+                        const int32_t h = find(m, pk >> (3 * (l - m)));
+                        if (h < 0) continue;
+                        if (t.box_leaf[h] >= 0) add_near(h, m);
+                        break;
+                    }
+                }
+            }
+        });
+        for (int64_t e = 0; e < nleaf; ++e)
+            if (!errs[e].empty()) throw PlanError{-1, errs[e]};
+        for (int64_t e = 0; e < nleaf; ++e) {
+            t.near_ptr[e + 1] = t.near_ptr[e] + (int32_t)nl[e].size();
+            t.w_ptr[e + 1] = t.w_ptr[e] + (int32_t)wl[e].size();
+        }
+        for (int64_t e = 0; e < nleaf; ++e) {
+            t.near_leaf.insert(t.near_leaf.end(), nl[e].begin(), nl[e].end());
+            t.near_code.insert(t.near_code.end(), nc[e].begin(), nc[e].end());
+            std::sort(wl[e].begin(), wl[e].end());
+            t.w_src.insert(t.w_src.end(), wl[e].begin(), wl[e].end());
+        }
+    }
+    // X lists: the dual of W
+    {
+        std::vector<int32_t> cnt(nb + 1, 0);
+        for (int32_t g : t.w_src) ++cnt[g + 1];
+        t.x_ptr.assign(nb + 1, 0);
+        for (int64_t g = 0; g < nb; ++g) t.x_ptr[g + 1] = t.x_ptr[g] + cnt[g + 1];
+        t.x_src.assign(t.w_src.size(), -1);
+        std::vector<int32_t> fill(t.x_ptr.begin(), t.x_ptr.end() - 1);
+        for (int64_t e = 0; e < nleaf; ++e)
+            for (int32_t k = t.w_ptr[e]; k < t.w_ptr[e + 1]; ++k) t.x_src[fill[t.w_src[k]]++] = (int32_t)e;
+    }
+    // V lists of every box at levels 2..D: children of the parent's
+    // same-level neighbours that do not share a vertex with the box
+    t.v_ptr.assign(nb + 1, 0);
+    {
+        std::vector<std::vector<int32_t>> vs(nb), vc(nb);
+        const int64_t b2 = D >= 2 ? t.level_begin[2] : nb;
+        parallel_for(nb - b2, [&](int64_t off) {
+            const int64_t b = b2 + off;
+            const int l = level_of(b);
+            const int64_t pside = int64_t(1) << (l - 1);
+            int64_t c[3];
+            unmorton(t.box_key[b], c);
+            const int64_t pc[3] = {c[0] >> 1, c[1] >> 1, c[2] >> 1};
+            for (int d = 0; d < 27; ++d) {
+                const int64_t pn[3] = {pc[0] + d / 9 - 1, pc[1] + (d / 3) % 3 - 1, pc[2] + d % 3 - 1};
+                if (pn[0] < 0 || pn[1] < 0 || pn[2] < 0 || pn[0] >= pside || pn[1] >= pside || pn[2] >= pside) continue;
+                const int32_t p = find(l - 1, morton(pn[0], pn[1], pn[2]));
+                if (p < 0) continue;
+                for (int o = 0; o < 8; ++o) {
+                    const int32_t ch = t.box_child[8 * (int64_t)p + o];
+                    if (ch < 0) continue;
+                    const int64_t cc[3] = {2 * pn[0] + ((o >> 2) & 1), 2 * pn[1] + ((o >> 1) & 1), 2 * pn[2] + (o & 1)};
+                    const int tx = (int)(c[0] - cc[0]), ty = (int)(c[1] - cc[1]), tz = (int)(c[2] - cc[2]);
+                    if (std::max(std::abs(tx), std::max(std::abs(ty), std::abs(tz))) < 2) continue;
+                    vs[b].push_back(ch);
+                    vc[b].push_back(class_of_offset(tx, ty, tz));
+                }
+            }
+        });
+        for (int64_t b = 0; b < nb; ++b) t.v_ptr[b + 1] = t.v_ptr[b] + (int32_t)vs[b].size();
         for (int64_t b = 0; b < nb; ++b) {
             t.v_src.insert(t.v_src.end(), vs[b].begin(), vs[b].end());
             t.v_cls.insert(t.v_cls.end(), vc[b].begin(), vc[b].end());

@@ -41,16 +41,48 @@ struct HostTree {
     std::vector<int32_t> v_src;         // source box (global index)
     std::vector<int32_t> v_cls;         // offset class of (target - source)
     std::vector<int32_t> leaf_coords;   // per caller point: level-depth cube (3 ints)
+    // Adaptive trees (build_adaptive_host_tree): leaves at several levels. The
+    // boxes of a level are its leaves, then its split cubes, each in Morton
+    // order; leaf indices follow the sorted points. Points are in the units of
+    // their own leaf. Near-field codes there are m * 729 + (ox+4) * 81 +
+    // (oy+4) * 9 + (oz+4): m = 0 source at the target's level, 1 one level
+    // finer, 2 one level coarser; o = (source centre - target centre) in
+    // half-widths of the finer of the two leaves.
+    bool adaptive = false;
+    std::vector<int64_t> level_leaves;  // leaves of each level
+    std::vector<int32_t> box_leaf;      // leaf index of a box, -1 for a split cube
+    std::vector<int32_t> leaf_box;      // global box index of a leaf
+    std::vector<int32_t> leaf_level;    // level of a leaf
+    std::vector<int32_t> w_ptr, w_src;  // W lists: CSR over leaves, source cube (global index)
+    std::vector<int32_t> x_ptr, x_src;  // X lists: CSR over boxes, source leaf (leaf index)
 
     int64_t n_box() const { return level_begin.back(); }
-    int64_t n_leaf() const { return level_begin[depth + 1] - level_begin[depth]; }
+    int64_t n_leaf() const { return (int64_t)leaf_ptr.size() - 1; }
     int64_t level_count(int l) const { return level_begin[l + 1] - level_begin[l]; }
     double half_width(int l) const { return r0 / double(int64_t(1) << l); }
 };
 
+// Level of global box g and its integer coordinates at that level.
+int box_cube(const HostTree& t, int64_t g, int64_t c[3]);
+// Leaf index of global box g (-1 for a split cube) and global box of leaf e,
+// for both kinds of tree.
+int64_t leaf_of_box(const HostTree& t, int64_t g);
+int64_t box_of_leaf(const HostTree& t, int64_t e);
+
 // Builds the tree; throws PlanError on invalid input.
 HostTree build_host_tree(const double* pts, int64_t n, int leaf_size, int depth_override,
                          int max_depth);
+
+// Adaptive octree (Sec. 2.1 read cube by cube): a cube holding more than
+// leaf_size points is split into its nonempty children, down to max_depth;
+// then 2:1 balance in rounds, every leaf sharing a vertex with a leaf two or
+// more levels finer being split, all at once, until none is left. Lists of
+// the kernel-independent FMM between leaves of different levels: U (near
+// field: leaves of any level sharing a vertex), V (as the uniform tree, at
+// every level >= 2), W (cubes below a same-level neighbour of a leaf whose
+// parent shares a vertex with the leaf but which do not) and X (the dual of
+// W). Throws PlanError on invalid input.
+HostTree build_adaptive_host_tree(const double* pts, int64_t n, int leaf_size, int max_depth);
 
 struct HostOps {
     int p = 0, n_eq = 0, k = 0;

@@ -73,6 +73,42 @@ static void run(const std::vector<double>& pts, int leaf, const char* name) {
                 (long long)t.n_leaf(), (long long)t.n_box(), t.v_src.size(), o.k, o.r2max);
 }
 
+// Adaptive tree: structure and list invariants (leaves partition the points,
+// points within their leaf, near sources within one level, W/X duality).
+static void run_adaptive(const std::vector<double>& pts, int leaf, const char* name) {
+    const int64_t n = (int64_t)pts.size() / 3;
+    HostTree t = build_adaptive_host_tree(pts.data(), n, leaf, 16);
+    CHECK(t.adaptive && t.n == n && t.leaf_ptr.front() == 0 && t.leaf_ptr.back() == n);
+    const int64_t nl = t.n_leaf();
+    CHECK((int64_t)t.leaf_box.size() == nl && (int64_t)t.leaf_level.size() == nl);
+    for (int64_t e = 0; e < nl; ++e) {
+        CHECK(t.leaf_ptr[e] < t.leaf_ptr[e + 1]);
+        CHECK(t.box_leaf[t.leaf_box[e]] == e);
+        CHECK(t.leaf_ptr[e + 1] - t.leaf_ptr[e] <= leaf || t.leaf_level[e] == 16);
+        CHECK(t.near_ptr[e + 1] - t.near_ptr[e] <= 64);
+        for (int32_t q = t.near_ptr[e]; q < t.near_ptr[e + 1]; ++q) {
+            const int32_t s = t.near_leaf[q];
+            CHECK(s >= 0 && s < nl);
+            if (s >= 0 && s < nl) CHECK(std::abs(t.leaf_level[s] - t.leaf_level[e]) <= 1);
+            CHECK(t.near_code[q] >= 0 && t.near_code[q] < 3 * 729);
+        }
+    }
+    for (double u : t.u) CHECK(std::fabs(u) <= 1.0);
+    int64_t wx = 0;
+    for (int32_t g : t.w_src) CHECK(g >= 0 && g < t.n_box());
+    for (int64_t g = 0; g < t.n_box(); ++g)
+        for (int32_t k = t.x_ptr[g]; k < t.x_ptr[g + 1]; ++k, ++wx) {
+            const int32_t e = t.x_src[k];
+            CHECK(e >= 0 && e < nl);
+            bool found = false;
+            for (int32_t q = t.w_ptr[e]; q < t.w_ptr[e + 1]; ++q) found |= t.w_src[q] == g;
+            CHECK(found);
+        }
+    CHECK(wx == (int64_t)t.w_src.size());
+    std::printf("%s (adaptive): n=%lld depth=%d leaves=%lld boxes=%lld v=%zu w=%zu\n", name, (long long)n, t.depth,
+                (long long)nl, (long long)t.n_box(), t.v_src.size(), t.w_src.size());
+}
+
 int main() {
     std::mt19937_64 rng(1211);
     std::uniform_real_distribution<double> u(-1.0, 1.0);
@@ -91,6 +127,13 @@ int main() {
         for (int a = 0; a < 3; ++a) sphere.push_back(sphere[a]);
     run(cube, 32, "cube");
     run(sphere, 16, "sphere+duplicates");
+    // a tight cluster in a sparse background: leaves over many levels
+    std::vector<double> clus(cube.begin(), cube.begin() + 3 * 500);
+    std::normal_distribution<double> g(0.0, 0.01);
+    for (int i = 0; i < 2000; ++i)
+        for (int a = 0; a < 3; ++a) clus.push_back(0.5 + g(rng));
+    run_adaptive(clus, 16, "cluster");
+    run_adaptive(sphere, 16, "sphere+duplicates");
     try {
         std::vector<double> bad{0.0, 0.0, NAN};
         build_host_tree(bad.data(), 1, 8, 0, 16);

@@ -28,11 +28,8 @@ from oracle.adaptive import build_adaptive_tree, fmm_adaptive, is_ancestor_or_se
 def clustered(n_bg=1500, n_cl=2500, seed=3):
     """Sparse uniform background plus a dense Gaussian cluster: leaves from
     level 2 to level 8."""
-    rng = np.random.default_rng(seed)
-    a = rng.uniform(-1, 1, (n_bg, 3))
-    b = 0.02 * rng.standard_normal((n_cl, 3)) + np.array([0.5, 0.5, 0.5])
-    x = np.concatenate([a, b])
-    return x, rng.uniform(-1, 1, x.shape[0])
+    x = workloads.clustered_points(n_bg, n_cl, seed)
+    return x, workloads.uniform_density(x.shape[0], seed + 100)
 
 
 @functools.lru_cache(maxsize=None)
@@ -96,6 +93,21 @@ def test_fmm_vs_direct_clustered(mode):
         errs.append(float(np.linalg.norm(phi - d) / np.linalg.norm(d)))
     print(f"clustered {mode}: p=4 {errs[0]:.3e}, p=6 {errs[1]:.3e}")
     assert errs[0] < 5e-4 and errs[1] < 1e-5 and errs[1] < errs[0] / 10
+
+
+def test_stage2_adaptive_vs_direct_and_dense():
+    # stage-2 factors (Sec. 3.2, C2 = 10) on the adaptive tree: within the
+    # uniform tree's stage-2 bar of the dense result, and of the direct sum
+    x, s = clustered()
+    t = clustered_tree()
+    d = oracle.direct(x, s)
+    dense = fmm_adaptive(x, s, _ops(6, 1e-8, 24, "dense"), t)
+    ops2 = oracle.build_operators(6, 1e-6, 24, mode="svd2", c2=10.0)
+    phi = fmm_adaptive(x, s, ops2, t)
+    e_dense = float(np.linalg.norm(phi - dense) / np.linalg.norm(dense))
+    e_direct = float(np.linalg.norm(phi - d) / np.linalg.norm(d))
+    print(f"stage 2 adaptive: vs dense {e_dense:.3e}, vs direct {e_direct:.3e}")
+    assert e_dense < 5e-6 and e_direct < 1e-5
 
 
 def test_fmm_vs_direct_ellipsoid():

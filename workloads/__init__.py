@@ -113,6 +113,25 @@ def ellipsoid_points(n: int, seed: int, axes=(2.0, 1.0, 0.5)):
     return cen[idx].copy()
 
 
+def clustered_points(n_bg: int, n_cl: int, seed: int, centre=(0.5, 0.5, 0.5), width: float = 0.02):
+    """n_bg iid uniform points in [-1,1]^3 and a Gaussian cluster of n_cl
+    points (standard deviation `width`) around `centre`: a point set whose
+    cube occupancy varies by orders of magnitude (adaptive-tree workloads)."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(-1.0, 1.0, (n_bg, 3))
+    b = width * rng.standard_normal((n_cl, 3)) + np.asarray(centre, dtype=np.float64)
+    return np.concatenate([a, b])
+
+
+def corner_clusters(n_dense: int, n_sparse: int, seed: int):
+    """A dense Gaussian cluster near (0.9, 0.9, 0.9) and a sparse one near
+    (-0.9, -0.9, -0.9): the sparse octant stays a leaf at level 1."""
+    rng = np.random.default_rng(seed)
+    a = 0.03 * rng.standard_normal((n_dense, 3)) + 0.9
+    b = 0.05 * rng.standard_normal((n_sparse, 3)) - 0.9
+    return np.concatenate([a, b])
+
+
 def uniform_cube(n: int, seed: int):
     """n iid points uniform in the unit cube [0,1]^3."""
     rng = np.random.default_rng(seed)
