@@ -201,6 +201,55 @@ def bench_precision(K, steps, warmup):
     return out
 
 
+def bench_adaptive(K, steps, warmup):
+    """The adaptive tree on the 2^20-point 2:1:0.5 ellipsoid (the precision
+    workload's surface and density), FP32, against the uniform tree on the
+    same points: p = 6, eps = 1e-6 and p = 8, eps = 1e-8, leaf 64; matvec ms,
+    per-stage ms, tree sizes and the error against the oracle's direct sum
+    (and, at p = 8, its dense-M2L KIFMM) at the 256 sampled points."""
+    import numpy as np
+    import torch
+    import workloads
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "p8_samples.json")))
+    x = workloads.ellipsoid_points(g["n"], g["seed"])
+    sig = workloads.sphere_density(x, g["seed"] + 100)
+    e = g["ellipsoid"]
+    idx = np.asarray(e["sample"])
+    sd = torch.tensor(sig, dtype=torch.float32, device="cuda:0")
+    out = {}
+    for p, eps in ((6, 1e-6), (8, 1e-8)):
+        rec = {}
+        for kind in ("uniform", "adaptive"):
+            t0 = time.perf_counter()
+            plan = K.Plan(x, p=p, eps=eps, leaf_size=64, adaptive=(kind == "adaptive"))
+            plan_s = time.perf_counter() - t0
+            o = torch.empty_like(sd)
+            ms = timed_ms(lambda: plan.apply(sd, o), steps, warmup)
+            got = o.double().cpu().numpy()[idx]
+            plan.profile(True)
+            for _ in range(steps):
+                plan.apply(sd, o)
+            torch.cuda.synchronize()
+            st_ms, calls = plan.profile_read()
+            plan.profile(False)
+            info = plan.info()
+            r = {"ms_per_matvec": round(ms, 4), "plan_seconds": round(plan_s, 2),
+                 "stage_ms": {k: round(v / max(calls, 1), 4) for k, v in st_ms.items()},
+                 "n_leaf": info["n_leaf"], "n_box": info["n_box"], "depth": info["depth"],
+                 "leaf_level_min": info["leaf_level_min"], "v_pairs": info["v_pairs"],
+                 "p2p_interactions": info["p2p_interactions"], "w_pairs": info["w_pairs"],
+                 "err_vs_direct_sum": rel(got, e["phi_direct"])}
+            if p == g["p"]:
+                r["err_vs_fp64_dense_oracle"] = rel(got, e["phi_dense"])
+            rec[kind] = r
+            log(f"ellipsoid p={p} {kind}: {ms:.3f} ms, leaves {info['n_leaf']} levels "
+                f"{info['leaf_level_min']}..{info['depth']}, err vs direct {r['err_vs_direct_sum']:.2e}")
+            plan.close()
+        rec["speedup_adaptive_vs_uniform"] = round(rec["uniform"]["ms_per_matvec"] / rec["adaptive"]["ms_per_matvec"], 3)
+        out[f"p{p}"] = rec
+    return out
+
+
 def bench_gradient(K, steps, warmup):
     """The differentiation workload: torus surface N = 262,144 (512 x 256 grid
     triangle centroids), p = 6, FP32; one gradient of 0.5 |F s - b|^2 is one
@@ -261,6 +310,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the batching, p = 8 precision and gradient workloads")
+    ap.add_argument("--only-adaptive", action="store_true",
+                    help="run the adaptive-tree workload only and print its record")
     ap.add_argument("--only", choices=["svd", "dense64", "dense32", "svd_bf16x3", "svd_stage2"], default=None,
                     help="time one plan only (profiling runs); prints no JSON line")
     ap.add_argument("--m2l-shape", type=int, default=-1,
@@ -280,6 +331,9 @@ def main():
     import paper_1211_2517_amd as K
     import workloads
 
+    if args.only_adaptive:
+        print(json.dumps(bench_adaptive(K, args.steps, args.warmup)), flush=True)
+        return
     log("generating the 2^20-point sphere")
     x = workloads.sphere_points(N, workloads.SEED_BASE + 1)
     s = workloads.sphere_density(x, workloads.SEED_BASE + 101)
@@ -421,6 +475,8 @@ def main():
         line["precision_p8"] = bench_precision(K, cs, cw)
         log("differentiation workload (torus gradient)")
         line["gradient_torus"] = bench_gradient(K, cs, cw)
+        log("adaptive tree (2:1:0.5 ellipsoid)")
+        line["adaptive_ellipsoid"] = bench_adaptive(K, cs, cw)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline()
