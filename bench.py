@@ -77,8 +77,8 @@ def traffic_record(info):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1211_2517_amd", "csrc", "kernels.hip"), "rb").read()
-    if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+    src = open(os.path.join(ROOT, "paper_1211_2517_amd", "csrc", "gemm.hip"), "rb").read()
+    if rec.get("gemm_hip_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("bytes_per_launch")
 
@@ -92,8 +92,8 @@ def trace_record(flops):
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_1211_2517_amd", "csrc", "kernels.hip"), "rb").read()
-    if rec.get("kernels_hip_sha256") != hashlib.sha256(src).hexdigest():
+    src = open(os.path.join(ROOT, "paper_1211_2517_amd", "csrc", "gemm.hip"), "rb").read()
+    if rec.get("gemm_hip_sha256") != hashlib.sha256(src).hexdigest():
         return None
     ms = rec["avg_ms"]
     return {"avg_launch_ms": ms, "frac": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),

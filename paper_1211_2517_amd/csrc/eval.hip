@@ -1,0 +1,634 @@
+// Point-evaluation kernels of the KIFMM for gfx950 (CDNA4, wave64).
+//
+// permute_in     densities into the sorted point order.
+// eval_surface   potential of the points of a leaf on the (3-2d) cube surface:
+//                the check potential of S2M (Sec. 2.2) and, in the adjoint,
+//                the transpose of the L2T evaluation.
+// eval_targets   near-field direct sum of eq. (1) over the near field (S2T)
+//                plus the potential of the downward equivalent densities on
+//                the leaf's points (L2T, Sec. 2.2), scattered to caller order.
+// eval_m2t       adaptive trees: equivalent densities of W-list cubes at a
+//                leaf's points (M2T).
+// eval_s2l       adaptive trees: check potentials of a cube from the points of
+//                its X-list leaves (S2L).
+#include "kernels.h"
+
+#include <type_traits>
+
+namespace kifmm {
+
+namespace {
+
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
+template <typename T>
+struct alignas(4 * sizeof(T)) P4 {
+    T x, y, z, w;
+};
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) permute_in_kernel(int64_t n, const int32_t* __restrict__ perm,
+                                                         const T* __restrict__ sigma, int64_t ld,
+                                                         int nrhs, T* __restrict__ sig_s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t src = perm[i];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sig_s[i * R + r] = r < nrhs ? sigma[src + r * ld] : T(0);
+}
+
+// Check potential of a leaf's points on its (3-2d) surface: one wave per
+// leaf, lanes over the surface points. The wave stages the leaf's points as
+// (x, y, z, sigma) 4-vectors in LDS (sigmas of further right-hand sides in a
+// second array), in batches of at most CAP points, so each interaction reads
+// one broadcast LDS vector.
+template <typename T, int R>
+__global__ void __launch_bounds__(256) eval_surface_kernel(int64_t n_leaf, const P4<T>* __restrict__ pts,
+                                                           const T* __restrict__ sig,
+                                                           const int32_t* __restrict__ leaf_ptr,
+                                                           const T* __restrict__ surf, int n_eq,
+                                                           int nep, T* __restrict__ C) {
+    constexpr int WPB = 4;
+    constexpr int CAP = 64;
+    __shared__ P4<T> sp[WPB][CAP];
+    __shared__ T ss[WPB][R > 1 ? CAP * R : 1];
+    const int wave = threadIdx.x >> 6;
+    const int64_t leaf = (int64_t)blockIdx.x * WPB + wave;
+    if (leaf >= n_leaf) return;
+    const int lane = threadIdx.x & 63;
+    P4<T>* st = sp[wave];
+    T* sst = ss[wave];
+    const int p0 = leaf_ptr[leaf];
+    const int p1 = leaf_ptr[leaf + 1];
+    constexpr int NA = (19 * 16 + 63) / 64;   // surface points per lane, at most
+    T sx[NA], sy[NA], sz[NA];
+    T acc[NA][R];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int a = k * 64 + lane;
+        const bool valid = a < n_eq;
+        sx[k] = valid ? surf[3 * a] : T(0);
+        sy[k] = valid ? surf[3 * a + 1] : T(0);
+        sz[k] = valid ? surf[3 * a + 2] : T(0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[k][r] = 0;
+    }
+    const int na = (nep + 63) / 64;
+    for (int base = p0; base < p1; base += CAP) {
+        const int cnt = min(CAP, p1 - base);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const P4<T> v = pts[base + lane];
+            T w0 = T(0);
+            if constexpr (R == 1) {
+                w0 = sig[base + lane];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) sst[lane * R + r] = sig[(int64_t)(base + lane) * R + r];
+            }
+            st[lane] = P4<T>{v.x, v.y, v.z, w0};
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+        for (int jj = 0; jj < cnt; ++jj) {
+            const P4<T> f = st[jj];
+#pragma unroll
+            for (int k = 0; k < NA; ++k) {
+                if (k < na) {
+                    const T dx = sx[k] - f.x, dy = sy[k] - f.y, dz = sz[k] - f.z;
+                    const T rinv = rsq(dx * dx + dy * dy + dz * dz);
+                    if constexpr (R == 1) {
+                        acc[k][0] += f.w * rinv;
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[k][r] += sst[jj * R + r] * rinv;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int a = k * 64 + lane;
+        if (k < na && a < nep) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) C[(leaf * R + r) * nep + a] = a < n_eq ? acc[k][r] : T(0);
+        }
+    }
+}
+
+// Near field (S2T, MODE bit 1) and far field (L2T, MODE bit 2) at the points
+// of a target leaf: one wave per target leaf, `lpt` lanes per target splitting
+// the sources. MODE 1 writes the near field, MODE 2 adds the far field to
+// what is there, MODE 3 writes both.
+// The wave stages the points of its near-field leaves in its own LDS slots
+// as 4-vectors (x, y, z in target-leaf units, sigma for one right-hand side;
+// the sigmas of several right-hand sides sit in a second array), so each
+// interaction reads one broadcast LDS vector; batches of at most CAP points
+// are staged and consumed in turn. The near-field entries (at most 27 in a
+// uniform tree, at most 64 here) are resolved in parallel, one per lane, and
+// a prefix sum of their point counts numbers the staged points, so every
+// staged point is one independent load: a batch costs one memory latency. For the far field the wave stages the
+// leaf's downward equivalent surface as (x, y, z, E) vectors the same way
+// (one right-hand side), or reads E from global memory (several).
+// FP32 near field: the points are also given in fixed point, q = round(u 2^28)
+// (int32; |u| <= 1 in leaf units), and the staged sources carry q - 2^29 d, so
+// every coordinate difference of a near pair is an exact integer that is
+// converted to FP32 once: the distance of a nearly coincident pair keeps full
+// FP32 relative accuracy (with FP32 leaf-unit coordinates it would lose the
+// digits the two coordinates share). The 2^28 scale is taken out in the
+// near-field factor.
+template <typename T, int R, int MODE, bool AD = false>
+__global__ void __launch_bounds__(256) eval_targets_kernel(
+    int64_t n_leaf, const P4<T>* __restrict__ pts, const P4<int32_t>* __restrict__ qpts, const T* __restrict__ sig,
+    const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ near_ptr,
+    const int32_t* __restrict__ near_leaf, const int32_t* __restrict__ near_code,
+    const int32_t* __restrict__ leaf_level, const T* __restrict__ E, const T* __restrict__ surf, int n_eq, int nep,
+    T near_scale, T far_scale, const int32_t* __restrict__ perm, T* __restrict__ out, int64_t ld, int nrhs) {
+    constexpr int WPB = 4;
+    constexpr int CAP = (R >= 8 ? 64 : R >= 2 ? 128 : 256) / (int)(sizeof(T) / 4);
+    constexpr int MAXEQ = 19 * 16;
+    constexpr bool FIX = sizeof(T) == 4;   // fixed-point near-field differences
+    using SP = typename std::conditional<FIX, P4<int32_t>, P4<T>>::type;
+    __shared__ SP sp[(MODE & 1) ? WPB : 1][(MODE & 1) ? CAP : 1];
+    __shared__ T ss[(MODE & 1) ? WPB : 1][(MODE & 1) && R > 1 ? CAP * R : 1];
+    __shared__ P4<T> fs[(MODE & 2) && R == 1 ? WPB : 1][(MODE & 2) && R == 1 ? MAXEQ : 1];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t leaf = (int64_t)blockIdx.x * WPB + wave;
+    if (leaf >= n_leaf) return;
+    SP* st = sp[(MODE & 1) ? wave : 0];
+    // adaptive trees: the leaf's own level sets its unit (near_scale is given
+    // for the root), and leaves above level 2 have no local expansion
+    int lev = 0;
+    if constexpr (AD) lev = leaf_level[leaf];
+    // fixed-point differences are in units of 2^-28 leaf half-widths
+    T nscale = (FIX && (MODE & 1)) ? near_scale * T(268435456.0f) : near_scale;
+    if constexpr (AD) nscale = ldexp(nscale, lev);
+    T* sst = ss[(MODE & 1) ? wave : 0];
+    const int p0 = leaf_ptr[leaf];
+    const int ne = leaf_ptr[leaf + 1] - p0;
+    int lpt = 64;
+    while (lpt > 1 && (64 / lpt) < ne) lpt >>= 1;
+    const int tpr = 64 / lpt;
+    const int sub = lane & (lpt - 1);
+    const int q0 = near_ptr[leaf];
+    const int q1 = near_ptr[leaf + 1];
+    const bool far_on = (MODE & 2) && E != nullptr && (!AD || lev >= 2);
+    // near-field entries, one per lane: first point, point count, offset code,
+    // and the inclusive prefix sum of the counts (the entries' staged ranges).
+    // Adaptive trees take the entries in two passes: sources at the target's
+    // level or coarser (differences in target-leaf units), then sources one
+    // level finer (differences in their units, so the target coordinates are
+    // doubled and the source weights too: exact in both arithmetics).
+    int e_b0 = 0, e_code = 0, e_cnt[2] = {0, 0}, e_incl[2] = {0, 0}, n_near[2] = {0, 0};
+    if constexpr ((MODE & 1) != 0) {
+        const int nq = min(q1 - q0, 64);
+        int cnt = 0, pass = 0;
+        if (lane < nq) {
+            const int nb = near_leaf[q0 + lane];
+            e_code = near_code[q0 + lane];
+            e_b0 = leaf_ptr[nb];
+            cnt = leaf_ptr[nb + 1] - e_b0;
+            if constexpr (AD) pass = (e_code / 729 == 1) ? 1 : 0;
+        }
+        e_cnt[0] = pass == 0 ? cnt : 0;
+        e_cnt[1] = pass == 1 ? cnt : 0;
+#pragma unroll
+        for (int ps = 0; ps < (AD ? 2 : 1); ++ps) {
+            int v0 = e_cnt[ps];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int v = __shfl_up(v0, off);
+                if (lane >= off) v0 += v;
+            }
+            e_incl[ps] = v0;
+            n_near[ps] = __shfl(v0, 63);
+        }
+    }
+    if constexpr ((MODE & 2) && R == 1) {
+        if (far_on) {
+            for (int a = lane; a < n_eq; a += 64)
+                fs[wave][a] = P4<T>{surf[3 * a], surf[3 * a + 1], surf[3 * a + 2], E[leaf * nep + a]};
+        }
+    }
+    for (int tb = 0; tb < ne; tb += tpr) {
+        const int tl = tb + lane / lpt;
+        const bool valid = tl < ne;
+        const int i = p0 + (valid ? tl : 0);
+        const P4<T> ui = pts[i];
+        P4<int32_t> qi{0, 0, 0, 0};
+        if constexpr (FIX && (MODE & 1)) qi = qpts[i];
+        P4<T> ut = ui;          // target coordinates of the current pass
+        P4<int32_t> qt = qi;
+        T acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0;
+        // consume the staged batch of n points
+        auto consume = [&](int n) {
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+            for (int jj = sub; jj < n; jj += lpt) {
+                const SP f = st[jj];
+                T dx, dy, dz, fw;
+                if constexpr (FIX) {
+                    dx = (T)(qt.x - f.x);
+                    dy = (T)(qt.y - f.y);
+                    dz = (T)(qt.z - f.z);
+                    fw = __int_as_float(f.w);
+                } else {
+                    dx = ut.x - f.x;
+                    dy = ut.y - f.y;
+                    dz = ut.z - f.z;
+                    fw = f.w;
+                }
+                const T r2 = dx * dx + dy * dy + dz * dz;
+                const T rinv = r2 > T(0) ? rsq(r2) : T(0);
+                if constexpr (R == 1) {
+                    acc[0] += fw * rinv;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] += sst[jj * R + r] * rinv;
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        };
+#pragma unroll 1
+        for (int ps = 0; ps < (AD ? 2 : 1); ++ps) {
+            const int incl = e_incl[ps], ecnt = e_cnt[ps], nn = n_near[ps];
+            if (ps == 1) {
+                qt = P4<int32_t>{2 * qi.x, 2 * qi.y, 2 * qi.z, 0};
+                ut = P4<T>{T(2) * ui.x, T(2) * ui.y, T(2) * ui.z, T(0)};
+            }
+            // stage and consume the near-field points in batches of CAP
+            for (int base = 0; base < nn; base += CAP) {
+                const int cnt = min(CAP, nn - base);
+#pragma unroll
+                for (int k = 0; k < CAP / 64; ++k) {
+                    const int slot = k * 64 + lane;
+                    const int sidx = base + slot;
+                    // entry of staged point sidx: the number of entries whose
+                    // range ends at or before it (binary search over the lanes)
+                    int e = 0;
+#pragma unroll
+                    for (int stp = 32; stp > 0; stp >>= 1) {
+                        const int v = __shfl(incl, e + stp - 1);
+                        if (v <= sidx) e += stp;
+                    }
+                    e = min(e, 63);
+                    const int b0 = __shfl(e_b0, e);
+                    const int ex = __shfl(incl, e) - __shfl(ecnt, e);
+                    const int code = __shfl(e_code, e);
+                    if (slot < cnt) {
+                        const int jj = b0 + (sidx - ex);
+                        // the source in the units of the pass: a s + o, where a = 2
+                        // for a coarser source (adaptive), and o = (source centre -
+                        // target centre) in those units (uniform: o = -2 d, d =
+                        // target - source cube)
+                        int ox, oy, oz, as = 1;
+                        T wm = T(1);
+                        if constexpr (AD) {
+                            const int m = code / 729, rem = code - 729 * m;
+                            ox = rem / 81 - 4;
+                            oy = (rem / 9) % 9 - 4;
+                            oz = rem % 9 - 4;
+                            as = m == 2 ? 2 : 1;
+                            wm = m == 1 ? T(2) : T(1);
+                        } else {
+                            ox = -2 * (code / 9 - 1);
+                            oy = -2 * ((code / 3) % 3 - 1);
+                            oz = -2 * (code % 3 - 1);
+                        }
+                        T w0 = T(0);
+                        if constexpr (R == 1) {
+                            w0 = wm * sig[jj];
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < R; ++r) sst[slot * R + r] = wm * sig[(int64_t)jj * R + r];
+                        }
+                        if constexpr (FIX) {
+                            const P4<int32_t> sq = qpts[jj];
+                            st[slot] = SP{as * sq.x + ox * (1 << 28), as * sq.y + oy * (1 << 28),
+                                          as * sq.z + oz * (1 << 28), __float_as_int(w0)};
+                        } else {
+                            const P4<T> sv = pts[jj];
+                            st[slot] = SP{T(as) * sv.x + T(ox), T(as) * sv.y + T(oy), T(as) * sv.z + T(oz), w0};
+                        }
+                    }
+                }
+                consume(cnt);
+            }
+        }
+        T far[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) far[r] = 0;
+        if (far_on) {
+            if constexpr ((MODE & 2) && R == 1) {
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+                for (int a = sub; a < n_eq; a += lpt) {
+                    const P4<T> f = fs[wave][a];
+                    const T dx = ui.x - f.x, dy = ui.y - f.y, dz = ui.z - f.z;
+                    far[0] += f.w * rsq(dx * dx + dy * dy + dz * dz);
+                }
+            } else {
+                for (int a = sub; a < n_eq; a += lpt) {
+                    const T dx = ui.x - surf[3 * a], dy = ui.y - surf[3 * a + 1], dz = ui.z - surf[3 * a + 2];
+                    const T rinv = rsq(dx * dx + dy * dy + dz * dz);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) far[r] += E[(leaf * R + r) * nep + a] * rinv;
+                }
+            }
+        }
+        for (int off = lpt >> 1; off > 0; off >>= 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                acc[r] += __shfl_xor(acc[r], off);
+                far[r] += __shfl_xor(far[r], off);
+            }
+        }
+        if (valid && sub == 0) {
+            const int64_t dst = perm[i];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (r < nrhs) {
+                    if constexpr (MODE == 1)
+                        out[dst + r * ld] = nscale * acc[r];
+                    else if constexpr (MODE == 2)
+                        out[dst + r * ld] += far_scale * far[r];
+                    else
+                        out[dst + r * ld] = nscale * acc[r] + far_scale * far[r];
+                }
+            }
+        }
+    }
+}
+
+// M2T at the points of the leaves in `lf_list` (one wave per leaf, `lpt`
+// lanes per target point splitting the surface points): for every W entry of
+// the leaf, the U~ q~ values Psi of its cube, placed on the cube's (1+d)
+// surface mapped into the leaf's units (rho s + o), are evaluated at the
+// leaf's points; the sum times scale0 * 2^level (scale0 = 1/(4 pi r_0)) is
+// added to out. One right-hand side stages (x, y, z, Psi) in LDS; several
+// read Psi from global memory.
+template <typename T, int R>
+__global__ void __launch_bounds__(256) eval_m2t_kernel(
+    int64_t n_lf, const int32_t* __restrict__ lf_list, const P4<T>* __restrict__ pts,
+    const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ leaf_level,
+    const int32_t* __restrict__ ent_ptr, const int32_t* __restrict__ ent_cube, const T* __restrict__ ent_geo,
+    const T* __restrict__ Psi, const T* __restrict__ surf_in, int n_eq, int nep, T scale0,
+    const int32_t* __restrict__ perm, T* __restrict__ out, int64_t ld, int nrhs) {
+    constexpr int WPB = 4;
+    constexpr int MAXEQ = 19 * 16;
+    __shared__ P4<T> fs[WPB][MAXEQ];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t wi = (int64_t)blockIdx.x * WPB + wave;
+    if (wi >= n_lf) return;
+    const int leaf = lf_list[wi];
+    const T scale = ldexp(scale0, leaf_level[leaf]);
+    const int p0 = leaf_ptr[leaf];
+    const int ne = leaf_ptr[leaf + 1] - p0;
+    int lpt = 64;
+    while (lpt > 1 && (64 / lpt) < ne) lpt >>= 1;
+    const int tpr = 64 / lpt;
+    const int sub = lane & (lpt - 1);
+    const int k0 = ent_ptr[wi], k1 = ent_ptr[wi + 1];
+    P4<T>* st = fs[wave];
+    for (int tb = 0; tb < ne; tb += tpr) {
+        const int tl = tb + lane / lpt;
+        const bool valid = tl < ne;
+        const int i = p0 + (valid ? tl : 0);
+        const P4<T> ui = pts[i];
+        T acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = 0;
+        for (int k = k0; k < k1; ++k) {
+            const int cube = ent_cube[k];
+            const T rho = ent_geo[4 * k], ox = ent_geo[4 * k + 1], oy = ent_geo[4 * k + 2], oz = ent_geo[4 * k + 3];
+            const T* ps = Psi + (int64_t)cube * R * nep;
+            __builtin_amdgcn_wave_barrier();
+            for (int a = lane; a < n_eq; a += 64)
+                st[a] = P4<T>{rho * surf_in[3 * a] + ox, rho * surf_in[3 * a + 1] + oy, rho * surf_in[3 * a + 2] + oz,
+                              R == 1 ? ps[a] : T(0)};
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+            for (int a = sub; a < n_eq; a += lpt) {
+                const P4<T> f = st[a];
+                const T dx = ui.x - f.x, dy = ui.y - f.y, dz = ui.z - f.z;
+                const T rinv = rsq(dx * dx + dy * dy + dz * dz);
+                if constexpr (R == 1) {
+                    acc[0] += f.w * rinv;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] += ps[(int64_t)r * nep + a] * rinv;
+                }
+            }
+        }
+        for (int off = lpt >> 1; off > 0; off >>= 1) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += __shfl_xor(acc[r], off);
+        }
+        if (valid && sub == 0) {
+            const int64_t dst = perm[i];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (r < nrhs) out[dst + r * ld] += scale * acc[r];
+        }
+    }
+}
+
+// S2L check potentials of the W cubes (one wave per cube, lanes over the
+// (1+d) surface points): CX[(w*R + r)*nep + a] = sum over the cube's X
+// entries of sum_j sig_s[j*R + r] / |s_a - (rho u_j + o)| for a < n_eq, 0 up
+// to nep; the points of each X leaf are mapped into the cube's units and
+// staged in LDS in batches of at most CAP.
+template <typename T, int R>
+__global__ void __launch_bounds__(256) eval_s2l_kernel(
+    int64_t n_cube, const P4<T>* __restrict__ pts, const T* __restrict__ sig, const int32_t* __restrict__ leaf_ptr,
+    const int32_t* __restrict__ ent_ptr, const int32_t* __restrict__ ent_leaf, const T* __restrict__ ent_geo,
+    const T* __restrict__ surf_in, int n_eq, int nep, T* __restrict__ CX) {
+    constexpr int WPB = 4;
+    constexpr int CAP = 64;
+    __shared__ P4<T> sp[WPB][CAP];
+    __shared__ T ss[WPB][R > 1 ? CAP * R : 1];
+    const int wave = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * WPB + wave;
+    if (w >= n_cube) return;
+    const int lane = threadIdx.x & 63;
+    P4<T>* st = sp[wave];
+    T* sst = ss[wave];
+    constexpr int NA = (19 * 16 + 63) / 64;
+    T sx[NA], sy[NA], sz[NA];
+    T acc[NA][R];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int a = k * 64 + lane;
+        const bool ok = a < n_eq;
+        sx[k] = ok ? surf_in[3 * a] : T(0);
+        sy[k] = ok ? surf_in[3 * a + 1] : T(0);
+        sz[k] = ok ? surf_in[3 * a + 2] : T(0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[k][r] = 0;
+    }
+    const int na = (nep + 63) / 64;
+    const int k0 = ent_ptr[w], k1 = ent_ptr[w + 1];
+    for (int ke = k0; ke < k1; ++ke) {
+        const int leaf = ent_leaf[ke];
+        const T rho = ent_geo[4 * ke], ox = ent_geo[4 * ke + 1], oy = ent_geo[4 * ke + 2], oz = ent_geo[4 * ke + 3];
+        const int p0 = leaf_ptr[leaf], p1 = leaf_ptr[leaf + 1];
+        for (int base = p0; base < p1; base += CAP) {
+            const int cnt = min(CAP, p1 - base);
+            __builtin_amdgcn_wave_barrier();
+            if (lane < cnt) {
+                const P4<T> v = pts[base + lane];
+                T w0 = T(0);
+                if constexpr (R == 1) {
+                    w0 = sig[base + lane];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) sst[lane * R + r] = sig[(int64_t)(base + lane) * R + r];
+                }
+                st[lane] = P4<T>{rho * v.x + ox, rho * v.y + oy, rho * v.z + oz, w0};
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+            for (int jj = 0; jj < cnt; ++jj) {
+                const P4<T> f = st[jj];
+#pragma unroll
+                for (int k = 0; k < NA; ++k) {
+                    if (k < na) {
+                        const T dx = sx[k] - f.x, dy = sy[k] - f.y, dz = sz[k] - f.z;
+                        const T rinv = rsq(dx * dx + dy * dy + dz * dz);
+                        if constexpr (R == 1) {
+                            acc[k][0] += f.w * rinv;
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < R; ++r) acc[k][r] += sst[jj * R + r] * rinv;
+                        }
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int a = k * 64 + lane;
+        if (k < na && a < nep) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) CX[(w * R + r) * nep + a] = a < n_eq ? acc[k][r] : T(0);
+        }
+    }
+}
+
+}  // namespace
+
+#define KIFMM_R_SWITCH(R, BODY)                      \
+    switch (R) {                                     \
+        case 1: { constexpr int RR = 1; BODY; break; }  \
+        case 2: { constexpr int RR = 2; BODY; break; }  \
+        case 4: { constexpr int RR = 4; BODY; break; }  \
+        case 8: { constexpr int RR = 8; BODY; break; }  \
+        case 16: { constexpr int RR = 16; BODY; break; } \
+        default: return hipErrorInvalidValue;        \
+    }
+
+hipError_t launch_permute_in(int elt, int R, int64_t n, const int32_t* perm, const void* sigma,
+                             int64_t ld, int nrhs, void* sig_s, hipStream_t st) {
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (elt == 4) {
+        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((permute_in_kernel<float, RR>), grid, dim3(256), 0, st, n, perm,
+                                             (const float*)sigma, ld, nrhs, (float*)sig_s))
+    } else {
+        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((permute_in_kernel<double, RR>), grid, dim3(256), 0, st, n, perm,
+                                             (const double*)sigma, ld, nrhs, (double*)sig_s))
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_surface(int elt, int R, int64_t n_leaf, const void* pts, const void* sig_s,
+                               const int32_t* leaf_ptr, const void* surf, int n_eq, int nep, void* C,
+                               hipStream_t st) {
+    if (n_leaf == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n_leaf + 3) / 4));
+    if (elt == 4) {
+        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_surface_kernel<float, RR>), grid, dim3(256), 0, st, n_leaf,
+                                             (const P4<float>*)pts, (const float*)sig_s, leaf_ptr,
+                                             (const float*)surf, n_eq, nep, (float*)C))
+    } else {
+        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_surface_kernel<double, RR>), grid, dim3(256), 0, st, n_leaf,
+                                             (const P4<double>*)pts, (const double*)sig_s, leaf_ptr,
+                                             (const double*)surf, n_eq, nep, (double*)C))
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const void* pts, const void* qpts,
+                               const void* sig_s,
+                               const int32_t* leaf_ptr, const int32_t* near_ptr, const int32_t* near_leaf,
+                               const int32_t* near_code, const int32_t* leaf_level, const void* E, const void* surf,
+                               int n_eq, int nep, double near_scale, double far_scale, const int32_t* perm, void* out,
+                               int64_t ld, int nrhs, hipStream_t st) {
+    if (n_leaf == 0) return hipSuccess;
+    if (mode < 1 || mode > 3 || (mode == 2 && E == nullptr)) return hipErrorInvalidValue;
+    if (elt == 4 && (mode & 1) && qpts == nullptr) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n_leaf + 3) / 4));
+#define KIFMM_EVT(TT, M, AD)                                                                                  \
+    KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_targets_kernel<TT, RR, M, AD>), grid, dim3(256), 0, st, n_leaf, \
+                                         (const P4<TT>*)pts, (const P4<int32_t>*)qpts, (const TT*)sig_s, leaf_ptr, near_ptr, near_leaf, \
+                                         near_code, leaf_level, (const TT*)E, (const TT*)surf, n_eq, nep, (TT)near_scale, \
+                                         (TT)far_scale, perm, (TT*)out, ld, nrhs))
+#define KIFMM_EVT_AD(TT, M) \
+    if (leaf_level) { KIFMM_EVT(TT, M, true) } else { KIFMM_EVT(TT, M, false) }
+    if (elt == 4) {
+        if (mode == 1) { KIFMM_EVT_AD(float, 1) } else if (mode == 2) { KIFMM_EVT_AD(float, 2) } else { KIFMM_EVT_AD(float, 3) }
+    } else {
+        if (mode == 1) { KIFMM_EVT_AD(double, 1) } else if (mode == 2) { KIFMM_EVT_AD(double, 2) } else { KIFMM_EVT_AD(double, 3) }
+    }
+#undef KIFMM_EVT_AD
+#undef KIFMM_EVT
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_m2t(int elt, int R, int64_t n_lf, const int32_t* lf_list, const void* pts,
+                           const int32_t* leaf_ptr, const int32_t* leaf_level, const int32_t* ent_ptr,
+                           const int32_t* ent_cube, const void* ent_geo, const void* Psi, const void* surf_in,
+                           int n_eq, int nep, double scale0, const int32_t* perm, void* out, int64_t ld, int nrhs,
+                           hipStream_t st) {
+    if (n_lf == 0) return hipSuccess;
+    if (n_eq > 19 * 16) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n_lf + 3) / 4));
+    if (elt == 4) {
+        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_m2t_kernel<float, RR>), grid, dim3(256), 0, st, n_lf, lf_list,
+                                             (const P4<float>*)pts, leaf_ptr, leaf_level, ent_ptr, ent_cube,
+                                             (const float*)ent_geo, (const float*)Psi, (const float*)surf_in, n_eq,
+                                             nep, (float)scale0, perm, (float*)out, ld, nrhs))
+    } else {
+        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_m2t_kernel<double, RR>), grid, dim3(256), 0, st, n_lf, lf_list,
+                                             (const P4<double>*)pts, leaf_ptr, leaf_level, ent_ptr, ent_cube,
+                                             (const double*)ent_geo, (const double*)Psi, (const double*)surf_in, n_eq,
+                                             nep, scale0, perm, (double*)out, ld, nrhs))
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_s2l(int elt, int R, int64_t n_cube, const void* pts, const void* sig_s,
+                           const int32_t* leaf_ptr, const int32_t* ent_ptr, const int32_t* ent_leaf,
+                           const void* ent_geo, const void* surf_in, int n_eq, int nep, void* CX, hipStream_t st) {
+    if (n_cube == 0) return hipSuccess;
+    if (n_eq > 19 * 16 || nep > 19 * 16) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n_cube + 3) / 4));
+    if (elt == 4) {
+        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_s2l_kernel<float, RR>), grid, dim3(256), 0, st, n_cube,
+                                             (const P4<float>*)pts, (const float*)sig_s, leaf_ptr, ent_ptr, ent_leaf,
+                                             (const float*)ent_geo, (const float*)surf_in, n_eq, nep, (float*)CX))
+    } else {
+        KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_s2l_kernel<double, RR>), grid, dim3(256), 0, st, n_cube,
+                                             (const P4<double>*)pts, (const double*)sig_s, leaf_ptr, ent_ptr, ent_leaf,
+                                             (const double*)ent_geo, (const double*)surf_in, n_eq, nep, (double*)CX))
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kifmm
