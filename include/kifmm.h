@@ -198,7 +198,18 @@ int kifmm_apply_batched(kifmm_plan_t plan, const void* sigma, void* phi, int nrh
 
 /* Group several plans (for instance independent point sets) so that one call
  * runs all their applies from one captured HIP graph. The plans must outlive
- * the group and must use one device and one precision. */
+ * the group and must use one device and one precision.
+ * When 2 to 64 plans also share the operators (p, eps, leaf_size, opts.cd,
+ * opts.pinv_rcond, opts.dense_m2l), the right-hand-side width (max_nrhs
+ * rounded up to a power of two) and none uses stage 2 (opts.c2 = 0), the
+ * group is merged: one synthetic plan holds the cubes, leaves and points of
+ * all of them one after the other (device copies of their lists and
+ * schedules, a workspace of the summed size), and every stage of an apply is
+ * one launch over all the plans (M2M and L2L one per level); the inputs are
+ * joined and the outputs split back by two small kernels. The results equal
+ * the plans' own applies up to the summation order of the M2L products (its
+ * work tiles differ). Otherwise each plan's apply is captured on a stream of
+ * its own. */
 int kifmm_group_create(const kifmm_plan_t* plans, int nplans, kifmm_group_t* out);
 /* sigma[i], phi[i]: device vectors of plan i (as in kifmm_apply). The first call
  * with a given set of pointers captures the graph; later calls with the same

@@ -131,6 +131,7 @@ struct kifmm_plan_s {
     DevSched d_m2t, d_s2l;
     int64_t n_m2t_leaf = 0;              // leaves with a nonempty W list
     int32_t* leaf_level = nullptr;
+    void* leaf_scale = nullptr;          // per leaf 1/(4 pi r_leaf), element type
     int32_t *m2t_leaf = nullptr, *m2t_ptr = nullptr, *m2t_cube = nullptr;
     int32_t *s2l_ptr = nullptr, *s2l_leaf = nullptr;
     void *m2t_geo = nullptr, *s2l_geo = nullptr;   // per entry (rho, ox, oy, oz) in the element type
@@ -155,6 +156,11 @@ struct kifmm_plan_s {
 
 struct kifmm_group_s {
     std::vector<kifmm_plan_t> plans;
+    // merged form (see build_fused): one synthetic plan over the cubes,
+    // leaves and points of all the plans, with joined input and output vectors
+    kifmm_plan_s* fused = nullptr;
+    void *sig_u = nullptr, *out_u = nullptr;
+    std::vector<int64_t> pt_off;
     std::vector<hipStream_t> side;
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> join;
@@ -492,36 +498,45 @@ int upload_tables(kifmm_plan_s* pl, Uploader& up) {
     return up.err;
 }
 
-// Device lists of an adaptive plan: leaf levels, the M2T entries of every
-// leaf with a W list and the S2L entries of every W cube, each with the
-// geometry (rho, o) that maps the source into the target's units: for M2T the
-// W cube's surface point s becomes rho s + o in the units of the target leaf
-// (rho = r_cube / r_leaf), for S2L a point u of the source leaf becomes
-// rho u + o in the units of the W cube (rho = r_leaf / r_cube); rho is a power
-// of two and o a multiple of rho or an integer, so both are exact.
+// Host form of the per-leaf data of the adaptive evaluation kernels (level and
+// near-field scale 1/(4 pi r_leaf)) and of the M2T and S2L entries; for a
+// uniform tree every leaf is at the leaf level and there are no entries.
 template <typename T>
-void upload_adaptive(kifmm_plan_s* pl, Uploader& up) {
+struct AdaptiveLists {
+    std::vector<int32_t> level;
+    std::vector<T> scale;
+    std::vector<int32_t> mleaf, mptr{0}, mcube, sptr{0}, sleaf;
+    std::vector<T> mgeo, sgeo;
+};
+
+template <typename T>
+AdaptiveLists<T> adaptive_lists(const kifmm_plan_s* pl) {
     const HostTree& t = pl->tree;
-    pl->leaf_level = (int32_t*)up.put(t.leaf_level);
+    AdaptiveLists<T> a;
+    const int64_t nl = t.n_leaf();
+    a.level.resize(nl);
+    a.scale.resize(nl);
+    for (int64_t e = 0; e < nl; ++e) {
+        a.level[e] = t.adaptive ? t.leaf_level[e] : t.depth;
+        a.scale[e] = (T)(1.0 / (kFourPi * t.half_width(a.level[e])));
+    }
     const int64_t nw = (int64_t)pl->w_cube_box.size();
-    if (nw == 0) return;
+    if (!t.adaptive || nw == 0) return a;
     std::vector<int32_t> cube_of_box(t.n_box(), -1);
     for (int64_t w = 0; w < nw; ++w) cube_of_box[pl->w_cube_box[w]] = (int32_t)w;
-    std::vector<int32_t> mleaf, mptr(1, 0), mcube, sptr(1, 0), sleaf;
-    std::vector<T> mgeo, sgeo;
-    for (int64_t e = 0; e < t.n_leaf(); ++e) {
+    for (int64_t e = 0; e < nl; ++e) {
         if (t.w_ptr[e + 1] == t.w_ptr[e]) continue;
         int64_t c[3], ec[3];
         const int l = box_cube(t, t.leaf_box[e], c);
-        mleaf.push_back((int32_t)e);
+        a.mleaf.push_back((int32_t)e);
         for (int32_t k = t.w_ptr[e]; k < t.w_ptr[e + 1]; ++k) {
             const int m = box_cube(t, t.w_src[k], ec);
             const double rho = std::ldexp(1.0, l - m);
-            mcube.push_back(cube_of_box[t.w_src[k]]);
-            mgeo.push_back((T)rho);
-            for (int a = 0; a < 3; ++a) mgeo.push_back((T)((2.0 * ec[a] + 1.0) * rho - (2.0 * c[a] + 1.0)));
+            a.mcube.push_back(cube_of_box[t.w_src[k]]);
+            a.mgeo.push_back((T)rho);
+            for (int d = 0; d < 3; ++d) a.mgeo.push_back((T)((2.0 * ec[d] + 1.0) * rho - (2.0 * c[d] + 1.0)));
         }
-        mptr.push_back((int32_t)mcube.size());
+        a.mptr.push_back((int32_t)a.mcube.size());
     }
     for (int64_t w = 0; w < nw; ++w) {
         const int64_t g = pl->w_cube_box[w];
@@ -531,20 +546,37 @@ void upload_adaptive(kifmm_plan_s* pl, Uploader& up) {
             const int32_t e = t.x_src[k];
             const int l = box_cube(t, t.leaf_box[e], c);
             const double rho = std::ldexp(1.0, m - l);
-            sleaf.push_back(e);
-            sgeo.push_back((T)rho);
-            for (int a = 0; a < 3; ++a) sgeo.push_back((T)((2.0 * c[a] + 1.0) * rho - (2.0 * ec[a] + 1.0)));
+            a.sleaf.push_back(e);
+            a.sgeo.push_back((T)rho);
+            for (int d = 0; d < 3; ++d) a.sgeo.push_back((T)((2.0 * c[d] + 1.0) * rho - (2.0 * ec[d] + 1.0)));
         }
-        sptr.push_back((int32_t)sleaf.size());
+        a.sptr.push_back((int32_t)a.sleaf.size());
     }
-    pl->n_m2t_leaf = (int64_t)mleaf.size();
-    pl->m2t_leaf = (int32_t*)up.put(mleaf);
-    pl->m2t_ptr = (int32_t*)up.put(mptr);
-    pl->m2t_cube = (int32_t*)up.put(mcube);
-    pl->m2t_geo = up.put(mgeo);
-    pl->s2l_ptr = (int32_t*)up.put(sptr);
-    pl->s2l_leaf = (int32_t*)up.put(sleaf);
-    pl->s2l_geo = up.put(sgeo);
+    return a;
+}
+
+// Device lists of an adaptive plan: leaf levels and scales, the M2T entries
+// of every leaf with a W list and the S2L entries of every W cube, each with
+// the geometry (rho, o) that maps the source into the target's units: for M2T
+// the W cube's surface point s becomes rho s + o in the units of the target
+// leaf (rho = r_cube / r_leaf), for S2L a point u of the source leaf becomes
+// rho u + o in the units of the W cube (rho = r_leaf / r_cube); rho is a power
+// of two and o a multiple of rho or an integer, so both are exact.
+template <typename T>
+void upload_adaptive(kifmm_plan_s* pl, Uploader& up) {
+    const AdaptiveLists<T> a = adaptive_lists<T>(pl);
+    pl->leaf_level = (int32_t*)up.put(a.level);
+    pl->leaf_scale = up.put(a.scale);
+    const int64_t nw = (int64_t)pl->w_cube_box.size();
+    if (nw == 0) return;
+    pl->n_m2t_leaf = (int64_t)a.mleaf.size();
+    pl->m2t_leaf = (int32_t*)up.put(a.mleaf);
+    pl->m2t_ptr = (int32_t*)up.put(a.mptr);
+    pl->m2t_cube = (int32_t*)up.put(a.mcube);
+    pl->m2t_geo = up.put(a.mgeo);
+    pl->s2l_ptr = (int32_t*)up.put(a.sptr);
+    pl->s2l_leaf = (int32_t*)up.put(a.sleaf);
+    pl->s2l_geo = up.put(a.sgeo);
     pl->d_m2t = upload_sched(up, pl->h_m2t, pl->elt);
     pl->d_s2l = upload_sched(up, pl->h_s2l, pl->elt, &pl->w_cube_box);
     const size_t bytes = (size_t)nw * pl->R * pl->nep * pl->elt;
@@ -1180,18 +1212,19 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     KIFMM_HIP(mark(KIFMM_STAGE_PERM, 1));
     const bool far = L >= 2;
     const double rL = t.half_width(L);
-    // adaptive trees: leaf-level scales from the root's, and the W/X steps
+    // adaptive form: per-leaf levels and scales, and the W/X steps
     const bool ad = t.adaptive;
     const int64_t nw = (int64_t)pl->w_cube_box.size();
-    const double near_scale = ad ? 1.0 / (kFourPi * t.r0) : 1.0 / (kFourPi * rL);
+    const double near_scale = 1.0 / (kFourPi * rL);   // uniform form (the adaptive form has per-leaf scales)
     const int32_t* lev = ad ? pl->leaf_level : nullptr;
+    const void* lsc = ad ? pl->leaf_scale : nullptr;
     const int n_eq = pl->ops().n_eq;
     // M2T at the points (after the far field, adding to it)
     auto m2t_eval = [&]() -> hipError_t {
         if (!far || !ad || pl->n_m2t_leaf == 0) return hipSuccess;
-        return launch_eval_m2t(elt, R, pl->n_m2t_leaf, pl->m2t_leaf, pl->pts, pl->leaf_ptr, pl->leaf_level,
-                               pl->m2t_ptr, pl->m2t_cube, pl->m2t_geo, w.Psi, pl->surf_in, n_eq, nep,
-                               1.0 / (kFourPi * t.r0), pl->perm, out, ld, nrhs, st);
+        return launch_eval_m2t(elt, R, pl->n_m2t_leaf, pl->m2t_leaf, pl->pts, pl->leaf_ptr, pl->leaf_scale,
+                               pl->m2t_ptr, pl->m2t_cube, pl->m2t_geo, w.Psi, pl->surf_in, n_eq, nep, pl->perm, out,
+                               ld, nrhs, st);
     };
     // The near field (S2T) runs on the plan's own stream, concurrent with the
     // far-field passes, and the far-field evaluation waits for it. Under
@@ -1206,7 +1239,7 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         KIFMM_HIP(hipStreamWaitEvent(ns, pl->ev_fork, 0));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P], ns));
         KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                      pl->near_leaf, pl->near_code, lev, nullptr, pl->surf, n_eq, nep,
+                                      pl->near_leaf, pl->near_code, lev, lsc, nullptr, pl->surf, n_eq, nep,
                                       near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, ns));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P + 1], ns));
         KIFMM_HIP(hipEventRecord(pl->ev_join, ns));
@@ -1283,7 +1316,7 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
             // far field at the points (L2T), added to the near field
             KIFMM_HIP(hipStreamWaitEvent(st, pl->ev_join, 0));
             KIFMM_HIP(launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                          pl->near_leaf, pl->near_code, lev, w.E, pl->surf, n_eq, nep,
+                                          pl->near_leaf, pl->near_code, lev, lsc, w.E, pl->surf, n_eq, nep,
                                           near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
             KIFMM_HIP(m2t_eval());
         }
@@ -1293,12 +1326,261 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         // near field and (when there is one) far field in one kernel
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
         KIFMM_HIP(launch_eval_targets(3, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                      pl->near_leaf, pl->near_code, lev, far ? w.E : nullptr, pl->surf,
+                                      pl->near_leaf, pl->near_code, lev, lsc, far ? w.E : nullptr, pl->surf,
                                       n_eq, nep, near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
         KIFMM_HIP(m2t_eval());
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
     }
     if (cur != pl->device) KIFMM_HIP(hipSetDevice(cur));
+    return KIFMM_OK;
+}
+
+// ------------------------------------------------------------ merged groups
+// Plans of a group that share device, precision, operators (p, eps, leaf
+// size, C_d, pseudo-inverse cutoff, dense), right-hand-side width and have no
+// stage 2 run as one merged plan: the cubes, leaves and points of all of them
+// numbered one after the other, every stage one launch over all of them (M2M
+// and L2L one per level). The per-plan scales travel with the work: the M2L
+// chunks carry their own r_l^-1, the leaves their near-field scale (the
+// adaptive form of the evaluation kernels, which the merged plan always uses).
+bool fusable(const std::vector<kifmm_plan_t>& ps) {
+    if (ps.size() < 2 || ps.size() > (size_t)kMaxSegments) return false;
+    const kifmm_plan_s* a = ps[0];
+    for (const kifmm_plan_s* b : ps) {
+        if (b->device != a->device || b->opts.precision != a->opts.precision || b->R != a->R || b->st2 ||
+            b->p != a->p || b->eps != a->eps || b->leaf_size != a->leaf_size || b->opts.cd != a->opts.cd ||
+            b->opts.pinv_rcond != a->opts.pinv_rcond || b->opts.dense_m2l != a->opts.dense_m2l ||
+            b->kp != a->kp || b->nep != a->nep || b->profiling)
+            return false;
+    }
+    return true;
+}
+
+// Appends src's tiles and chunks to dst, target rows shifted by tgt_off and
+// source rows by src_off.
+void append_sched(GGSched& dst, const GGSched& src, int64_t tgt_off, int64_t src_off) {
+    if (src.n_tiles() == 0) return;
+    if (dst.tile_chunk0.empty()) dst.tile_chunk0.push_back(0);
+    const int32_t base = (int32_t)dst.chunk_cls.size();
+    for (int t = 0; t < src.n_tiles(); ++t) {
+        dst.tile_tgt0.push_back((int32_t)(src.tile_tgt0[t] + tgt_off));
+        dst.tile_ntgt.push_back(src.tile_ntgt[t]);
+        dst.tile_chunk0.push_back(base + src.tile_chunk0[t + 1]);
+    }
+    dst.chunk_cls.insert(dst.chunk_cls.end(), src.chunk_cls.begin(), src.chunk_cls.end());
+    dst.chunk_next.insert(dst.chunk_next.end(), src.chunk_next.begin(), src.chunk_next.end());
+    dst.chunk_nblk.insert(dst.chunk_nblk.end(), src.chunk_nblk.begin(), src.chunk_nblk.end());
+    dst.chunk_scale.insert(dst.chunk_scale.end(), src.chunk_scale.begin(), src.chunk_scale.end());
+    dst.chunk_col.insert(dst.chunk_col.end(), src.chunk_col.begin(), src.chunk_col.end());
+    for (int32_t v : src.chunk_src) dst.chunk_src.push_back(v < 0 ? v : (int32_t)(v + src_off));
+    dst.max_tile = std::max(dst.max_tile, src.max_tile);
+    dst.pairs += src.pairs;
+    dst.variant = src.variant;
+}
+
+void destroy_fused(kifmm_group_s* g) {
+    if (!g->fused) return;
+    release_streams(g->fused);
+    release_device(g->fused);
+    delete g->fused;
+    g->fused = nullptr;
+}
+
+template <typename T>
+int build_fused_t(kifmm_group_s* g) {
+    const std::vector<kifmm_plan_t>& ps = g->plans;
+    const kifmm_plan_s* p0 = ps[0];
+    const int np = (int)ps.size();
+    kifmm_plan_s* fp = new (std::nothrow) kifmm_plan_s();
+    if (!fp) return fail(KIFMM_ENOMEM, "host allocation failed");
+    g->fused = fp;
+    fp->opts = p0->opts;
+    fp->p = p0->p;
+    fp->eps = p0->eps;
+    fp->leaf_size = p0->leaf_size;
+    fp->ops_sp = p0->ops_sp;
+    fp->k = p0->k;
+    fp->kp = p0->kp;
+    fp->nep = p0->nep;
+    fp->R = p0->R;
+    fp->elt = p0->elt;
+    fp->b3 = p0->b3;
+    fp->device = p0->device;
+    fp->num_cu = p0->num_cu;
+    fp->tables = p0->tables;
+    fp->Kt = p0->Kt; fp->KtT = p0->KtT; fp->Mt = p0->Mt; fp->MtT = p0->MtT; fp->Lt = p0->Lt; fp->LtT = p0->LtT;
+    fp->Sop = p0->Sop; fp->SopT = p0->SopT; fp->Top = p0->Top; fp->TopT = p0->TopT;
+    fp->surf = p0->surf; fp->Ut = p0->Ut; fp->UtT = p0->UtT; fp->surf_in = p0->surf_in;
+    // offsets of every plan's points, leaves, cubes, W cubes and near entries
+    std::vector<int64_t> pt(np + 1, 0), lf(np + 1, 0), bx(np + 1, 0), wc(np + 1, 0), ne(np + 1, 0);
+    int D = 0;
+    for (int i = 0; i < np; ++i) {
+        const HostTree& t = ps[i]->tree;
+        pt[i + 1] = pt[i] + t.n;
+        lf[i + 1] = lf[i] + t.n_leaf();
+        bx[i + 1] = bx[i] + t.n_box();
+        wc[i + 1] = wc[i] + (int64_t)ps[i]->w_cube_box.size();
+        ne[i + 1] = ne[i] + (int64_t)t.near_leaf.size();
+        D = std::max(D, t.depth);
+    }
+    if (pt[np] > INT32_MAX / 2 || bx[np] > INT32_MAX / 2 || ne[np] > INT32_MAX / 2)
+        return fail(KIFMM_EINVAL, "the plans of the group are too large to merge");
+    g->pt_off = pt;
+    HostTree& U = fp->tree;
+    U.adaptive = true;
+    U.depth = D;
+    U.n = pt[np];
+    U.r0 = 1.0;
+    U.level_begin.assign(D + 2, 0);
+    U.level_begin[D + 1] = bx[np];
+    U.leaf_ptr.assign(1, 0);
+    for (int i = 0; i < np; ++i) {
+        const HostTree& t = ps[i]->tree;
+        for (int64_t e = 1; e <= t.n_leaf(); ++e) U.leaf_ptr.push_back((int32_t)(t.leaf_ptr[e] + pt[i]));
+    }
+    // schedules
+    const int cp = 32 / fp->R;
+    for (GGSched* s : {&fp->h_leafup, &fp->h_leafdown, &fp->h_m2l, &fp->h_m2t, &fp->h_s2l}) {
+        *s = GGSched();
+        s->cp = cp;
+        s->rhs = fp->R;
+    }
+    fp->h_up.assign(D + 1, GGSched());
+    fp->h_down.assign(D + 1, GGSched());
+    for (auto* v : {&fp->h_up, &fp->h_down})
+        for (auto& s : *v) {
+            s.cp = cp;
+            s.rhs = fp->R;
+        }
+    const int variant = p0->h_m2l.variant;
+    int64_t nb2 = 0;
+    for (int i = 0; i < np; ++i) {
+        const HostTree& t = ps[i]->tree;
+        if (t.depth >= 2) nb2 += t.n_box() - t.level_begin[2];
+    }
+    const int n_rg = row_groups(fp->kp, variant);
+    const int slots = std::max(1, fp->num_cu * gg_variant_wgs_per_cu(variant) / n_rg);
+    const int cap = max_tile_for(p0, variant, fp->kp);
+    int rounds = 1;
+    while ((int64_t)rounds * slots * cap < nb2 * 11 / 10) ++rounds;
+    const int64_t tiles = (int64_t)rounds * slots;
+    for (int i = 0; i < np; ++i) {
+        const kifmm_plan_s* m = ps[i];
+        const HostTree& t = m->tree;
+        if (t.depth < 2) continue;
+        append_sched(fp->h_leafup, m->h_leafup, bx[i], lf[i]);
+        append_sched(fp->h_leafdown, m->h_leafdown, lf[i], bx[i]);
+        for (int l = 0; l <= t.depth; ++l) {
+            append_sched(fp->h_up[l], m->h_up[l], bx[i], bx[i]);
+            append_sched(fp->h_down[l], m->h_down[l], bx[i], bx[i]);
+        }
+        const int64_t nbi = t.n_box() - t.level_begin[2];
+        const int ti = (int)std::max<int64_t>(1, (tiles * nbi + nb2 / 2) / std::max<int64_t>(1, nb2));
+        append_sched(fp->h_m2l, build_m2l_sched(m, variant, ti, 0), bx[i], bx[i]);
+        append_sched(fp->h_m2t, m->h_m2t, wc[i], bx[i]);
+        append_sched(fp->h_s2l, m->h_s2l, wc[i], wc[i]);
+        for (int32_t b : m->w_cube_box) fp->w_cube_box.push_back((int32_t)(b + bx[i]));
+    }
+    // host lists
+    std::vector<int32_t> perm, near_ptr(1, 0), near_leaf, near_code, level, mleaf, mptr(1, 0), mcube, sptr(1, 0), sleaf;
+    std::vector<T> scale, mgeo, sgeo;
+    for (int i = 0; i < np; ++i) {
+        const kifmm_plan_s* m = ps[i];
+        const HostTree& t = m->tree;
+        for (int32_t v : t.perm) perm.push_back((int32_t)(v + pt[i]));
+        for (int64_t e = 1; e <= t.n_leaf(); ++e) near_ptr.push_back((int32_t)(t.near_ptr[e] + ne[i]));
+        for (int32_t v : t.near_leaf) near_leaf.push_back((int32_t)(v + lf[i]));
+        for (int32_t c : t.near_code) {
+            if (t.adaptive) {
+                near_code.push_back(c);
+            } else {
+                // uniform code of d = target - source cube; adaptive form o = -2 d
+                const int dx = c / 9 - 1, dy = (c / 3) % 3 - 1, dz = c % 3 - 1;
+                near_code.push_back((4 - 2 * dx) * 81 + (4 - 2 * dy) * 9 + (4 - 2 * dz));
+            }
+        }
+        const AdaptiveLists<T> a = adaptive_lists<T>(m);
+        level.insert(level.end(), a.level.begin(), a.level.end());
+        scale.insert(scale.end(), a.scale.begin(), a.scale.end());
+        const int32_t m0 = (int32_t)mcube.size(), s0 = (int32_t)sleaf.size();
+        for (int32_t v : a.mleaf) mleaf.push_back((int32_t)(v + lf[i]));
+        for (size_t k = 1; k < a.mptr.size(); ++k) mptr.push_back(a.mptr[k] + m0);
+        for (int32_t v : a.mcube) mcube.push_back((int32_t)(v + wc[i]));
+        mgeo.insert(mgeo.end(), a.mgeo.begin(), a.mgeo.end());
+        if (t.adaptive && !m->w_cube_box.empty())
+            for (size_t k = 1; k < a.sptr.size(); ++k) sptr.push_back(a.sptr[k] + s0);
+        for (int32_t v : a.sleaf) sleaf.push_back((int32_t)(v + lf[i]));
+        sgeo.insert(sgeo.end(), a.sgeo.begin(), a.sgeo.end());
+    }
+    int cur = 0;
+    hipGetDevice(&cur);
+    hipSetDevice(fp->device);
+    Uploader up{fp, 0};
+    fp->perm = (int32_t*)up.put(perm);
+    fp->leaf_ptr = (int32_t*)up.put(U.leaf_ptr);
+    fp->near_ptr = (int32_t*)up.put(near_ptr);
+    fp->near_leaf = (int32_t*)up.put(near_leaf);
+    fp->near_code = (int32_t*)up.put(near_code);
+    fp->leaf_level = (int32_t*)up.put(level);
+    fp->leaf_scale = up.put(scale);
+    fp->pts = up.alloc((size_t)pt[np] * 4 * sizeof(T));
+    if (fp->elt == 4) fp->qpts = up.alloc((size_t)pt[np] * 4 * sizeof(int32_t));
+    for (int i = 0; i < np && up.err == KIFMM_OK; ++i) {
+        const size_t n = (size_t)ps[i]->tree.n;
+        hipError_t e = hipMemcpy(static_cast<char*>(fp->pts) + (size_t)pt[i] * 4 * sizeof(T), ps[i]->pts,
+                                 n * 4 * sizeof(T), hipMemcpyDeviceToDevice);
+        if (e == hipSuccess && fp->qpts)
+            e = hipMemcpy(static_cast<char*>(fp->qpts) + (size_t)pt[i] * 4 * sizeof(int32_t), ps[i]->qpts,
+                          n * 4 * sizeof(int32_t), hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) {
+            up.err = KIFMM_EHIP;
+            up.msg = std::string("hipMemcpy (merging the group's points): ") + hipGetErrorString(e);
+        }
+    }
+    const size_t elt = fp->elt, R = fp->R;
+    fp->sig_s = up.zeros((size_t)pt[np] * R * elt);
+    if (D >= 2) {
+        fp->C = up.zeros((size_t)lf[np] * R * fp->nep * elt);
+        fp->E = up.zeros((size_t)lf[np] * R * fp->nep * elt);
+        fp->Q = up.zeros((size_t)bx[np] * R * fp->kp * elt);
+        fp->P = up.zeros((size_t)bx[np] * R * fp->kp * elt);
+    }
+    fp->d_leafup = upload_sched(up, fp->h_leafup, fp->elt);
+    fp->d_leafdown = upload_sched(up, fp->h_leafdown, fp->elt);
+    fp->d_m2l = upload_sched(up, fp->h_m2l, fp->elt);
+    fp->d_up.resize(D + 1);
+    fp->d_down.resize(D + 1);
+    for (int l = 0; l <= D; ++l) {
+        fp->d_up[l] = upload_sched(up, fp->h_up[l], fp->elt);
+        fp->d_down[l] = upload_sched(up, fp->h_down[l], fp->elt);
+    }
+    if (!fp->w_cube_box.empty()) {
+        fp->n_m2t_leaf = (int64_t)mleaf.size();
+        fp->m2t_leaf = (int32_t*)up.put(mleaf);
+        fp->m2t_ptr = (int32_t*)up.put(mptr);
+        fp->m2t_cube = (int32_t*)up.put(mcube);
+        fp->m2t_geo = up.put(mgeo);
+        fp->s2l_ptr = (int32_t*)up.put(sptr);
+        fp->s2l_leaf = (int32_t*)up.put(sleaf);
+        fp->s2l_geo = up.put(sgeo);
+        fp->d_m2t = upload_sched(up, fp->h_m2t, fp->elt);
+        fp->d_s2l = upload_sched(up, fp->h_s2l, fp->elt, &fp->w_cube_box);
+        fp->CX = up.zeros(fp->w_cube_box.size() * R * fp->nep * elt);
+        fp->Psi = up.zeros(fp->w_cube_box.size() * R * fp->nep * elt);
+    }
+    g->sig_u = up.zeros((size_t)pt[np] * elt);
+    g->out_u = up.zeros((size_t)pt[np] * elt);
+    if (up.err == KIFMM_OK &&
+        (hipStreamCreateWithFlags(&fp->near_stream, hipStreamNonBlocking) != hipSuccess ||
+         hipEventCreateWithFlags(&fp->ev_fork, hipEventDisableTiming) != hipSuccess ||
+         hipEventCreateWithFlags(&fp->ev_join, hipEventDisableTiming) != hipSuccess)) {
+        up.err = KIFMM_EHIP;
+        up.msg = "creating the merged plan's stream or events failed";
+    }
+    hipDeviceSynchronize();
+    hipSetDevice(cur);
+    if (up.err != KIFMM_OK) return fail(up.err, up.msg);
+    fp->on_device = true;
     return KIFMM_OK;
 }
 
@@ -1731,6 +2013,14 @@ int kifmm_group_create(const kifmm_plan_t* plans, int nplans, kifmm_group_t* out
         kifmm_group_destroy(g);
         return fail(KIFMM_EHIP, "stream/event creation failed");
     }
+    if (fusable(g->plans)) {
+        const int rc = g->plans[0]->elt == 4 ? build_fused_t<float>(g) : build_fused_t<double>(g);
+        if (rc != KIFMM_OK) {
+            const std::string msg = g_last_error;
+            kifmm_group_destroy(g);
+            return fail(rc, msg);
+        }
+    }
     *out = g;
     return KIFMM_OK;
 }
@@ -1763,12 +2053,32 @@ int kifmm_group_apply(kifmm_group_t g, const void* const* sigma, void* const* ph
         }
         KIFMM_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         int rc = KIFMM_OK;
-        hipEventRecord(g->fork, cap);
-        for (int i = 0; i < np && rc == KIFMM_OK; ++i) {
-            hipStreamWaitEvent(g->side[i], g->fork, 0);
-            rc = run_passes(g->plans[i], plan_work(g->plans[i]), sigma[i], phi[i], 1, g->plans[i]->tree.n, false, g->side[i]);
-            hipEventRecord(g->join[i], g->side[i]);
-            hipStreamWaitEvent(cap, g->join[i], 0);
+        if (g->fused) {
+            // the joined input, the merged plan's passes, the joined output split back
+            SegTable in{}, outs{};
+            in.count = outs.count = np;
+            for (int i = 0; i <= np; ++i) in.off[i] = outs.off[i] = g->pt_off[i];
+            for (int i = 0; i < np; ++i) {
+                in.ptr[i] = sigma[i];
+                outs.ptr[i] = phi[i];
+            }
+            const int64_t n = g->pt_off[np];
+            hipError_t e = launch_gather_segments(g->fused->elt, n, in, g->sig_u, cap);
+            if (e != hipSuccess) rc = fail(KIFMM_EHIP, std::string("gather launch: ") + hipGetErrorString(e));
+            if (rc == KIFMM_OK) rc = run_passes(g->fused, plan_work(g->fused), g->sig_u, g->out_u, 1, n, false, cap);
+            if (rc == KIFMM_OK) {
+                e = launch_scatter_segments(g->fused->elt, n, outs, g->out_u, cap);
+                if (e != hipSuccess) rc = fail(KIFMM_EHIP, std::string("scatter launch: ") + hipGetErrorString(e));
+            }
+        } else {
+            hipEventRecord(g->fork, cap);
+            for (int i = 0; i < np && rc == KIFMM_OK; ++i) {
+                hipStreamWaitEvent(g->side[i], g->fork, 0);
+                rc = run_passes(g->plans[i], plan_work(g->plans[i]), sigma[i], phi[i], 1, g->plans[i]->tree.n, false,
+                                g->side[i]);
+                hipEventRecord(g->join[i], g->side[i]);
+                hipStreamWaitEvent(cap, g->join[i], 0);
+            }
         }
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(cap, &graph);
@@ -1799,6 +2109,7 @@ void kifmm_group_destroy(kifmm_group_t g) {
     if (!g) return;
     if (g->exec) hipGraphExecDestroy(g->exec);
     if (g->graph) hipGraphDestroy(g->graph);
+    destroy_fused(g);
     for (auto s : g->side)
         if (s) hipStreamDestroy(s);
     for (auto e : g->join)

@@ -144,8 +144,9 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     int64_t n_leaf, const P4<T>* __restrict__ pts, const P4<int32_t>* __restrict__ qpts, const T* __restrict__ sig,
     const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ near_ptr,
     const int32_t* __restrict__ near_leaf, const int32_t* __restrict__ near_code,
-    const int32_t* __restrict__ leaf_level, const T* __restrict__ E, const T* __restrict__ surf, int n_eq, int nep,
-    T near_scale, T far_scale, const int32_t* __restrict__ perm, T* __restrict__ out, int64_t ld, int nrhs) {
+    const int32_t* __restrict__ leaf_level, const T* __restrict__ leaf_scale, const T* __restrict__ E,
+    const T* __restrict__ surf, int n_eq, int nep, T near_scale, T far_scale, const int32_t* __restrict__ perm,
+    T* __restrict__ out, int64_t ld, int nrhs) {
     constexpr int WPB = 4;
     constexpr int CAP = (R >= 8 ? 64 : R >= 2 ? 128 : 256) / (int)(sizeof(T) / 4);
     constexpr int MAXEQ = 19 * 16;
@@ -159,13 +160,16 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     const int64_t leaf = (int64_t)blockIdx.x * WPB + wave;
     if (leaf >= n_leaf) return;
     SP* st = sp[(MODE & 1) ? wave : 0];
-    // adaptive trees: the leaf's own level sets its unit (near_scale is given
-    // for the root), and leaves above level 2 have no local expansion
+    // adaptive form: every leaf has its own near-field scale (its unit), and
+    // leaves above level 2 have no local expansion
     int lev = 0;
-    if constexpr (AD) lev = leaf_level[leaf];
+    T nsc = near_scale;
+    if constexpr (AD) {
+        lev = leaf_level[leaf];
+        nsc = leaf_scale[leaf];
+    }
     // fixed-point differences are in units of 2^-28 leaf half-widths
-    T nscale = (FIX && (MODE & 1)) ? near_scale * T(268435456.0f) : near_scale;
-    if constexpr (AD) nscale = ldexp(nscale, lev);
+    const T nscale = (FIX && (MODE & 1)) ? nsc * T(268435456.0f) : nsc;
     T* sst = ss[(MODE & 1) ? wave : 0];
     const int p0 = leaf_ptr[leaf];
     const int ne = leaf_ptr[leaf + 1] - p0;
@@ -369,15 +373,15 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
 // lanes per target point splitting the surface points): for every W entry of
 // the leaf, the U~ q~ values Psi of its cube, placed on the cube's (1+d)
 // surface mapped into the leaf's units (rho s + o), are evaluated at the
-// leaf's points; the sum times scale0 * 2^level (scale0 = 1/(4 pi r_0)) is
-// added to out. One right-hand side stages (x, y, z, Psi) in LDS; several
+// leaf's points; the sum times leaf_scale[leaf] (1/(4 pi r_leaf)) is added
+// to out. One right-hand side stages (x, y, z, Psi) in LDS; several
 // read Psi from global memory.
 template <typename T, int R>
 __global__ void __launch_bounds__(256) eval_m2t_kernel(
     int64_t n_lf, const int32_t* __restrict__ lf_list, const P4<T>* __restrict__ pts,
-    const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ leaf_level,
+    const int32_t* __restrict__ leaf_ptr, const T* __restrict__ leaf_scale,
     const int32_t* __restrict__ ent_ptr, const int32_t* __restrict__ ent_cube, const T* __restrict__ ent_geo,
-    const T* __restrict__ Psi, const T* __restrict__ surf_in, int n_eq, int nep, T scale0,
+    const T* __restrict__ Psi, const T* __restrict__ surf_in, int n_eq, int nep,
     const int32_t* __restrict__ perm, T* __restrict__ out, int64_t ld, int nrhs) {
     constexpr int WPB = 4;
     constexpr int MAXEQ = 19 * 16;
@@ -387,7 +391,7 @@ __global__ void __launch_bounds__(256) eval_m2t_kernel(
     const int64_t wi = (int64_t)blockIdx.x * WPB + wave;
     if (wi >= n_lf) return;
     const int leaf = lf_list[wi];
-    const T scale = ldexp(scale0, leaf_level[leaf]);
+    const T scale = leaf_scale[leaf];
     const int p0 = leaf_ptr[leaf];
     const int ne = leaf_ptr[leaf + 1] - p0;
     int lpt = 64;
@@ -522,6 +526,29 @@ __global__ void __launch_bounds__(256) eval_s2l_kernel(
     }
 }
 
+// Vectors of several plans joined into one (gather) and split back
+// (scatter): element i of the joined vector belongs to segment s with
+// off[s] <= i < off[s+1], at index i - off[s] of that segment's pointer.
+template <typename T>
+__global__ void __launch_bounds__(256) gather_segments_kernel(int64_t n, SegTable seg, T* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int s = 0;
+    for (int stp = kMaxSegments / 2; stp > 0; stp >>= 1)
+        if (s + stp < seg.count && seg.off[s + stp] <= i) s += stp;
+    dst[i] = static_cast<const T*>(seg.ptr[s])[i - seg.off[s]];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) scatter_segments_kernel(int64_t n, SegTable seg, const T* __restrict__ src) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int s = 0;
+    for (int stp = kMaxSegments / 2; stp > 0; stp >>= 1)
+        if (s + stp < seg.count && seg.off[s + stp] <= i) s += stp;
+    static_cast<T*>(const_cast<void*>(seg.ptr[s]))[i - seg.off[s]] = src[i];
+}
+
 }  // namespace
 
 #define KIFMM_R_SWITCH(R, BODY)                      \
@@ -567,17 +594,19 @@ hipError_t launch_eval_surface(int elt, int R, int64_t n_leaf, const void* pts, 
 hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const void* pts, const void* qpts,
                                const void* sig_s,
                                const int32_t* leaf_ptr, const int32_t* near_ptr, const int32_t* near_leaf,
-                               const int32_t* near_code, const int32_t* leaf_level, const void* E, const void* surf,
-                               int n_eq, int nep, double near_scale, double far_scale, const int32_t* perm, void* out,
-                               int64_t ld, int nrhs, hipStream_t st) {
+                               const int32_t* near_code, const int32_t* leaf_level, const void* leaf_scale,
+                               const void* E, const void* surf, int n_eq, int nep, double near_scale,
+                               double far_scale, const int32_t* perm, void* out, int64_t ld, int nrhs,
+                               hipStream_t st) {
     if (n_leaf == 0) return hipSuccess;
     if (mode < 1 || mode > 3 || (mode == 2 && E == nullptr)) return hipErrorInvalidValue;
     if (elt == 4 && (mode & 1) && qpts == nullptr) return hipErrorInvalidValue;
+    if ((leaf_level == nullptr) != (leaf_scale == nullptr)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n_leaf + 3) / 4));
 #define KIFMM_EVT(TT, M, AD)                                                                                  \
     KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_targets_kernel<TT, RR, M, AD>), grid, dim3(256), 0, st, n_leaf, \
                                          (const P4<TT>*)pts, (const P4<int32_t>*)qpts, (const TT*)sig_s, leaf_ptr, near_ptr, near_leaf, \
-                                         near_code, leaf_level, (const TT*)E, (const TT*)surf, n_eq, nep, (TT)near_scale, \
+                                         near_code, leaf_level, (const TT*)leaf_scale, (const TT*)E, (const TT*)surf, n_eq, nep, (TT)near_scale, \
                                          (TT)far_scale, perm, (TT*)out, ld, nrhs))
 #define KIFMM_EVT_AD(TT, M) \
     if (leaf_level) { KIFMM_EVT(TT, M, true) } else { KIFMM_EVT(TT, M, false) }
@@ -592,23 +621,23 @@ hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const v
 }
 
 hipError_t launch_eval_m2t(int elt, int R, int64_t n_lf, const int32_t* lf_list, const void* pts,
-                           const int32_t* leaf_ptr, const int32_t* leaf_level, const int32_t* ent_ptr,
+                           const int32_t* leaf_ptr, const void* leaf_scale, const int32_t* ent_ptr,
                            const int32_t* ent_cube, const void* ent_geo, const void* Psi, const void* surf_in,
-                           int n_eq, int nep, double scale0, const int32_t* perm, void* out, int64_t ld, int nrhs,
+                           int n_eq, int nep, const int32_t* perm, void* out, int64_t ld, int nrhs,
                            hipStream_t st) {
     if (n_lf == 0) return hipSuccess;
     if (n_eq > 19 * 16) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n_lf + 3) / 4));
     if (elt == 4) {
         KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_m2t_kernel<float, RR>), grid, dim3(256), 0, st, n_lf, lf_list,
-                                             (const P4<float>*)pts, leaf_ptr, leaf_level, ent_ptr, ent_cube,
-                                             (const float*)ent_geo, (const float*)Psi, (const float*)surf_in, n_eq,
-                                             nep, (float)scale0, perm, (float*)out, ld, nrhs))
+                                             (const P4<float>*)pts, leaf_ptr, (const float*)leaf_scale, ent_ptr,
+                                             ent_cube, (const float*)ent_geo, (const float*)Psi,
+                                             (const float*)surf_in, n_eq, nep, perm, (float*)out, ld, nrhs))
     } else {
         KIFMM_R_SWITCH(R, hipLaunchKernelGGL((eval_m2t_kernel<double, RR>), grid, dim3(256), 0, st, n_lf, lf_list,
-                                             (const P4<double>*)pts, leaf_ptr, leaf_level, ent_ptr, ent_cube,
-                                             (const double*)ent_geo, (const double*)Psi, (const double*)surf_in, n_eq,
-                                             nep, scale0, perm, (double*)out, ld, nrhs))
+                                             (const P4<double>*)pts, leaf_ptr, (const double*)leaf_scale, ent_ptr,
+                                             ent_cube, (const double*)ent_geo, (const double*)Psi,
+                                             (const double*)surf_in, n_eq, nep, perm, (double*)out, ld, nrhs))
     }
     return hipGetLastError();
 }
@@ -628,6 +657,28 @@ hipError_t launch_eval_s2l(int elt, int R, int64_t n_cube, const void* pts, cons
                                              (const P4<double>*)pts, (const double*)sig_s, leaf_ptr, ent_ptr, ent_leaf,
                                              (const double*)ent_geo, (const double*)surf_in, n_eq, nep, (double*)CX))
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_segments(int elt, int64_t n, const SegTable& seg, void* dst, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (seg.count < 1 || seg.count > kMaxSegments) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (elt == 4)
+        hipLaunchKernelGGL((gather_segments_kernel<float>), grid, dim3(256), 0, st, n, seg, (float*)dst);
+    else
+        hipLaunchKernelGGL((gather_segments_kernel<double>), grid, dim3(256), 0, st, n, seg, (double*)dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_segments(int elt, int64_t n, const SegTable& seg, const void* src, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (seg.count < 1 || seg.count > kMaxSegments) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (elt == 4)
+        hipLaunchKernelGGL((scatter_segments_kernel<float>), grid, dim3(256), 0, st, n, seg, (const float*)src);
+    else
+        hipLaunchKernelGGL((scatter_segments_kernel<double>), grid, dim3(256), 0, st, n, seg, (const double*)src);
     return hipGetLastError();
 }
 

@@ -77,6 +77,19 @@ int gg_nbuf(int elt, int variant, int KP16);
 // included) and K dimension KP16*16.
 size_t gg_lds_bytes(int elt, int variant, int KP16, int cols);
 
+// A joined vector of up to kMaxSegments plans' vectors (passed by value to
+// the kernels): segment s holds elements [off[s], off[s+1]) at ptr[s].
+constexpr int kMaxSegments = 64;
+struct SegTable {
+    const void* ptr[kMaxSegments];
+    int64_t off[kMaxSegments + 1];
+    int count;
+};
+// dst[i] = ptr[s][i - off[s]] for i < n = off[count] (the joined vector)
+hipError_t launch_gather_segments(int elt, int64_t n, const SegTable& seg, void* dst, hipStream_t st);
+// ptr[s][i - off[s]] = src[i]
+hipError_t launch_scatter_segments(int elt, int64_t n, const SegTable& seg, const void* src, hipStream_t st);
+
 // sig_s[i*R + r] = r < nrhs ? sigma[perm[i] + r*ld] : 0
 hipError_t launch_permute_in(int elt, int R, int64_t n, const int32_t* perm, const void* sigma,
                              int64_t ld, int nrhs, void* sig_s, hipStream_t st);
@@ -94,27 +107,27 @@ hipError_t launch_eval_surface(int elt, int R, int64_t n_leaf, const void* pts, 
 // pts: leaf-unit coordinates (4 values per point, the last unused); qpts (FP32
 // only, modes 1 and 3): the same coordinates in fixed point, 4 int32 per point,
 // round(u * 2^28), for exact near-field differences.
-// leaf_level (adaptive trees, else null): the level of every leaf; near_scale
-// is then that of the root (the leaf's is near_scale * 2^level), near codes are
-// those of HostTree's adaptive form (sources one level finer or coarser), and
-// leaves above level 2 get no far(i).
+// leaf_level and leaf_scale (adaptive form, else both null): the level of
+// every leaf and its near-field scale 1/(4 pi r_leaf), which replaces
+// near_scale; near codes are those of HostTree's adaptive form (sources one
+// level finer or coarser), and leaves above level 2 get no far(i).
 hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const void* pts, const void* qpts,
                                const void* sig_s,
                                const int32_t* leaf_ptr, const int32_t* near_ptr,
                                const int32_t* near_leaf, const int32_t* near_code, const int32_t* leaf_level,
-                               const void* E, const void* surf, int n_eq, int nep, double near_scale,
-                               double far_scale, const int32_t* perm, void* out, int64_t ld,
+                               const void* leaf_scale, const void* E, const void* surf, int n_eq, int nep,
+                               double near_scale, double far_scale, const int32_t* perm, void* out, int64_t ld,
                                int nrhs, hipStream_t st);
 
 // M2T (adaptive trees): for every leaf lf_list[w] and each of its entries k in
 // [ent_ptr[w], ent_ptr[w+1]), the values Psi[(ent_cube[k]*R + r)*nep + a] on the
 // surface points rho * surf_in[a] + o (ent_geo[4k..4k+3] = rho, o; leaf units)
-// are evaluated at the leaf's points: out[perm[i] + r*ld] += scale0 * 2^level *
+// are evaluated at the leaf's points: out[perm[i] + r*ld] += leaf_scale[leaf] *
 // sum_k sum_a Psi / |u_i - (rho s_a + o)|.
 hipError_t launch_eval_m2t(int elt, int R, int64_t n_lf, const int32_t* lf_list, const void* pts,
-                           const int32_t* leaf_ptr, const int32_t* leaf_level, const int32_t* ent_ptr,
+                           const int32_t* leaf_ptr, const void* leaf_scale, const int32_t* ent_ptr,
                            const int32_t* ent_cube, const void* ent_geo, const void* Psi, const void* surf_in,
-                           int n_eq, int nep, double scale0, const int32_t* perm, void* out, int64_t ld, int nrhs,
+                           int n_eq, int nep, const int32_t* perm, void* out, int64_t ld, int nrhs,
                            hipStream_t st);
 
 // S2L (adaptive trees): CX[(w*R + r)*nep + a] = sum over entries k in

@@ -118,8 +118,7 @@ def test_24_surfaces_one_graph_and_16_rhs():
     big = g["big"]
     plans, sig, eager = [], [], []
     for i, (x, _) in enumerate(sets):
-        plans.append(K.Plan(x, p=g["p"], eps=g["eps"], leaf_size=g["leaf_size"],
-                            max_nrhs=16 if i == big else 1))
+        plans.append(K.Plan(x, p=g["p"], eps=g["eps"], leaf_size=g["leaf_size"]))
         sig.append(torch.tensor(workloads.uniform_density(x.shape[0], 100 + i), dtype=torch.float32,
                                 device="cuda:0"))
     for p, s in zip(plans, sig):
@@ -127,13 +126,21 @@ def test_24_surfaces_one_graph_and_16_rhs():
     torch.cuda.synchronize()
     grp = K.Group(plans)
     outs = [torch.empty_like(s) for s in sig]
+    # the 24 plans share their operators, so the group is merged: every stage
+    # one launch over all of them; equal to the plans' own applies up to the
+    # summation order of M2L, and replays agree bitwise
+    first = None
     for rep in range(2):
         for o in outs:
             o.fill_(float("nan"))
         grp.apply(sig, outs)
         torch.cuda.synchronize()
         for i, (o, e) in enumerate(zip(outs, eager)):
-            assert torch.equal(o, e), f"replay {rep}, set {i}"
+            assert float((o - e).abs().max() / e.abs().max()) < 1e-6, f"replay {rep}, set {i}"
+        if first is None:
+            first = [o.clone() for o in outs]
+        else:
+            assert all(torch.equal(a, b) for a, b in zip(first, outs)), f"replay {rep}"
     worst = 0.0
     for i, (x, name) in enumerate(sets):
         gs = g["sets"][i]
@@ -145,7 +152,7 @@ def test_24_surfaces_one_graph_and_16_rhs():
         worst = max(worst, e)
         print(f"set {i} ({name}, N={x.shape[0]}): rel L2 {e:.3e}, max {m:.3e} vs fp64 dense oracle")
         assert e < 1e-5 and m < 1e-5, f"set {i}"
-    print(f"24 sets in one graph: worst rel L2 vs oracle {worst:.3e}")
+    print(f"24 sets in one merged group: worst rel L2 vs oracle {worst:.3e}")
     # 16 right-hand sides on the largest set, each column against the oracle
     xb = sets[big][0]
     gb = g["sets"][big]
@@ -153,7 +160,8 @@ def test_24_surfaces_one_graph_and_16_rhs():
     want = np.asarray(gb["phi_rhs"])
     assert want.shape == (idx.size, g["nrhs"])
     S = torch.tensor(workloads.uniform_density(xb.shape[0], 7, nrhs=16), dtype=torch.float32, device="cuda:0")
-    outb = plans[big].apply_batched(S).double().cpu().numpy()[idx]
+    plan16 = K.Plan(xb, p=g["p"], eps=g["eps"], leaf_size=g["leaf_size"], max_nrhs=16)
+    outb = plan16.apply_batched(S).double().cpu().numpy()[idx]
     worst = max(max(rel(outb[:, j], want[:, j]), maxrel(outb[:, j], want[:, j])) for j in range(16))
     print(f"largest set N={xb.shape[0]}: 16 right-hand sides vs oracle, worst column error {worst:.3e}")
     assert worst < 1e-5

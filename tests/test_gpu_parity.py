@@ -514,7 +514,12 @@ def test_group_graph_replays_match_eager(c2):
         grp.apply(sig, outs)
         torch.cuda.synchronize()
         for o, e in zip(outs, eager):
-            assert torch.equal(o, e), f"replay {rep}"
+            if c2 > 0:
+                # stage-2 plans are not merged: each plan's own launches, bitwise
+                assert torch.equal(o, e), f"replay {rep}"
+            else:
+                # merged group: other M2L work tiles, so another summation order
+                assert float((o - e).abs().max() / e.abs().max()) < 1e-6, f"replay {rep}"
         _ = [p.apply(s) for p, s in zip(plans, sig)]   # eager work between replays
         torch.cuda.synchronize()
 
