@@ -17,6 +17,12 @@ multipole method and its application to BEM"):
                   of Sec. 3.1 and the reduced upward/downward operators of
                   Sec. 3.3 (``mode="svd"``).
 
+* ``bem``       - the collocation BEM of Sec. 4 (triangles, piecewise-constant
+                  densities, single- and double-layer operators with closed-form
+                  triangle integrals, the KIFMM BEM matvec, the ellipsoid
+                  conductor in closed form, GMRES).
+* ``adaptive``  - the KIFMM on an adaptive 2:1-balanced octree (U/V/W/X lists).
+
 Library primitives used as single steps: ``numpy.linalg.svd`` and
 ``numpy.linalg.pinv`` (truncated-SVD pseudo-inverse), matrix products, sorting.
 

@@ -34,8 +34,14 @@ def _sign(o01):
 def fmm(x: np.ndarray, sigma: np.ndarray, p: int, eps: float, leaf_size: int,
         mode: str = "dense", cd: float = 0.5, rcond: float = 1e-10,
         depth: int | None = None, max_depth: int = 16, sample: np.ndarray | None = None,
-        ops=None, tree=None, c2: float = 0.0):
+        ops=None, tree=None, c2: float = 0.0, source_field=None, near_field=None):
     """Potential phi (N,) or (N,m) at every point (or at `sample` indices).
+
+    The sources are point charges at the points unless `source_field` and
+    `near_field` say otherwise (the boundary elements of Sec. 4):
+    source_field(P, idx) is the matrix of the potentials at the points P of
+    the unit densities of sources idx (S2M's check potential, Sec. 4.2), and
+    near_field(tidx, sidx) that at points tidx of sources sidx (S2T).
 
     Returns (phi, info) where info holds the tree and the operators.
     """
@@ -57,7 +63,9 @@ def fmm(x: np.ndarray, sigma: np.ndarray, p: int, eps: float, leaf_size: int,
         rL = tree.half_width(L)
         for b, idx in tree.leaf_points.items():
             c = tree.box_centre(L, b)
-            check = kernel_matrix(c + rL * ops.UC, x[idx]) @ s[idx]   # S2M, Sec. 2.2
+            P = c + rL * ops.UC
+            G = kernel_matrix(P, x[idx]) if source_field is None else source_field(P, idx)
+            check = G @ s[idx]                                          # S2M, Sec. 2.2
             up[L][b] = rL * (ops.S @ check)
         for level in range(L - 1, 1, -1):                               # M2M, Sec. 2.2
             for b in tree.boxes[level]:
@@ -109,7 +117,8 @@ def fmm(x: np.ndarray, sigma: np.ndarray, p: int, eps: float, leaf_size: int,
             phi[idx] += kernel_matrix(x[idx], c + rL * ops.DE) @ e
         for nb in tree.near(L, b):
             j = tree.leaf_points[nb]
-            phi[idx] += kernel_matrix(x[idx], x[j]) @ s[j]
+            G = kernel_matrix(x[idx], x[j]) if near_field is None else near_field(idx, j)
+            phi[idx] += G @ s[j]
     if sample is not None:
         phi = phi[np.asarray(sample)]
     if vec:

@@ -113,6 +113,34 @@ def ellipsoid_points(n: int, seed: int, axes=(2.0, 1.0, 0.5)):
     return cen[idx].copy()
 
 
+def ellipsoid_surface_mesh(level: int, axes=(2.0, 1.0, 3.0)):
+    """Triangulated ellipsoid: the octahedron (8 faces) refined `level` times by
+    edge midpoints pushed out to the unit sphere, vertices scaled by `axes`.
+    8 * 4^level triangles (level 3: 512, each further level x4), outward
+    orientation (counterclockwise seen from outside). Returns (vertices (nv, 3)
+    float64, triangles (nt, 3) int32)."""
+    v = [np.array(a, dtype=np.float64) for a in
+         ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1))]
+    f = [(0, 2, 4), (2, 1, 4), (1, 3, 4), (3, 0, 4), (2, 0, 5), (1, 2, 5), (3, 1, 5), (0, 3, 5)]
+    for _ in range(level):
+        mid = {}
+
+        def m(a, b):
+            key = (min(a, b), max(a, b))
+            if key not in mid:
+                w = v[a] + v[b]
+                v.append(w / np.linalg.norm(w))
+                mid[key] = len(v) - 1
+            return mid[key]
+        nf = []
+        for a, b, c in f:
+            ab, bc, ca = m(a, b), m(b, c), m(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        f = nf
+    verts = np.asarray(v) * np.asarray(axes, dtype=np.float64)
+    return verts, np.asarray(f, dtype=np.int32)
+
+
 def clustered_points(n_bg: int, n_cl: int, seed: int, centre=(0.5, 0.5, 0.5), width: float = 0.02):
     """n_bg iid uniform points in [-1,1]^3 and a Gaussian cluster of n_cl
     points (standard deviation `width`) around `centre`: a point set whose
