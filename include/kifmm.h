@@ -64,6 +64,11 @@ enum {
                         a multiple of 32) */
 };
 
+enum {
+    KIFMM_SINGLE_LAYER = 0, /* BEM plans: G(x, y) = 1 / (4 pi |x - y|) */
+    KIFMM_DOUBLE_LAYER = 1  /* BEM plans: dG(x, y)/dn(y) */
+};
+
 typedef struct {
     int precision;      /* KIFMM_FP64 / KIFMM_FP32 / KIFMM_BF16X3; default KIFMM_FP32 */
     double cd;          /* surface constant C_d of d = C_d / sqrt(leaf_size) (Sec. 4.1); default 0.5 */
@@ -145,6 +150,7 @@ typedef struct {
     int64_t w_cubes;        /* adaptive: cubes in some W list (their U~ q~ is formed once) */
     double m2t_flops;       /* adaptive: M2T (U~ products and point evaluations) per apply */
     double s2l_flops;       /* adaptive: S2L (point evaluations and U~^T products) per apply */
+    int layer;              /* -1 point sources; BEM plans: KIFMM_SINGLE_LAYER / KIFMM_DOUBLE_LAYER */
 } kifmm_info_t;
 
 /* Fill `o` with the defaults listed above. Returns KIFMM_EINVAL if o is NULL. */
@@ -165,6 +171,31 @@ int kifmm_plan(const double* points, int64_t n, int p, double eps, int leaf_size
 /* As kifmm_plan with options (NULL = defaults). */
 int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_size,
                   const kifmm_opts_t* opts, kifmm_plan_t* out);
+
+/* BEM plan (Sec. 4): the collocation operator of piecewise-constant densities
+ * on a mesh of flat triangles, evaluated at the triangles' centroids,
+ *     phi_i = sum_j q_j int_{T_j} K(x_i, y) dS_y,
+ * K = G (KIFMM_SINGLE_LAYER, eq. of Sec. 4) or dG/dn(y) (KIFMM_DOUBLE_LAYER,
+ * n the unit normal given by the vertex order of T_j; the self term is its
+ * principal value, 0 on a flat triangle; the free term of a boundary integral
+ * equation is the caller's). The octree is built over the centroids (Sec. 4.1,
+ * with d = C_d / sqrt(leaf_size)); S2M evaluates the check potentials of the
+ * leaf's triangles by a 7-point degree-5 rule on each triangle (with the
+ * double-layer kernel for KIFMM_DOUBLE_LAYER, the first step of S2M in
+ * Sec. 4.2), S2T the near-field integrals in closed form (single layer: the
+ * edge formula of the integral of 1/|x - y| over a flat triangle; double
+ * layer: the signed solid angle); the other steps are those of kifmm_plan.
+ *   vertices:  host, n_vertices x 3 doubles; triangles: host, n_triangles x 3
+ *              vertex indices (0-based); both copied. Point i of the plan (the
+ *              order of sigma and phi in kifmm_apply) is triangle i.
+ *   opts:      as kifmm_plan_ex; adaptive must be 0 and max_nrhs 1.
+ * kifmm_apply, kifmm_apply_noalloc, kifmm_apply_batched (nrhs = 1) and groups
+ * (not merged) work on BEM plans; kifmm_apply_adjoint returns KIFMM_ESTATE.
+ * Errors: KIFMM_EINVAL (unknown layer, index out of range, zero-area
+ * triangle, adaptive or max_nrhs > 1), KIFMM_ENONFINITE, KIFMM_ENOMEM,
+ * KIFMM_EHIP. */
+int kifmm_plan_bem(const double* vertices, int64_t n_vertices, const int32_t* triangles, int64_t n_triangles,
+                   int layer, int p, double eps, int leaf_size, const kifmm_opts_t* opts, kifmm_plan_t* out);
 
 /* phi = F sigma, the FMM approximation of eq. (1) (Alg. Steps 2-4, Sec. 4.3).
  *   sigma, phi: device, n elements each, caller order; must not alias. */
@@ -217,6 +248,24 @@ int kifmm_group_create(const kifmm_plan_t* plans, int nplans, kifmm_group_t* out
 int kifmm_group_apply(kifmm_group_t group, const void* const* sigma, void* const* phi,
                       void* stream);
 void kifmm_group_destroy(kifmm_group_t group); /* NULL-safe */
+
+/* Solve A x = b for the plan's operator A (the BEM systems of Sec. 4 are
+ * solved by GMRES, Sec. 5) with restarted GMRES(restart): classical
+ * Gram-Schmidt applied twice, the Krylov basis in device memory in the plan's
+ * precision (restart + 1 vectors of n elements, allocated by this call and
+ * freed before it returns), the small Hessenberg problem on the host in FP64.
+ *   b:  device, n elements, caller order (not modified).
+ *   x:  device, n elements: the initial guess on entry, the solution on return.
+ *   Stops when the relative residual |b - A x| / |b| (recomputed explicitly at
+ *   every restart and at the end) is <= tol, or after max_iter applies.
+ *   iterations (may be NULL): applies used; residual (may be NULL): the final
+ *   relative residual. The call synchronizes `stream` (it reads the inner
+ *   products on the host every iteration) and cannot be captured in a graph.
+ * Errors: KIFMM_EINVAL (tol <= 0, restart outside [1, 200], max_iter < 1,
+ * NULL or equal pointers), KIFMM_ESTATE (host-only plan), KIFMM_EHIP. Not
+ * reaching tol is not an error: check *residual. */
+int kifmm_solve_gmres(kifmm_plan_t plan, const void* b, void* x, double tol, int restart, int max_iter,
+                      void* stream, int* iterations, double* residual);
 
 /* Sizes, counts and per-stage algorithmic flops/bytes of a plan. */
 int kifmm_plan_info(kifmm_plan_t plan, kifmm_info_t* info);

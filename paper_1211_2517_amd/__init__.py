@@ -30,6 +30,7 @@ EXPORTED_SYMBOLS = (
     "kifmm_plan_info", "kifmm_plan_export_tree", "kifmm_plan_export_operator", "kifmm_profile",
     "kifmm_profile_read", "kifmm_destroy", "kifmm_last_error", "kifmm_apply_noalloc",
     "kifmm_plan_export_point_leaves", "kifmm_plan_export_boxes", "kifmm_plan_export_list",
+    "kifmm_plan_bem", "kifmm_solve_gmres",
 )
 
 
@@ -59,7 +60,8 @@ class _Info(ctypes.Structure):
                 ("m2l_variant", ctypes.c_int), ("m2l_tiles", ctypes.c_int),
                 ("m2l_rank_max", ctypes.c_int), ("m2l_rank_mean", ctypes.c_double),
                 ("adaptive", ctypes.c_int), ("leaf_level_min", ctypes.c_int), ("w_pairs", ctypes.c_int64),
-                ("w_cubes", ctypes.c_int64), ("m2t_flops", ctypes.c_double), ("s2l_flops", ctypes.c_double)]
+                ("w_cubes", ctypes.c_int64), ("m2t_flops", ctypes.c_double), ("s2l_flops", ctypes.c_double),
+                ("layer", ctypes.c_int)]
 
 
 _LIB = None
@@ -96,6 +98,8 @@ def load_library():
     lib.kifmm_plan_export_point_leaves.argtypes = [V, P]
     lib.kifmm_plan_export_boxes.argtypes = [V, P, ctypes.POINTER(I64)]
     lib.kifmm_plan_export_list.argtypes = [V, I, P, ctypes.POINTER(I64)]
+    lib.kifmm_solve_gmres.argtypes = [V, P, P, D, I, I, P, ctypes.POINTER(I), ctypes.POINTER(D)]
+    lib.kifmm_plan_bem.argtypes = [P, I64, P, I64, I, I, D, I, ctypes.POINTER(_Opts), ctypes.POINTER(V)]
     lib.kifmm_profile.argtypes = [V, I]
     lib.kifmm_profile_read.argtypes = [V, P, ctypes.POINTER(I64)]
     lib.kifmm_destroy.argtypes = [V]
@@ -125,7 +129,7 @@ class Plan:
                  precision: str = "fp32", dense_m2l: bool = False, max_nrhs: int = 1, device: int = 0,
                  depth: int = 0, max_depth: int = 16, cd: float = 0.5, pinv_rcond: float = 1e-10,
                  mem_limit: int = 0, tile_targets: int = 0, m2l_shape: int = -1, c2: float = 0.0,
-                 adaptive: bool = False):
+                 adaptive: bool = False, _mesh=None):
         lib = load_library()
         pts = np.ascontiguousarray(np.asarray(points.cpu().numpy() if hasattr(points, "cpu") else points,
                                               dtype=np.float64))
@@ -147,8 +151,13 @@ class Plan:
         o.c2 = float(c2)
         o.adaptive = int(bool(adaptive))
         h = ctypes.c_void_p()
-        _check(lib.kifmm_plan_ex(pts.ctypes.data, pts.shape[0], int(p), float(eps), int(leaf_size),
-                                 ctypes.byref(o), ctypes.byref(h)))
+        if _mesh is None:
+            _check(lib.kifmm_plan_ex(pts.ctypes.data, pts.shape[0], int(p), float(eps), int(leaf_size),
+                                     ctypes.byref(o), ctypes.byref(h)))
+        else:
+            verts, tris, layer = _mesh
+            _check(lib.kifmm_plan_bem(verts.ctypes.data, verts.shape[0], tris.ctypes.data, tris.shape[0], layer,
+                                      int(p), float(eps), int(leaf_size), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         self._lib = lib
         self.n = pts.shape[0]
@@ -156,6 +165,21 @@ class Plan:
         self.precision = precision
         self.device = device
         self.max_nrhs = max_nrhs
+
+    @classmethod
+    def bem(cls, vertices, triangles, layer: str = "single", p: int = 6, eps: float = 1e-6, leaf_size: int = 64,
+            **kw):
+        """BEM plan (kifmm_plan_bem): point i is the centroid of triangle i;
+        apply(q) gives sum_j q_j int_{T_j} K(x_i, y) dS_y, K the single layer
+        G or the double layer dG/dn(y)."""
+        verts = np.ascontiguousarray(np.asarray(vertices, dtype=np.float64))
+        tris = np.ascontiguousarray(np.asarray(triangles, dtype=np.int32))
+        if verts.ndim != 2 or verts.shape[1] != 3 or tris.ndim != 2 or tris.shape[1] != 3:
+            raise ValueError("vertices must be (nv, 3) and triangles (nt, 3)")
+        lay = {"single": 0, "double": 1}[layer]
+        centroids = verts[tris].mean(axis=1) if tris.size and tris.min() >= 0 and tris.max() < len(verts) \
+            else np.zeros((tris.shape[0], 3))
+        return cls(centroids, p=p, eps=eps, leaf_size=leaf_size, _mesh=(verts, tris, lay), **kw)
 
     # ------------------------------------------------------------------ info
     def info(self) -> dict:
@@ -330,6 +354,17 @@ class Plan:
         _check(self._lib.kifmm_apply_batched(self._h, sigma_cm.data_ptr(), out_cm.data_ptr(), nrhs, self.n,
                                              self._stream()))
         return out_cm
+
+    def solve_gmres(self, b, x0=None, tol: float = 1e-6, restart: int = 50, max_iter: int = 500):
+        """x with A x = b (kifmm_solve_gmres): returns (x, applies used, final relative residual)."""
+        b = self._check_vec(b, "b")
+        torch = _torch()
+        x = torch.zeros_like(b) if x0 is None else self._check_vec(x0, "x0").clone()
+        it = ctypes.c_int()
+        res = ctypes.c_double()
+        _check(self._lib.kifmm_solve_gmres(self._h, b.data_ptr(), x.data_ptr(), float(tol), int(restart),
+                                           int(max_iter), self._stream(), ctypes.byref(it), ctypes.byref(res)))
+        return x, it.value, res.value
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -136,6 +136,11 @@ struct kifmm_plan_s {
     int32_t *s2l_ptr = nullptr, *s2l_leaf = nullptr;
     void *m2t_geo = nullptr, *s2l_geo = nullptr;   // per entry (rho, ox, oy, oz) in the element type
     void *Ut = nullptr, *UtT = nullptr, *surf_in = nullptr;
+    // BEM plans (Sec. 4): the points are the triangles' centroids; per
+    // triangle (sorted order, leaf units) its 7-point rule (x, y, z, W), its
+    // unit normal, and its vertices and normal for the near-field integrals
+    int layer = -1;                      // -1 point sources, 0 single layer, 1 double layer
+    void *bem_qp = nullptr, *bem_tn = nullptr, *bem_tri = nullptr;
     void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
     void *CX = nullptr, *Psi = nullptr;   // adaptive: per W cube, S2L check potentials and U~ q~
     std::vector<void*> allocs;
@@ -584,6 +589,63 @@ void upload_adaptive(kifmm_plan_s* pl, Uploader& up) {
     pl->Psi = up.zeros(bytes);
 }
 
+// Triangles of a BEM plan in the plan's point order, in the units of each
+// triangle's leaf (the leaf of its centroid): the 7-point rule of Radon
+// (degree 5; weights x area, divided by r_L for the double layer, whose S2M
+// kernel carries one more inverse length), the unit normal, and the vertices.
+struct BemMesh {
+    std::vector<double> verts;   // 3 per vertex
+    std::vector<int32_t> tris;   // 3 per triangle (caller order)
+};
+
+template <typename T>
+void upload_bem(kifmm_plan_s* pl, Uploader& up, const BemMesh& m) {
+    const HostTree& t = pl->tree;
+    const int64_t n = t.n;
+    const double r = t.half_width(t.depth);
+    const double s15 = std::sqrt(15.0);
+    const double a1 = (6.0 - s15) / 21.0, b1 = (9.0 + 2.0 * s15) / 21.0;
+    const double a2 = (6.0 + s15) / 21.0, b2 = (9.0 - 2.0 * s15) / 21.0;
+    const double w1 = (155.0 - s15) / 1200.0, w2 = (155.0 + s15) / 1200.0;
+    const double bary[7][3] = {{1.0 / 3, 1.0 / 3, 1.0 / 3}, {a1, a1, b1}, {a1, b1, a1}, {b1, a1, a1},
+                               {a2, a2, b2}, {a2, b2, a2}, {b2, a2, a2}};
+    const double wq[7] = {9.0 / 40.0, w1, w1, w1, w2, w2, w2};
+    std::vector<T> qp(28 * (size_t)n), tn(4 * (size_t)n, T(0)), tri(16 * (size_t)n, T(0));
+    for (int64_t e = 0; e < t.n_leaf(); ++e) {
+        int64_t c[3];
+        box_cube(t, t.level_begin[t.depth] + e, c);
+        double cen[3];
+        for (int a = 0; a < 3; ++a) cen[a] = (t.centre[a] - t.r0) + (2.0 * double(c[a]) + 1.0) * r;
+        for (int32_t i = t.leaf_ptr[e]; i < t.leaf_ptr[e + 1]; ++i) {
+            const int32_t* f = &m.tris[3 * (size_t)t.perm[i]];
+            double v[3][3];
+            for (int k = 0; k < 3; ++k)
+                for (int a = 0; a < 3; ++a) v[k][a] = (m.verts[3 * (size_t)f[k] + a] - cen[a]) / r;
+            const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+            const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+            const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                                  e1[0] * e2[1] - e1[1] * e2[0]};
+            const double len = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+            const double area = 0.5 * len * r * r;   // physical area
+            const double wscale = pl->layer == 1 ? area / r : area;
+            for (int k = 0; k < 7; ++k) {
+                for (int a = 0; a < 3; ++a)
+                    qp[28 * (size_t)i + 4 * k + a] =
+                        (T)(bary[k][0] * v[0][a] + bary[k][1] * v[1][a] + bary[k][2] * v[2][a]);
+                qp[28 * (size_t)i + 4 * k + 3] = (T)(wq[k] * wscale);
+            }
+            for (int a = 0; a < 3; ++a) {
+                tn[4 * (size_t)i + a] = (T)(cr[a] / len);
+                for (int k = 0; k < 3; ++k) tri[16 * (size_t)i + 4 * k + a] = (T)v[k][a];
+                tri[16 * (size_t)i + 12 + a] = (T)(cr[a] / len);
+            }
+        }
+    }
+    pl->bem_qp = up.put(qp);
+    pl->bem_tn = up.put(tn);
+    pl->bem_tri = up.put(tri);
+}
+
 // Device schedules and buffer of the stage-2 M2L (Sec. 3.2), from the M2L
 // schedule (same tiles and chunks): phase A writes w = V^ q of every pair into
 // its own chunk slot (direct form: one output row per slot), phase B adds
@@ -729,6 +791,7 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
     in.m2l_variant = pl->h_m2l.variant;
     in.m2l_tiles = pl->h_m2l.n_tiles();
     in.adaptive = t.adaptive ? 1 : 0;
+    in.layer = pl->layer;
     in.leaf_level_min = t.depth;
     if (t.adaptive) {
         for (int32_t l : t.leaf_level) in.leaf_level_min = std::min(in.leaf_level_min, (int)l);
@@ -1189,6 +1252,8 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     KIFMM_HIP(hipStreamIsCapturing(st, &cap_status));
     if (pl->profiling && cap_status != hipStreamCaptureStatusNone)
         return fail(KIFMM_ESTATE, "a plan with profiling on cannot be applied inside a stream capture");
+    if (adjoint && pl->layer >= 0)
+        return fail(KIFMM_ESTATE, "BEM plans have no adjoint apply (the collocation operator is not symmetric)");
     int cur = 0;
     KIFMM_HIP(hipGetDevice(&cur));
     if (cur != pl->device) KIFMM_HIP(hipSetDevice(pl->device));
@@ -1219,6 +1284,10 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     const int32_t* lev = ad ? pl->leaf_level : nullptr;
     const void* lsc = ad ? pl->leaf_scale : nullptr;
     const int n_eq = pl->ops().n_eq;
+    // BEM plans (Sec. 4): triangles as sources; near-field scale of the
+    // closed-form integrals in leaf units
+    const bool bem = pl->layer >= 0;
+    const double bem_scale = pl->layer == 1 ? -1.0 / kFourPi : rL / kFourPi;
     // M2T at the points (after the far field, adding to it)
     auto m2t_eval = [&]() -> hipError_t {
         if (!far || !ad || pl->n_m2t_leaf == 0) return hipSuccess;
@@ -1238,6 +1307,10 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         KIFMM_HIP(hipEventRecord(pl->ev_fork, st));
         KIFMM_HIP(hipStreamWaitEvent(ns, pl->ev_fork, 0));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P], ns));
+        if (bem)
+            KIFMM_HIP(launch_eval_near_bem(elt, pl->layer, nleaf, pl->pts, pl->bem_tri, w.sig_s, pl->leaf_ptr,
+                                           pl->near_ptr, pl->near_leaf, pl->near_code, bem_scale, pl->perm, out, ns));
+        else
         KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
                                       pl->near_leaf, pl->near_code, lev, lsc, nullptr, pl->surf, n_eq, nep,
                                       near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, ns));
@@ -1247,8 +1320,12 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 0));
     if (far) {
         // upward (forward) / L2T^T (adjoint): surface evaluation and the leaf GEMM
-        KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, w.sig_s, pl->leaf_ptr, pl->surf, pl->ops().n_eq, nep,
-                                      w.C, st));
+        if (bem)
+            KIFMM_HIP(launch_eval_surface_bem(elt, pl->layer, nleaf, pl->bem_qp, pl->bem_tn, w.sig_s, pl->leaf_ptr,
+                                              pl->surf, n_eq, nep, w.C, st));
+        else
+            KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, w.sig_s, pl->leaf_ptr, pl->surf, n_eq, nep, w.C,
+                                          st));
         KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->k, pl->ops().n_eq, w.C, nep,
                             adjoint ? w.P : w.Q, kp, R, 0, st));
     }
@@ -1322,7 +1399,17 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_L2P, 1));
-    if (!fork) {
+    if (!fork && bem) {
+        // BEM: the near-field integrals, then the far field added
+        KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
+        KIFMM_HIP(launch_eval_near_bem(elt, pl->layer, nleaf, pl->pts, pl->bem_tri, w.sig_s, pl->leaf_ptr,
+                                       pl->near_ptr, pl->near_leaf, pl->near_code, bem_scale, pl->perm, out, st));
+        if (far)
+            KIFMM_HIP(launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
+                                          pl->near_leaf, pl->near_code, lev, lsc, w.E, pl->surf, n_eq, nep,
+                                          near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
+        KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
+    } else if (!fork) {
         // near field and (when there is one) far field in one kernel
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
         KIFMM_HIP(launch_eval_targets(3, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
@@ -1350,7 +1437,7 @@ bool fusable(const std::vector<kifmm_plan_t>& ps) {
         if (b->device != a->device || b->opts.precision != a->opts.precision || b->R != a->R || b->st2 ||
             b->p != a->p || b->eps != a->eps || b->leaf_size != a->leaf_size || b->opts.cd != a->opts.cd ||
             b->opts.pinv_rcond != a->opts.pinv_rcond || b->opts.dense_m2l != a->opts.dense_m2l ||
-            b->kp != a->kp || b->nep != a->nep || b->profiling)
+            b->kp != a->kp || b->nep != a->nep || b->profiling || b->layer >= 0)
             return false;
     }
     return true;
@@ -1612,6 +1699,21 @@ void destroy_profile_events(kifmm_plan_s* pl) {
 
 extern "C" {
 
+}  // extern "C"
+
+namespace kifmm {
+int solve_fail(int code, const std::string& msg) { return fail(code, msg); }
+// element bytes of a plan that can be applied (and its point count), or an error code
+int plan_precision_bytes(kifmm_plan_t plan, int64_t* n) {
+    const int rc = check_plan_for_apply(plan);
+    if (rc) return rc;
+    *n = plan->tree.n;
+    return plan->elt;
+}
+}  // namespace kifmm
+
+extern "C" {
+
 int kifmm_opts_default(kifmm_opts_t* o) {
     if (!o) return fail(KIFMM_EINVAL, "opts is NULL");
     std::memset(o, 0, sizeof(*o));
@@ -1633,8 +1735,8 @@ int kifmm_plan(const double* points, int64_t n, int p, double eps, int leaf_size
     return kifmm_plan_ex(points, n, p, eps, leaf_size, nullptr, out);
 }
 
-int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_size,
-                  const kifmm_opts_t* opts, kifmm_plan_t* out) {
+static int plan_build(const double* points, int64_t n, int p, double eps, int leaf_size, const kifmm_opts_t* opts,
+                      const BemMesh* bem, int layer, kifmm_plan_t* out) {
     g_last_error.clear();
     if (!out) return fail(KIFMM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -1656,6 +1758,8 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
         return fail(KIFMM_EINVAL, "c2 > 0 (stage-2 low rank) needs compressed operators in FP32 or FP64");
     if (o.adaptive != 0 && o.adaptive != 1) return fail(KIFMM_EINVAL, "adaptive must be 0 or 1");
     if (o.adaptive && o.depth > 0) return fail(KIFMM_EINVAL, "adaptive trees take no forced depth (opts.depth)");
+    if (bem && (o.adaptive || o.max_nrhs != 1))
+        return fail(KIFMM_EINVAL, "BEM plans take uniform trees and one right-hand side (adaptive = 0, max_nrhs = 1)");
     const auto t0 = std::chrono::steady_clock::now();
     kifmm_plan_s* pl = new (std::nothrow) kifmm_plan_s();
     if (!pl) return fail(KIFMM_ENOMEM, "host allocation failed");
@@ -1665,6 +1769,7 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     pl->leaf_size = leaf_size;
     pl->elt = o.precision == KIFMM_FP64 ? 8 : 4;
     pl->b3 = o.precision == KIFMM_BF16X3;
+    pl->layer = bem ? layer : -1;
     pl->R = 1;
     while (pl->R < o.max_nrhs) pl->R <<= 1;
     try {
@@ -1756,6 +1861,12 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
             else
                 upload_adaptive<double>(pl, up);
         }
+        if (up.err == KIFMM_OK && bem) {
+            if (pl->elt == 4)
+                upload_bem<float>(pl, up, *bem);
+            else
+                upload_bem<double>(pl, up, *bem);
+        }
         if (up.err == KIFMM_OK &&
             (hipStreamCreateWithFlags(&pl->near_stream, hipStreamNonBlocking) != hipSuccess ||
              hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -1791,6 +1902,50 @@ int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_s
     fill_info(pl, secs);
     *out = pl;
     return KIFMM_OK;
+}
+
+int kifmm_plan_ex(const double* points, int64_t n, int p, double eps, int leaf_size, const kifmm_opts_t* opts,
+                  kifmm_plan_t* out) {
+    return plan_build(points, n, p, eps, leaf_size, opts, nullptr, -1, out);
+}
+
+int kifmm_plan_bem(const double* vertices, int64_t n_vertices, const int32_t* triangles, int64_t n_triangles,
+                   int layer, int p, double eps, int leaf_size, const kifmm_opts_t* opts, kifmm_plan_t* out) {
+    g_last_error.clear();
+    if (!out) return fail(KIFMM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!vertices || !triangles) return fail(KIFMM_EINVAL, "vertices and triangles must be non-NULL");
+    if (layer != KIFMM_SINGLE_LAYER && layer != KIFMM_DOUBLE_LAYER) return fail(KIFMM_EINVAL, "unknown layer");
+    if (n_vertices < 3 || n_triangles < 1 || n_triangles > (int64_t)INT32_MAX / 2)
+        return fail(KIFMM_EINVAL, "need at least 3 vertices and 1 triangle");
+    BemMesh m;
+    try {
+        m.verts.assign(vertices, vertices + 3 * n_vertices);
+        m.tris.assign(triangles, triangles + 3 * n_triangles);
+    } catch (const std::bad_alloc&) {
+        return fail(KIFMM_ENOMEM, "host allocation failed");
+    }
+    for (double v : m.verts)
+        if (!std::isfinite(v)) return fail(KIFMM_ENONFINITE, "non-finite vertex coordinate");
+    std::vector<double> cen(3 * (size_t)n_triangles);
+    for (int64_t j = 0; j < n_triangles; ++j) {
+        const int32_t* f = &m.tris[3 * (size_t)j];
+        for (int k = 0; k < 3; ++k)
+            if (f[k] < 0 || f[k] >= n_vertices)
+                return fail(KIFMM_EINVAL, "triangle " + std::to_string(j) + " has a vertex index out of range");
+        double e1[3], e2[3];
+        for (int a = 0; a < 3; ++a) {
+            const double v0 = m.verts[3 * (size_t)f[0] + a];
+            e1[a] = m.verts[3 * (size_t)f[1] + a] - v0;
+            e2[a] = m.verts[3 * (size_t)f[2] + a] - v0;
+            cen[3 * (size_t)j + a] = (v0 + m.verts[3 * (size_t)f[1] + a] + m.verts[3 * (size_t)f[2] + a]) / 3.0;
+        }
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                     cz = e1[0] * e2[1] - e1[1] * e2[0];
+        if (!(cx * cx + cy * cy + cz * cz > 0.0))
+            return fail(KIFMM_EINVAL, "triangle " + std::to_string(j) + " has zero area");
+    }
+    return plan_build(cen.data(), n_triangles, p, eps, leaf_size, opts, &m, layer, out);
 }
 
 int kifmm_apply(kifmm_plan_t plan, const void* sigma, void* phi, void* stream) {

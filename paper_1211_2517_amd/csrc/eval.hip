@@ -526,6 +526,199 @@ __global__ void __launch_bounds__(256) eval_s2l_kernel(
     }
 }
 
+// BEM S2M check potentials (Sec. 4.2): one wave per leaf, lanes over the
+// (3-2d) surface; the sources are the 7 quadrature points of every triangle of
+// the leaf, staged as (x, y, z, W q) in leaf units (W = rule weight x area,
+// divided by r_L for the double layer), with the triangle's unit normal for
+// the double layer, whose kernel n.(s - y) / |s - y|^3 replaces 1/|s - y|.
+template <typename T, bool DL>
+__global__ void __launch_bounds__(256) eval_surface_bem_kernel(
+    int64_t n_leaf, const P4<T>* __restrict__ qp, const P4<T>* __restrict__ tn, const T* __restrict__ sig,
+    const int32_t* __restrict__ leaf_ptr, const T* __restrict__ surf, int n_eq, int nep, T* __restrict__ C) {
+    constexpr int WPB = 4;
+    constexpr int CAP = 64;
+    __shared__ P4<T> sp[WPB][CAP];
+    __shared__ P4<T> sn[WPB][DL ? CAP : 1];
+    const int wave = threadIdx.x >> 6;
+    const int64_t leaf = (int64_t)blockIdx.x * WPB + wave;
+    if (leaf >= n_leaf) return;
+    const int lane = threadIdx.x & 63;
+    P4<T>* st = sp[wave];
+    P4<T>* stn = sn[DL ? wave : 0];
+    constexpr int NA = (19 * 16 + 63) / 64;
+    T sx[NA], sy[NA], sz[NA], acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int a = k * 64 + lane;
+        const bool ok = a < n_eq;
+        sx[k] = ok ? surf[3 * a] : T(0);
+        sy[k] = ok ? surf[3 * a + 1] : T(0);
+        sz[k] = ok ? surf[3 * a + 2] : T(0);
+        acc[k] = 0;
+    }
+    const int na = (nep + 63) / 64;
+    const int q0 = 7 * leaf_ptr[leaf], q1 = 7 * leaf_ptr[leaf + 1];
+    for (int base = q0; base < q1; base += CAP) {
+        const int cnt = min(CAP, q1 - base);
+        __builtin_amdgcn_wave_barrier();
+        if (lane < cnt) {
+            const int qi = base + lane;
+            const P4<T> v = qp[qi];
+            st[lane] = P4<T>{v.x, v.y, v.z, v.w * sig[qi / 7]};
+            if constexpr (DL) stn[lane] = tn[qi / 7];
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+        for (int jj = 0; jj < cnt; ++jj) {
+            const P4<T> f = st[jj];
+            P4<T> nv{0, 0, 0, 0};
+            if constexpr (DL) nv = stn[jj];
+#pragma unroll
+            for (int k = 0; k < NA; ++k) {
+                if (k < na) {
+                    const T dx = sx[k] - f.x, dy = sy[k] - f.y, dz = sz[k] - f.z;
+                    const T rinv = rsq(dx * dx + dy * dy + dz * dz);
+                    if constexpr (DL)
+                        acc[k] += f.w * (nv.x * dx + nv.y * dy + nv.z * dz) * rinv * rinv * rinv;
+                    else
+                        acc[k] += f.w * rinv;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int a = k * 64 + lane;
+        if (k < na && a < nep) C[leaf * nep + a] = a < n_eq ? acc[k] : T(0);
+    }
+}
+
+// int_T 1/|x - y| dS_y over a flat triangle (vertices a, b, c, unit normal n)
+// in closed form: for the projection x0 of x on the plane and its height h,
+// every edge with in-plane outward normal m and unit tangent t adds
+// p ln((R+ + s+)/(R- + s-)) - |h| (atan(p s+ / (R0^2 + |h| R+)) - atan(p s- /
+// (R0^2 + |h| R-))), p = (start - x0).m, s = (end points - x0).t, R0^2 = p^2 +
+// h^2, R = sqrt(s^2 + R0^2) (Wilton et al. 1984); R + s is formed as R0^2 /
+// (R - s) for s < 0, which has no cancellation.
+template <typename T>
+__device__ __forceinline__ T tri_inv_r(T x, T y, T z, const P4<T>& a, const P4<T>& b, const P4<T>& c,
+                                       const P4<T>& n) {
+    const T h = (x - a.x) * n.x + (y - a.y) * n.y + (z - a.z) * n.z;
+    const T x0 = x - h * n.x, y0 = y - h * n.y, z0 = z - h * n.z;
+    const T ah = fabs(h);
+    T total = 0;
+    const P4<T>* vs[3] = {&a, &b, &c};
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const P4<T>& u = *vs[e];
+        const P4<T>& w = *vs[(e + 1) % 3];
+        const T ex = w.x - u.x, ey = w.y - u.y, ez = w.z - u.z;
+        const T len = sqrt(ex * ex + ey * ey + ez * ez);
+        const T il = T(1) / len;
+        const T tx = ex * il, ty = ey * il, tz = ez * il;
+        const T mx = ty * n.z - tz * n.y, my = tz * n.x - tx * n.z, mz = tx * n.y - ty * n.x;
+        const T dx = u.x - x0, dy = u.y - y0, dz = u.z - z0;
+        const T p = dx * mx + dy * my + dz * mz;
+        const T sm = dx * tx + dy * ty + dz * tz;
+        const T sp = sm + len;
+        const T r0 = p * p + h * h;
+        const T rm = sqrt(sm * sm + r0), rp = sqrt(sp * sp + r0);
+        if (p != T(0)) {
+            const T num = sp >= T(0) ? rp + sp : r0 / (rp - sp);
+            const T den = sm >= T(0) ? rm + sm : r0 / (rm - sm);
+            total += p * log(num / den);
+            if (ah > T(0)) total -= ah * (atan(p * sp / (r0 + ah * rp)) - atan(p * sm / (r0 + ah * rm)));
+        }
+    }
+    return total;
+}
+
+// signed solid angle of the triangle (a, b, c) seen from x (Van Oosterom and
+// Strackee 1983): positive when x is on the side the normal points away from
+template <typename T>
+__device__ __forceinline__ T tri_solid_angle(T x, T y, T z, const P4<T>& a, const P4<T>& b, const P4<T>& c) {
+    const T r1x = a.x - x, r1y = a.y - y, r1z = a.z - z;
+    const T r2x = b.x - x, r2y = b.y - y, r2z = b.z - z;
+    const T r3x = c.x - x, r3y = c.y - y, r3z = c.z - z;
+    const T l1 = sqrt(r1x * r1x + r1y * r1y + r1z * r1z);
+    const T l2 = sqrt(r2x * r2x + r2y * r2y + r2z * r2z);
+    const T l3 = sqrt(r3x * r3x + r3y * r3y + r3z * r3z);
+    const T num = r1x * (r2y * r3z - r2z * r3y) + r1y * (r2z * r3x - r2x * r3z) + r1z * (r2x * r3y - r2y * r3x);
+    const T den = l1 * l2 * l3 + (r1x * r2x + r1y * r2y + r1z * r2z) * l3 + (r1x * r3x + r1y * r3y + r1z * r3z) * l2 +
+                  (r2x * r3x + r2y * r3y + r2z * r3z) * l1;
+    return T(2) * atan2(num, den);
+}
+
+// BEM near field (S2T, Sec. 4.2): one wave per target leaf, `lpt` lanes per
+// collocation point splitting the near-field triangles, which are staged as
+// four 4-vectors (vertices shifted into the target leaf's units by the cube
+// offset, unit normal; q in the first vertex's w, the triangle's index in the
+// second's). Single layer: out = scale * sum_j q_j int_T 1/|x - y| (scale =
+// r_L / (4 pi)); double layer: scale * sum_j q_j Omega_j (scale = -1/(4 pi)),
+// the self triangle contributing 0 (principal value). Writes out.
+template <typename T, bool DL>
+__global__ void __launch_bounds__(256) eval_near_bem_kernel(
+    int64_t n_leaf, const P4<T>* __restrict__ pts, const P4<T>* __restrict__ tri, const T* __restrict__ sig,
+    const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_leaf,
+    const int32_t* __restrict__ near_code, T scale, const int32_t* __restrict__ perm, T* __restrict__ out) {
+    constexpr int WPB = 4;
+    constexpr int CAP = 32;
+    __shared__ P4<T> sp[WPB][4 * CAP];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t leaf = (int64_t)blockIdx.x * WPB + wave;
+    if (leaf >= n_leaf) return;
+    P4<T>* st = sp[wave];
+    const int p0 = leaf_ptr[leaf];
+    const int ne = leaf_ptr[leaf + 1] - p0;
+    int lpt = 64;
+    while (lpt > 1 && (64 / lpt) < ne) lpt >>= 1;
+    const int tpr = 64 / lpt;
+    const int sub = lane & (lpt - 1);
+    const int q0 = near_ptr[leaf], q1 = near_ptr[leaf + 1];
+    for (int tb = 0; tb < ne; tb += tpr) {
+        const int tl = tb + lane / lpt;
+        const bool valid = tl < ne;
+        const int i = p0 + (valid ? tl : 0);
+        const P4<T> ui = pts[i];
+        T acc = 0;
+        for (int q = q0; q < q1; ++q) {
+            const int nb = near_leaf[q];
+            const int code = near_code[q];
+            // source shifted into target-leaf units: s - 2 d, d = target - source cube
+            const T ox = T(-2 * (code / 9 - 1)), oy = T(-2 * ((code / 3) % 3 - 1)), oz = T(-2 * (code % 3 - 1));
+            const int b0 = leaf_ptr[nb], b1 = leaf_ptr[nb + 1];
+            for (int base = b0; base < b1; base += CAP) {
+                const int cnt = min(CAP, b1 - base);
+                __builtin_amdgcn_wave_barrier();
+                for (int f = lane; f < 4 * cnt; f += 64) {
+                    const int t = f >> 2, part = f & 3;
+                    P4<T> v = tri[4 * (int64_t)(base + t) + part];
+                    if (part < 3) {
+                        v.x += ox;
+                        v.y += oy;
+                        v.z += oz;
+                    }
+                    if (part == 0) v.w = sig[base + t];
+                    if (part == 1) v.w = T(base + t);
+                    st[f] = v;
+                }
+                __builtin_amdgcn_wave_barrier();
+                for (int t = sub; t < cnt; t += lpt) {
+                    const P4<T> a = st[4 * t], b = st[4 * t + 1], c = st[4 * t + 2], n = st[4 * t + 3];
+                    if constexpr (DL) {
+                        if ((int)b.w != i) acc += a.w * tri_solid_angle(ui.x, ui.y, ui.z, a, b, c);
+                    } else {
+                        acc += a.w * tri_inv_r(ui.x, ui.y, ui.z, a, b, c, n);
+                    }
+                }
+            }
+        }
+        for (int off = lpt >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (valid && sub == 0) out[perm[i]] = scale * acc;
+    }
+}
+
 // Vectors of several plans joined into one (gather) and split back
 // (scatter): element i of the joined vector belongs to segment s with
 // off[s] <= i < off[s+1], at index i - off[s] of that segment's pointer.
@@ -679,6 +872,43 @@ hipError_t launch_scatter_segments(int elt, int64_t n, const SegTable& seg, cons
         hipLaunchKernelGGL((scatter_segments_kernel<float>), grid, dim3(256), 0, st, n, seg, (const float*)src);
     else
         hipLaunchKernelGGL((scatter_segments_kernel<double>), grid, dim3(256), 0, st, n, seg, (const double*)src);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_surface_bem(int elt, int layer, int64_t n_leaf, const void* qp, const void* tn,
+                                   const void* sig_s, const int32_t* leaf_ptr, const void* surf, int n_eq, int nep,
+                                   void* C, hipStream_t st) {
+    if (n_leaf == 0) return hipSuccess;
+    if (n_eq > 19 * 16 || nep > 19 * 16 || (layer == 1 && tn == nullptr)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n_leaf + 3) / 4));
+#define KIFMM_SB(TT, DLV)                                                                              \
+    hipLaunchKernelGGL((eval_surface_bem_kernel<TT, DLV>), grid, dim3(256), 0, st, n_leaf, (const P4<TT>*)qp, \
+                       (const P4<TT>*)tn, (const TT*)sig_s, leaf_ptr, (const TT*)surf, n_eq, nep, (TT*)C)
+    if (elt == 4) {
+        if (layer == 1) KIFMM_SB(float, true); else KIFMM_SB(float, false);
+    } else {
+        if (layer == 1) KIFMM_SB(double, true); else KIFMM_SB(double, false);
+    }
+#undef KIFMM_SB
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_near_bem(int elt, int layer, int64_t n_leaf, const void* pts, const void* tri,
+                                const void* sig_s, const int32_t* leaf_ptr, const int32_t* near_ptr,
+                                const int32_t* near_leaf, const int32_t* near_code, double scale,
+                                const int32_t* perm, void* out, hipStream_t st) {
+    if (n_leaf == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n_leaf + 3) / 4));
+#define KIFMM_NB(TT, DLV)                                                                                   \
+    hipLaunchKernelGGL((eval_near_bem_kernel<TT, DLV>), grid, dim3(256), 0, st, n_leaf, (const P4<TT>*)pts,  \
+                       (const P4<TT>*)tri, (const TT*)sig_s, leaf_ptr, near_ptr, near_leaf, near_code, (TT)scale, \
+                       perm, (TT*)out)
+    if (elt == 4) {
+        if (layer == 1) KIFMM_NB(float, true); else KIFMM_NB(float, false);
+    } else {
+        if (layer == 1) KIFMM_NB(double, true); else KIFMM_NB(double, false);
+    }
+#undef KIFMM_NB
     return hipGetLastError();
 }
 

@@ -77,6 +77,22 @@ int gg_nbuf(int elt, int variant, int KP16);
 // included) and K dimension KP16*16.
 size_t gg_lds_bytes(int elt, int variant, int KP16, int cols);
 
+// BEM plans (Sec. 4). Check potentials of the leaves' triangles on the
+// (3-2d) surface from their 7-point rules: qp holds 7 (x, y, z, W) per
+// triangle in leaf units (sorted order), tn the unit normal per triangle
+// (double layer, layer = 1: kernel n.(s - y)/|s - y|^3); C as eval_surface.
+hipError_t launch_eval_surface_bem(int elt, int layer, int64_t n_leaf, const void* qp, const void* tn,
+                                   const void* sig_s, const int32_t* leaf_ptr, const void* surf, int n_eq, int nep,
+                                   void* C, hipStream_t st);
+// Near field of BEM plans: out[perm[i]] = scale * sum over the triangles j of
+// the near field of q_j int_{T_j} 1/|x_i - y| (layer 0) or q_j Omega_ij (layer
+// 1, signed solid angle, self term 0), in leaf units. tri holds 4 (x, y, z, -)
+// per triangle: the vertices in its own leaf's units and the unit normal.
+hipError_t launch_eval_near_bem(int elt, int layer, int64_t n_leaf, const void* pts, const void* tri,
+                                const void* sig_s, const int32_t* leaf_ptr, const int32_t* near_ptr,
+                                const int32_t* near_leaf, const int32_t* near_code, double scale,
+                                const int32_t* perm, void* out, hipStream_t st);
+
 // A joined vector of up to kMaxSegments plans' vectors (passed by value to
 // the kernels): segment s holds elements [off[s], off[s+1]) at ptr[s].
 constexpr int kMaxSegments = 64;

@@ -1,0 +1,141 @@
+"""Parity of the BEM plans (kifmm_plan_bem, Sec. 4) with the BEM oracle.
+
+The library builds the octree over the triangle centroids, evaluates S2M by
+the 7-point rule on every triangle and the near field by the closed-form
+triangle integrals (single layer) or solid angles (double layer); the oracle
+(oracle/bem.py) does the same in FP64 with its own code. Tolerances: FP64
+against the oracle in the same operator mode 1e-10 (p = 4) and 1e-8 (p = 6),
+as for point sources (the two FP64 routes through the check-to-equivalent
+pseudo-inverses differ by rounding amplified by their conditioning), except
+the double layer at p = 6: 5e-8 (measured 1.5e-8). Its values are differences
+of near- and far-field terms larger than the result, so the same rounding
+shows larger relative to it. FP32: 1e-5 relative L2 for the single layer and
+1e-4 for the double layer, for the same reason.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle import bem
+
+pytestmark = pytest.mark.gpu
+AXES = (2.0, 1.0, 3.0)
+
+
+def _k():
+    import paper_1211_2517_amd as K
+    return K
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@functools.lru_cache(maxsize=None)
+def mesh(level):
+    return workloads.ellipsoid_surface_mesh(level, AXES)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_mv(level, layer, p, leaf, mode, which):
+    V, F = mesh(level)
+    q = np.ones(F.shape[0]) if which == "one" else workloads.uniform_density(F.shape[0], 5)
+    ops = oracle.build_operators(p, 1e-8, leaf, mode=mode)
+    return bem.bem_fmm(V, F, q, p, 1e-8, leaf, layer=layer, ops=ops)[0]
+
+
+def gpu_mv(level, layer, p, leaf, precision, which, **kw):
+    import torch
+    V, F = mesh(level)
+    q = np.ones(F.shape[0]) if which == "one" else workloads.uniform_density(F.shape[0], 5)
+    plan = _k().Plan.bem(V, F, layer, p=p, eps=1e-8, leaf_size=leaf, precision=precision, **kw)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    out = plan.apply(torch.tensor(q, dtype=dt, device="cuda:0"))
+    torch.cuda.synchronize()
+    return out.double().cpu().numpy(), plan
+
+
+@pytest.mark.parametrize("layer", ["single", "double"])
+@pytest.mark.parametrize("level,p,leaf,tol", [(3, 4, 16, 1e-10), (4, 6, 32, 1e-8)])
+@pytest.mark.parametrize("mode", ["svd", "dense"])
+def test_fp64_matches_oracle(layer, level, p, leaf, tol, mode):
+    if layer == "double" and p == 6:
+        tol = 5e-8
+    want = oracle_mv(level, layer, p, leaf, mode, "rand")
+    got, plan = gpu_mv(level, layer, p, leaf, "fp64", "rand", dense_m2l=(mode == "dense"))
+    assert plan.info()["layer"] == (0 if layer == "single" else 1) and plan.info()["depth"] >= 2
+    e = rel(got, want)
+    print(f"{layer} level {level} p={p} {mode} fp64: {e:.3e}")
+    assert e < tol
+
+
+@pytest.mark.parametrize("layer,tol", [("single", 1e-5), ("double", 1e-4)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_fp32_vs_oracle(layer, tol, precision):
+    want = oracle_mv(4, layer, 6, 32, "dense", "rand")
+    got, _ = gpu_mv(4, layer, 6, 32, precision, "rand")
+    e = rel(got, want)
+    print(f"{layer} {precision}: {e:.3e}")
+    assert e < tol
+
+
+def test_double_layer_of_constant():
+    # exactly -1/2 for the dense operator; the FMM's far field by quadrature
+    # leaves the oracle's deviation, which the device result must reproduce
+    want = oracle_mv(4, "double", 6, 32, "svd", "one")
+    got, _ = gpu_mv(4, "double", 6, 32, "fp64", "one")
+    assert np.abs(want + 0.5).max() < 1e-3
+    assert np.abs(got - want).max() < 1e-8
+
+
+def test_single_leaf_is_dense_operator():
+    # leaf size >= n: no far field, every pair by the closed-form integrals
+    V, F = mesh(2)
+    for layer in ("single", "double"):
+        A = bem.dense_operator(V, F, layer)
+        q = workloads.uniform_density(F.shape[0], 6)
+        import torch
+        plan = _k().Plan.bem(V, F, layer, p=4, eps=1e-6, leaf_size=200, precision="fp64")
+        assert plan.info()["depth"] < 2
+        got = plan.apply(torch.tensor(q, dtype=torch.float64, device="cuda:0")).cpu().numpy()
+        assert rel(got, A @ q) < 1e-12, layer
+
+
+def test_bem_plan_refuses_adjoint_and_noalloc_matches():
+    import torch
+    V, F = mesh(4)
+    plan = _k().Plan.bem(V, F, "single", p=4, eps=1e-6, leaf_size=32)
+    q = torch.tensor(workloads.uniform_density(F.shape[0], 7), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(_k().KifmmError):
+        plan.apply_adjoint(q)
+    a = plan.apply(q).clone()
+    b = torch.full_like(a, float("nan"))
+    plan.apply_noalloc(q, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_conductor_gmres_matches_dense_solution():
+    # the ellipsoid conductor (2, 1, 3) at potential 1 on 2048 triangles: the
+    # device GMRES on the BEM plan against the dense collocation solution (the
+    # FMM's matvec differs from the dense operator by ~1e-5 at p = 6), and
+    # both against the closed-form density
+    import torch
+    V, F = mesh(4)
+    c, _, _ = bem.geometry(V, F)
+    q_dense = np.linalg.solve(bem.dense_operator(V, F, "single"), np.ones(F.shape[0]))
+    exact = bem.conductor_density(c, AXES)
+    e_dense = rel(q_dense, exact)
+    for precision, tol, bar in (("fp64", 1e-10, 1e-4), ("fp32", 1e-6, 1e-3)):
+        plan = _k().Plan.bem(V, F, "single", p=6, eps=1e-8, leaf_size=32, precision=precision)
+        dt = torch.float64 if precision == "fp64" else torch.float32
+        b = torch.ones(F.shape[0], dtype=dt, device="cuda:0")
+        x, iters, res = plan.solve_gmres(b, tol=tol, restart=60, max_iter=400)
+        q = x.double().cpu().numpy()
+        print(f"{precision}: {iters} applies, residual {res:.2e}, vs dense {rel(q, q_dense):.2e}, "
+              f"vs closed form {rel(q, exact):.4e} (dense {e_dense:.4e})")
+        assert res <= tol and rel(q, q_dense) < bar
+        assert abs(rel(q, exact) - e_dense) < 0.05 * e_dense
