@@ -253,6 +253,55 @@ def bench_adaptive(K, steps, warmup):
     return out
 
 
+# Relative density errors the paper reports for this conductor (Table 1,
+# p = 6, C1 = 0.1, C2 = 0 / C2 = 10; another mesh of the same sizes, CPU code):
+PAPER_TABLE1_P6 = {131072: (0.003219, 0.003220), 2097152: (0.000791, 0.000791)}
+
+
+def bench_bem(K, steps, warmup):
+    """The BEM workload (Sec. 5.1): the ellipsoid conductor (2, 1, 3) at
+    potential 1, collocation single layer on 131,072 and 2,097,152 triangles,
+    FP32, p = 6, leaf 64, eps1 = C1 2^-L / L with C1 = 0.1 (the paper's
+    setting), C2 = 0 and C2 = 10; matvec ms, GMRES to 1e-6 (applies, seconds)
+    and the density error against the closed form at 2048 sampled centroids."""
+    import numpy as np
+    import torch
+    import workloads
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "conductor_samples.json")))
+    out = {}
+    for level in ("7", "9"):
+        gl = g["levels"][level]
+        V, F = workloads.ellipsoid_surface_mesh(int(level), tuple(g["axes"]))
+        depth = K.Plan.bem(V, F, "single", p=6, eps=0.0, leaf_size=64, device=-1, dense_m2l=True).info()["depth"]
+        eps1 = 0.1 * 2.0 ** (-depth) / depth
+        rec = {"n": int(F.shape[0]), "depth": depth, "eps1": eps1}
+        for c2 in (0.0, 10.0):
+            t0 = time.perf_counter()
+            plan = K.Plan.bem(V, F, "single", p=6, eps=eps1, leaf_size=64, c2=c2)
+            plan_s = time.perf_counter() - t0
+            b = torch.ones(F.shape[0], dtype=torch.float32, device="cuda:0")
+            o = torch.empty_like(b)
+            ms = timed_ms(lambda: plan.apply(b, o), steps, warmup)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, iters, res = plan.solve_gmres(b, tol=1e-6, restart=100, max_iter=1000)
+            torch.cuda.synchronize()
+            solve_s = time.perf_counter() - t0
+            idx = np.asarray(gl["sample"])
+            err = rel(x.double().cpu().numpy()[idx], gl["density"])
+            info = plan.info()
+            rec[f"c2_{int(c2)}"] = {"k": info["k"], "m2l_rank_mean": info["m2l_rank_mean"],
+                                    "plan_seconds": round(plan_s, 2), "matvec_ms": round(ms, 4),
+                                    "gmres_applies": iters, "gmres_residual": res, "solve_seconds": round(solve_s, 3),
+                                    "density_err_vs_closed_form": err,
+                                    "paper_table1_err": PAPER_TABLE1_P6[int(F.shape[0])][0 if c2 == 0 else 1]}
+            log(f"BEM conductor N={F.shape[0]} C2={c2}: matvec {ms:.3f} ms, GMRES {iters} applies in "
+                f"{solve_s:.2f} s, density err {err:.2e}")
+            plan.close()
+        out[level] = rec
+    return {"ellipsoid_2_1_3": out}
+
+
 def bench_gradient(K, steps, warmup):
     """The differentiation workload: torus surface N = 262,144 (512 x 256 grid
     triangle centroids), p = 6, FP32; one gradient of 0.5 |F s - b|^2 is one
@@ -315,6 +364,8 @@ def main():
                     help="skip the batching, p = 8 precision and gradient workloads")
     ap.add_argument("--only-adaptive", action="store_true",
                     help="run the adaptive-tree workload only and print its record")
+    ap.add_argument("--only-bem", action="store_true",
+                    help="run the BEM conductor workload only and print its record")
     ap.add_argument("--only", choices=["svd", "dense64", "dense32", "svd_bf16x3", "svd_stage2"], default=None,
                     help="time one plan only (profiling runs); prints no JSON line")
     ap.add_argument("--m2l-shape", type=int, default=-1,
@@ -336,6 +387,9 @@ def main():
 
     if args.only_adaptive:
         print(json.dumps(bench_adaptive(K, args.steps, args.warmup)), flush=True)
+        return
+    if args.only_bem:
+        print(json.dumps(bench_bem(K, args.steps, args.warmup)), flush=True)
         return
     log("generating the 2^20-point sphere")
     x = workloads.sphere_points(N, workloads.SEED_BASE + 1)
@@ -480,6 +534,8 @@ def main():
         line["gradient_torus"] = bench_gradient(K, cs, cw)
         log("adaptive tree (2:1:0.5 ellipsoid)")
         line["adaptive_ellipsoid"] = bench_adaptive(K, cs, cw)
+        log("BEM conductor (2, 1, 3)")
+        line["bem_conductor"] = bench_bem(K, cs, cw)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline()
