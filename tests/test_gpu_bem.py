@@ -162,3 +162,26 @@ def test_conductor_full_size_sampled():
     e = rel(q[idx], gl["density"])
     print(f"2^21 triangles: {iters} applies, residual {res:.2e}, density error {e:.3e}")
     assert res <= 1e-6 and e < 2e-3
+
+
+def test_green_identity_with_both_layers():
+    # S[du/dn] - B[u] = u/2 on the boundary for u = 1/|y - x0|, x0 outside
+    # (Green's third identity): the device single- and double-layer plans give
+    # the dense operators' collocation residual up to the FMM error
+    import torch
+    V, F = mesh(4)
+    c, _, nrm = bem.geometry(V, F)
+    d = c - np.array([3.0, 0.5, 4.0])
+    r = np.linalg.norm(d, axis=1)
+    u, dn = 1.0 / r, -np.einsum("ij,ij->i", d, nrm) / r ** 3
+    res_dense = bem.dense_operator(V, F, "single") @ dn - bem.dense_operator(V, F, "double") @ u - 0.5 * u
+    K = _k()
+    S = K.Plan.bem(V, F, "single", p=6, eps=1e-8, leaf_size=32, precision="fp64")
+    B = K.Plan.bem(V, F, "double", p=6, eps=1e-8, leaf_size=32, precision="fp64")
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda:0")
+    res = (S.apply(t(dn)) - B.apply(t(u))).cpu().numpy() - 0.5 * u
+    scale = np.linalg.norm(0.5 * u)
+    print(f"residual dense {np.linalg.norm(res_dense) / scale:.3e}, device {np.linalg.norm(res) / scale:.3e}, "
+          f"difference {np.linalg.norm(res - res_dense) / scale:.3e}")
+    assert np.linalg.norm(res - res_dense) / scale < 1e-4
+    assert np.linalg.norm(res) / scale < 2e-3

@@ -215,3 +215,27 @@ def test_planted_mistakes_fail(monkeypatch):
     phi, _ = bem.bem_fmm(V, F, q, 6, 1e-8, 32, layer="double")
     monkeypatch.undo()
     assert np.linalg.norm(phi - B @ q) / np.linalg.norm(B @ q) > 1e-1
+
+
+def green_data(level, x0=(3.0, 0.5, 4.0)):
+    """u = 1/|y - x0| (harmonic inside the ellipsoid, x0 outside) and its
+    outward normal derivative at the centroids."""
+    V, F = mesh(level)
+    c, _, nrm = bem.geometry(V, F)
+    d = c - np.asarray(x0)
+    r = np.linalg.norm(d, axis=1)
+    return V, F, 1.0 / r, -np.einsum("ij,ij->i", d, nrm) / r ** 3
+
+
+def test_green_identity_single_and_double_layer():
+    # Green's third identity on the boundary (n outward): for u harmonic inside,
+    # S[du/dn] - B[u] = u / 2 at every smooth boundary point; the collocation
+    # residual falls with the mesh size (the mixed-condition problems of Sec. 5.2
+    # combine exactly these two operators)
+    res = []
+    for level in (3, 4):
+        V, F, u, dn = green_data(level)
+        r = dense(level, "single") @ dn - dense(level, "double") @ u - 0.5 * u
+        res.append(float(np.linalg.norm(r) / np.linalg.norm(0.5 * u)))
+    print("Green identity residuals", res)
+    assert res[0] < 0.05 and res[1] < res[0] / 1.8
