@@ -26,6 +26,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KIFMM matvec ms + M2L MFMA util at N=1M p=6: SVD-M2L vs dense-M2L, same acc"
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 M2L_KERNEL = "gg_kernel (M2L, compressed, FP32 MFMA)"
 N, P, EPS, LEAF = 1 << 20, 6, 1e-6, 64
@@ -98,6 +100,35 @@ def trace_record(flops):
     ms = rec["avg_ms"]
     return {"avg_launch_ms": ms, "frac": round(flops / (ms * 1e-3) / 1e12 / PEAK_FP32_MFMA_TFLOPS, 4),
             "source": "profiles/m2l_trace_sphere1m_p6.json"}
+
+
+# Bound of every stage of the FP32 plan and the peak it is held against: the
+# point evaluations are FP32 vector arithmetic (11 flop per pair), the
+# translations MFMA products, the permutation a memory copy.
+STAGE_BOUND = {"p2m": ("alu", PEAK_FP32_VECTOR_TFLOPS), "m2m": ("mfma", PEAK_FP32_MFMA_TFLOPS),
+               "m2l": ("mfma", PEAK_FP32_MFMA_TFLOPS), "l2l": ("mfma", PEAK_FP32_MFMA_TFLOPS),
+               "l2p": ("alu", PEAK_FP32_VECTOR_TFLOPS), "p2p": ("alu", PEAK_FP32_VECTOR_TFLOPS),
+               "perm": ("hbm", PEAK_HBM_GBS)}
+
+
+def stage_roofline(rec):
+    """Per stage: time (HIP events of the profiled pass), the algorithmic flops
+    or bytes per apply (kifmm_plan_info), the rate they give and its fraction of
+    the stage's peak (P2P runs on its own stream, overlapping P2M and M2M)."""
+    out = {}
+    for st, ms in rec["stages"].items():
+        bound, peak = STAGE_BOUND[st]
+        if bound == "hbm":
+            work = rec["info"]["bytes"][st]
+            ach = work / (ms * 1e-3) / 1e9
+            unit = "GB/s"
+        else:
+            work = rec["info"]["flops"][st]
+            ach = work / (ms * 1e-3) / 1e12
+            unit = "TFLOP/s"
+        out[st] = {"ms": round(ms, 4), "bound": bound, "work_per_apply": work, "achieved": round(ach, 3),
+                   "peak": peak, "unit": unit, "frac": round(ach / peak, 4)}
+    return out
 
 
 def timed_ms(fn, steps, warmup):
@@ -516,6 +547,7 @@ def main():
         "svd_stage2": stage2_record(res["svd_stage2"]),
         "m2l_mfma_util": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4),
         "stage_ms": {k: round(v, 4) for k, v in svd["stages"].items()},
+        "stage_roofline": stage_roofline(svd),
         "err_vs_fp64_dense_oracle": svd["err"],
         "fmm_err_vs_direct_sum": {"svd_fp32": svd["err_direct"], "dense_fp64": d64["err_direct"]},
         "roofline": {"bound": "mfma", "kernel": M2L_KERNEL,

@@ -105,6 +105,11 @@ typedef struct {
                            and a coarser leaf's points giving a cube's downward check potential,
                            projected by U~^T (S2L). 0 = uniform depth (default). KIFMM_EINVAL with
                            depth > 0 */
+    int fused_leaf;     /* FP32 plans with max_nrhs 1: bit 0 runs S2M (check potentials and S~) as
+                           one launch, bit 1 L2P (T~ and the far field) as one launch, where the
+                           kernels exist (p <= 6 for L2P); other plans ignore it. Default 3
+                           (both); 0 = separate launches (for checks and profiling). The fused
+                           and separate forms compute the same sums in the same order */
 } kifmm_opts_t;
 
 /* Per-stage counters; index with the KIFMM_STAGE_* values. */

@@ -140,6 +140,11 @@ struct kifmm_plan_s {
     // triangle (sorted order, leaf units) its 7-point rule (x, y, z, W), its
     // unit normal, and its vertices and normal for the near-field integrals
     int layer = -1;                      // -1 point sources, 0 single layer, 1 double layer
+    // leaf stages fused with their products (FP32, one right-hand side): the
+    // check potentials with S~ (S2M), T~ with the far field (L2P); leaf_row is
+    // the Q/P row of every leaf (-1: no local expansion)
+    bool fuse_s2m = false, fuse_l2p = false;
+    int32_t* leaf_row = nullptr;
     void *bem_qp = nullptr, *bem_tn = nullptr, *bem_tri = nullptr;
     void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
     void *CX = nullptr, *Psi = nullptr;   // adaptive: per W cube, S2L check potentials and U~ q~
@@ -1319,15 +1324,22 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     }
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 0));
     if (far) {
-        // upward (forward) / L2T^T (adjoint): surface evaluation and the leaf GEMM
-        if (bem)
-            KIFMM_HIP(launch_eval_surface_bem(elt, pl->layer, nleaf, pl->bem_qp, pl->bem_tn, w.sig_s, pl->leaf_ptr,
-                                              pl->surf, n_eq, nep, w.C, st));
-        else
-            KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, w.sig_s, pl->leaf_ptr, pl->surf, n_eq, nep, w.C,
-                                          st));
-        KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->k, pl->ops().n_eq, w.C, nep,
-                            adjoint ? w.P : w.Q, kp, R, 0, st));
+        // upward (forward) / L2T^T (adjoint): surface evaluation and the leaf
+        // GEMM, in one launch when the fused kernel exists for this plan
+        if (!bem && pl->fuse_s2m) {
+            KIFMM_HIP(launch_s2m_fused(nleaf, pl->pts, w.sig_s, pl->leaf_ptr, pl->surf, n_eq, nep,
+                                       adjoint ? pl->TopT : pl->Sop, kp, pl->leaf_row, 1.0 / kFourPi,
+                                       adjoint ? w.P : w.Q, kp, st));
+        } else {
+            if (bem)
+                KIFMM_HIP(launch_eval_surface_bem(elt, pl->layer, nleaf, pl->bem_qp, pl->bem_tn, w.sig_s,
+                                                  pl->leaf_ptr, pl->surf, n_eq, nep, w.C, st));
+            else
+                KIFMM_HIP(launch_eval_surface(elt, R, nleaf, pl->pts, w.sig_s, pl->leaf_ptr, pl->surf, n_eq, nep,
+                                              w.C, st));
+            KIFMM_HIP(launch_gg(pl->d_leafup, elt, adjoint ? pl->TopT : pl->Sop, MBk, KPe, pl->k, n_eq, w.C, nep,
+                                adjoint ? w.P : w.Q, kp, R, 0, st));
+        }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 0));
@@ -1384,37 +1396,52 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     }
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_L2P, 0));
+    // L2P: the T~ product and the far field at the points in one launch when
+    // the fused kernel exists for this plan (else the product into E, then the
+    // far-field evaluation)
+    const bool fl2p = far && pl->fuse_l2p;
+    auto l2p = [&]() -> hipError_t {
+        if (fl2p)
+            return launch_l2p_fused(nleaf, pl->pts, pl->leaf_ptr, pl->leaf_row, adjoint ? pl->SopT : pl->Top, kp, nep,
+                                    adjoint ? w.Q : w.P, pl->surf, n_eq, 1.0 / kFourPi, pl->perm, out, st);
+        return launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
+                                   pl->near_leaf, pl->near_code, lev, lsc, w.E, pl->surf, n_eq, nep, near_scale,
+                                   1.0 / kFourPi, pl->perm, out, ld, nrhs, st);
+    };
     if (far) {
-        if (!adjoint)
-            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, pl->ops().n_eq, pl->k, w.P, kp, w.E, nep, R, 0, st));
-        else
-            KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, pl->ops().n_eq, pl->k, w.Q, kp, w.E, nep, R, 0, st));
+        if (!fl2p) {
+            if (!adjoint)
+                KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->Top, MBe, KPk, n_eq, pl->k, w.P, kp, w.E, nep, R, 0, st));
+            else
+                KIFMM_HIP(launch_gg(pl->d_leafdown, elt, pl->SopT, MBe, KPk, n_eq, pl->k, w.Q, kp, w.E, nep, R, 0, st));
+        }
         if (fork) {
             // far field at the points (L2T), added to the near field
             KIFMM_HIP(hipStreamWaitEvent(st, pl->ev_join, 0));
-            KIFMM_HIP(launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                          pl->near_leaf, pl->near_code, lev, lsc, w.E, pl->surf, n_eq, nep,
-                                          near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
+            KIFMM_HIP(l2p());
             KIFMM_HIP(m2t_eval());
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_L2P, 1));
-    if (!fork && bem) {
-        // BEM: the near-field integrals, then the far field added
+    if (!fork) {
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
-        KIFMM_HIP(launch_eval_near_bem(elt, pl->layer, nleaf, pl->pts, pl->bem_tri, w.sig_s, pl->leaf_ptr,
-                                       pl->near_ptr, pl->near_leaf, pl->near_code, bem_scale, pl->perm, out, st));
-        if (far)
-            KIFMM_HIP(launch_eval_targets(2, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                          pl->near_leaf, pl->near_code, lev, lsc, w.E, pl->surf, n_eq, nep,
+        if (bem) {
+            // BEM: the near-field integrals, then the far field added
+            KIFMM_HIP(launch_eval_near_bem(elt, pl->layer, nleaf, pl->pts, pl->bem_tri, w.sig_s, pl->leaf_ptr,
+                                           pl->near_ptr, pl->near_leaf, pl->near_code, bem_scale, pl->perm, out, st));
+            if (far) KIFMM_HIP(l2p());
+        } else if (fl2p) {
+            // the near field, then the fused L2P added
+            KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
+                                          pl->near_leaf, pl->near_code, lev, lsc, nullptr, pl->surf, n_eq, nep,
                                           near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
-        KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
-    } else if (!fork) {
-        // near field and (when there is one) far field in one kernel
-        KIFMM_HIP(mark(KIFMM_STAGE_P2P, 0));
-        KIFMM_HIP(launch_eval_targets(3, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                      pl->near_leaf, pl->near_code, lev, lsc, far ? w.E : nullptr, pl->surf,
-                                      n_eq, nep, near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
+            KIFMM_HIP(l2p());
+        } else {
+            // near field and (when there is one) far field in one kernel
+            KIFMM_HIP(launch_eval_targets(3, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
+                                          pl->near_leaf, pl->near_code, lev, lsc, far ? w.E : nullptr, pl->surf,
+                                          n_eq, nep, near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, st));
+        }
         KIFMM_HIP(m2t_eval());
         KIFMM_HIP(mark(KIFMM_STAGE_P2P, 1));
     }
@@ -1655,6 +1682,21 @@ int build_fused_t(kifmm_group_s* g) {
         fp->CX = up.zeros(fp->w_cube_box.size() * R * fp->nep * elt);
         fp->Psi = up.zeros(fp->w_cube_box.size() * R * fp->nep * elt);
     }
+    if (D >= 2) {
+        std::vector<int32_t> rows;
+        for (int i = 0; i < np; ++i) {
+            const HostTree& t = ps[i]->tree;
+            for (int64_t e = 0; e < t.n_leaf(); ++e) {
+                int64_t r = -1;
+                if (t.depth >= 2) r = t.adaptive ? (t.leaf_level[e] >= 2 ? t.leaf_box[e] : -1) : t.level_begin[t.depth] + e;
+                rows.push_back(r < 0 ? -1 : (int32_t)(r + bx[i]));
+            }
+        }
+        fp->leaf_row = (int32_t*)up.put(rows);
+        const bool ok = fp->elt == 4 && fp->R == 1 && p0->opts.fused_leaf;
+        fp->fuse_s2m = ok && (p0->opts.fused_leaf & 1) && s2m_fused_supported(fp->nep, fp->kp);
+        fp->fuse_l2p = ok && (p0->opts.fused_leaf & 2) && l2p_fused_supported(fp->nep, fp->kp);
+    }
     g->sig_u = up.zeros((size_t)pt[np] * elt);
     g->out_u = up.zeros((size_t)pt[np] * elt);
     if (up.err == KIFMM_OK &&
@@ -1728,6 +1770,7 @@ int kifmm_opts_default(kifmm_opts_t* o) {
     o->mem_limit = 0;
     o->tile_targets = 0;
     o->m2l_shape = -1;
+    o->fused_leaf = 3;
     return KIFMM_OK;
 }
 
@@ -1757,6 +1800,7 @@ static int plan_build(const double* points, int64_t n, int p, double eps, int le
     if (o.c2 > 0.0 && (o.dense_m2l || o.precision == KIFMM_BF16X3))
         return fail(KIFMM_EINVAL, "c2 > 0 (stage-2 low rank) needs compressed operators in FP32 or FP64");
     if (o.adaptive != 0 && o.adaptive != 1) return fail(KIFMM_EINVAL, "adaptive must be 0 or 1");
+    if (o.fused_leaf < 0 || o.fused_leaf > 3) return fail(KIFMM_EINVAL, "fused_leaf must be in [0, 3]");
     if (o.adaptive && o.depth > 0) return fail(KIFMM_EINVAL, "adaptive trees take no forced depth (opts.depth)");
     if (bem && (o.adaptive || o.max_nrhs != 1))
         return fail(KIFMM_EINVAL, "BEM plans take uniform trees and one right-hand side (adaptive = 0, max_nrhs = 1)");
@@ -1866,6 +1910,17 @@ static int plan_build(const double* points, int64_t n, int p, double eps, int le
                 upload_bem<float>(pl, up, *bem);
             else
                 upload_bem<double>(pl, up, *bem);
+        }
+        if (up.err == KIFMM_OK && t.depth >= 2) {
+            // the Q/P row of every leaf for the fused leaf kernels
+            std::vector<int32_t> rows(t.n_leaf());
+            for (int64_t e = 0; e < t.n_leaf(); ++e)
+                rows[e] = t.adaptive ? (t.leaf_level[e] >= 2 ? t.leaf_box[e] : -1)
+                                     : (int32_t)(t.level_begin[t.depth] + e);
+            pl->leaf_row = (int32_t*)up.put(rows);
+            const bool ok = pl->elt == 4 && pl->R == 1 && o.fused_leaf;
+            pl->fuse_s2m = ok && (o.fused_leaf & 1) && !bem && s2m_fused_supported(pl->nep, pl->kp);
+            pl->fuse_l2p = ok && (o.fused_leaf & 2) && l2p_fused_supported(pl->nep, pl->kp);
         }
         if (up.err == KIFMM_OK &&
             (hipStreamCreateWithFlags(&pl->near_stream, hipStreamNonBlocking) != hipSuccess ||

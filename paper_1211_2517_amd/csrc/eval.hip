@@ -719,6 +719,208 @@ __global__ void __launch_bounds__(256) eval_near_bem_kernel(
     }
 }
 
+// ------------------------------------------------------------------------
+// Leaf stages fused with their reduced-operator products (FP32 plans, one
+// right-hand side). The products use the FP32 16x16x4 MFMA: lane (j, g)
+// supplies A[j][4 g + e] and B[4 g + e][j] of each K-step and holds the
+// output rows 4 g + q of column j.
+typedef float fv4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ fv4 leaf_mfma(float a, float b, fv4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// S2M: the check potentials of LB leaves on the (3-2d) surface (one wave per
+// leaf in turn, as eval_surface_kernel) are kept in LDS as the columns of
+// C (KDIM x LB), then Y[leaf_row[leaf]] = scale * A C[leaf] for the k_pad rows
+// of A (the reduced S~, or T~^T in the adjoint; row-major, lda = KDIM).
+// Leaves with leaf_row < 0 are computed and not stored.
+template <int KP16>
+__global__ void __launch_bounds__(256) s2m_fused_kernel(int64_t n_leaf, const P4<float>* __restrict__ pts,
+                                                        const float* __restrict__ sig,
+                                                        const int32_t* __restrict__ leaf_ptr,
+                                                        const float* __restrict__ surf, int n_eq,
+                                                        const float* __restrict__ A, int MB,
+                                                        const int32_t* __restrict__ leaf_row, float scale,
+                                                        float* __restrict__ Y, int ldy) {
+    constexpr int LB = 32, WPB = 4, CAP = 64;
+    constexpr int KDIM = KP16 * 16, LDB = KDIM + 4;
+    constexpr int NA = (KDIM + 63) / 64;
+    __shared__ P4<float> sp[WPB][CAP];
+    __shared__ __align__(16) float cs[LB * LDB];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t l0 = (int64_t)blockIdx.x * LB;
+    const int nl = (int)min((int64_t)LB, n_leaf - l0);
+    float sx[NA], sy[NA], sz[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+        const int a = k * 64 + lane;
+        const bool ok = a < n_eq;
+        sx[k] = ok ? surf[3 * a] : 0.0f;
+        sy[k] = ok ? surf[3 * a + 1] : 0.0f;
+        sz[k] = ok ? surf[3 * a + 2] : 0.0f;
+    }
+    P4<float>* st = sp[wave];
+    for (int ll = wave; ll < LB; ll += WPB) {
+        float acc[NA];
+#pragma unroll
+        for (int k = 0; k < NA; ++k) acc[k] = 0.0f;
+        if (ll < nl) {
+            const int p0 = leaf_ptr[l0 + ll], p1 = leaf_ptr[l0 + ll + 1];
+            for (int base = p0; base < p1; base += CAP) {
+                const int cnt = min(CAP, p1 - base);
+                __builtin_amdgcn_wave_barrier();
+                if (lane < cnt) {
+                    const P4<float> v = pts[base + lane];
+                    st[lane] = P4<float>{v.x, v.y, v.z, sig[base + lane]};
+                }
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll 2
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const P4<float> f = st[jj];
+#pragma unroll
+                    for (int k = 0; k < NA; ++k) {
+                        const float dx = sx[k] - f.x, dy = sy[k] - f.y, dz = sz[k] - f.z;
+                        acc[k] += f.w * rsq(dx * dx + dy * dy + dz * dz);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NA; ++k) {
+            const int a = k * 64 + lane;
+            if (a < KDIM) cs[ll * LDB + a] = (a < n_eq && ll < nl) ? acc[k] : 0.0f;
+        }
+    }
+    __syncthreads();
+    const int j = lane & 15, grp = lane >> 4;
+    int orow[LB / 16];
+#pragma unroll
+    for (int b = 0; b < LB / 16; ++b) {
+        const int c = b * 16 + j;
+        orow[b] = c < nl ? leaf_row[l0 + c] : -1;
+    }
+    for (int blk = wave; blk < MB; blk += WPB) {
+        fv4 a[KP16];
+        const float* ar = A + (int64_t)(blk * 16 + j) * KDIM + 4 * grp;
+#pragma unroll
+        for (int t = 0; t < KP16; ++t) a[t] = *reinterpret_cast<const fv4*>(ar + 16 * t);
+#pragma unroll
+        for (int cb = 0; cb < LB / 16; ++cb) {
+            if (cb * 16 >= nl) break;
+            fv4 d0 = fv4{0, 0, 0, 0}, d1 = fv4{0, 0, 0, 0};
+            const float* bc = cs + (cb * 16 + j) * LDB + 4 * grp;
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) {
+                const fv4 bv = *reinterpret_cast<const fv4*>(bc + 16 * t);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (t & 1)
+                        d1 = leaf_mfma(a[t][e], bv[e], d1);
+                    else
+                        d0 = leaf_mfma(a[t][e], bv[e], d0);
+                }
+            }
+            const int o = orow[cb];
+            if (o >= 0) {
+                float* yp = Y + (int64_t)o * ldy + blk * 16;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) yp[4 * grp + q] = scale * (d0[q] + d1[q]);
+            }
+        }
+    }
+}
+
+// L2P: E (the leaves' downward equivalent densities) of LB leaves on MFMA,
+// E[leaf] = A X[leaf_row[leaf]] (A = T~, or S~^T in the adjoint: NR16 * 16
+// rows of K = KP16 * 16; X rows of ldx), kept in LDS, then the far field at
+// each leaf's points (one wave per leaf in turn, the surface and E staged as
+// 4-vectors) added to out: out[perm[i]] += far_scale * sum_a E_a / |u_i - s_a|.
+// Leaves with leaf_row < 0 get no far field.
+template <int KP16, int NR16, int LB>
+__global__ void __launch_bounds__(256) l2p_fused_kernel(int64_t n_leaf, const P4<float>* __restrict__ pts,
+                                                        const int32_t* __restrict__ leaf_ptr,
+                                                        const int32_t* __restrict__ leaf_row,
+                                                        const float* __restrict__ A,
+                                                        const float* __restrict__ X, int ldx,
+                                                        const float* __restrict__ surf, int n_eq, float far_scale,
+                                                        const int32_t* __restrict__ perm, float* __restrict__ out) {
+    constexpr int WPB = 4;
+    constexpr int KDIM = KP16 * 16, LDB = KDIM + 4;
+    constexpr int NROW = NR16 * 16, LDE = NROW + 4;
+    constexpr int BB = LB * LDB, FS = WPB * NROW * 4;
+    __shared__ __align__(16) float xs[BB > FS ? BB : FS];   // gathered X columns, then the staged surfaces
+    __shared__ __align__(16) float es[LB * LDE];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t l0 = (int64_t)blockIdx.x * LB;
+    const int nl = (int)min((int64_t)LB, n_leaf - l0);
+    for (int f = tid; f < LB * (KDIM / 4); f += 256) {
+        const int c = f / (KDIM / 4), part = 4 * (f - c * (KDIM / 4));
+        const int r = c < nl ? leaf_row[l0 + c] : -1;
+        fv4 v = fv4{0, 0, 0, 0};
+        if (r >= 0) v = *reinterpret_cast<const fv4*>(X + (int64_t)r * ldx + part);
+        *reinterpret_cast<fv4*>(xs + c * LDB + part) = v;
+    }
+    __syncthreads();
+    const int j = lane & 15, grp = lane >> 4;
+    for (int blk = wave; blk < NR16; blk += WPB) {
+        fv4 a[KP16];
+        const float* ar = A + (int64_t)(blk * 16 + j) * KDIM + 4 * grp;
+#pragma unroll
+        for (int t = 0; t < KP16; ++t) a[t] = *reinterpret_cast<const fv4*>(ar + 16 * t);
+#pragma unroll
+        for (int cb = 0; cb < LB / 16; ++cb) {
+            fv4 d0 = fv4{0, 0, 0, 0}, d1 = fv4{0, 0, 0, 0};
+            const float* bc = xs + (cb * 16 + j) * LDB + 4 * grp;
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) {
+                const fv4 bv = *reinterpret_cast<const fv4*>(bc + 16 * t);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (t & 1)
+                        d1 = leaf_mfma(a[t][e], bv[e], d1);
+                    else
+                        d0 = leaf_mfma(a[t][e], bv[e], d0);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) es[(cb * 16 + j) * LDE + blk * 16 + 4 * grp + q] = d0[q] + d1[q];
+        }
+    }
+    __syncthreads();
+    P4<float>* fs = reinterpret_cast<P4<float>*>(xs) + wave * NROW;
+    for (int ll = wave; ll < nl; ll += WPB) {
+        if (leaf_row[l0 + ll] < 0) continue;
+        const int p0 = leaf_ptr[l0 + ll];
+        const int ne = leaf_ptr[l0 + ll + 1] - p0;
+        __builtin_amdgcn_wave_barrier();
+        for (int a = lane; a < n_eq; a += 64)
+            fs[a] = P4<float>{surf[3 * a], surf[3 * a + 1], surf[3 * a + 2], es[ll * LDE + a]};
+        __builtin_amdgcn_wave_barrier();
+        int lpt = 64;
+        while (lpt > 1 && (64 / lpt) < ne) lpt >>= 1;
+        const int tpr = 64 / lpt;
+        const int sub = lane & (lpt - 1);
+        for (int tb = 0; tb < ne; tb += tpr) {
+            const int tl = tb + lane / lpt;
+            const bool valid = tl < ne;
+            const int i = p0 + (valid ? tl : 0);
+            const P4<float> ui = pts[i];
+            float far = 0.0f;
+#pragma unroll 4
+            for (int a = sub; a < n_eq; a += lpt) {
+                const P4<float> f = fs[a];
+                const float dx = ui.x - f.x, dy = ui.y - f.y, dz = ui.z - f.z;
+                far += f.w * rsq(dx * dx + dy * dy + dz * dz);
+            }
+            for (int off = lpt >> 1; off > 0; off >>= 1) far += __shfl_xor(far, off);
+            if (valid && sub == 0) out[perm[i]] += far_scale * far;
+        }
+    }
+}
+
 // Vectors of several plans joined into one (gather) and split back
 // (scatter): element i of the joined vector belongs to segment s with
 // off[s] <= i < off[s+1], at index i - off[s] of that segment's pointer.
@@ -910,6 +1112,86 @@ hipError_t launch_eval_near_bem(int elt, int layer, int64_t n_leaf, const void* 
     }
 #undef KIFMM_NB
     return hipGetLastError();
+}
+
+namespace {
+
+template <int KP16>
+hipError_t s2m_fused_t(int64_t n_leaf, const void* pts, const void* sig_s, const int32_t* leaf_ptr, const void* surf,
+                       int n_eq, const void* A, int kp, const int32_t* leaf_row, double scale, void* Y, int ldy,
+                       hipStream_t st) {
+    const dim3 grid((unsigned)((n_leaf + 31) / 32));
+    hipLaunchKernelGGL((s2m_fused_kernel<KP16>), grid, dim3(256), 0, st, n_leaf, (const P4<float>*)pts,
+                       (const float*)sig_s, leaf_ptr, (const float*)surf, n_eq, (const float*)A, kp / 16, leaf_row,
+                       (float)scale, (float*)Y, ldy);
+    return hipGetLastError();
+}
+
+template <int KP16, int NR16>
+hipError_t l2p_fused_t(int64_t n_leaf, const void* pts, const int32_t* leaf_ptr, const int32_t* leaf_row,
+                       const void* A, const void* X, int kp, const void* surf, int n_eq, double far_scale,
+                       const int32_t* perm, void* out, hipStream_t st) {
+    constexpr int LB = 16;   // leaves per workgroup: 16 keeps 8 workgroups (32 waves) on a CU
+    const dim3 grid((unsigned)((n_leaf + LB - 1) / LB));
+    hipLaunchKernelGGL((l2p_fused_kernel<KP16, NR16, LB>), grid, dim3(256), 0, st, n_leaf, (const P4<float>*)pts,
+                       leaf_ptr, leaf_row, (const float*)A, (const float*)X, kp, (const float*)surf, n_eq,
+                       (float)far_scale, perm, (float*)out);
+    return hipGetLastError();
+}
+
+template <int NR16>
+hipError_t l2p_fused_nr(int kp16, int64_t n_leaf, const void* pts, const int32_t* leaf_ptr, const int32_t* leaf_row,
+                        const void* A, const void* X, int kp, const void* surf, int n_eq, double far_scale,
+                        const int32_t* perm, void* out, hipStream_t st) {
+#define KIFMM_L2PF(K) \
+    case K: return l2p_fused_t<K, NR16>(n_leaf, pts, leaf_ptr, leaf_row, A, X, kp, surf, n_eq, far_scale, perm, out, st);
+    switch (kp16) {
+        KIFMM_L2PF(1) KIFMM_L2PF(2) KIFMM_L2PF(3) KIFMM_L2PF(4) KIFMM_L2PF(5)
+        KIFMM_L2PF(6) KIFMM_L2PF(7) KIFMM_L2PF(8) KIFMM_L2PF(9) KIFMM_L2PF(10)
+        default: return hipErrorNotSupported;
+    }
+#undef KIFMM_L2PF
+}
+
+}  // namespace
+
+bool s2m_fused_supported(int nep, int kp) {
+    const int r = nep / 16;
+    return nep % 16 == 0 && kp % 16 == 0 && kp <= 19 * 16 &&
+           (r == 1 || r == 2 || r == 4 || r == 7 || r == 10 || r == 14 || r == 19);
+}
+
+bool l2p_fused_supported(int nep, int kp) {
+    const int r = nep / 16;
+    return nep % 16 == 0 && kp % 16 == 0 && kp <= nep && kp / 16 <= 10 && (r == 4 || r == 7 || r == 10);
+}
+
+hipError_t launch_s2m_fused(int64_t n_leaf, const void* pts, const void* sig_s, const int32_t* leaf_ptr,
+                            const void* surf, int n_eq, int nep, const void* A, int kp, const int32_t* leaf_row,
+                            double scale, void* Y, int ldy, hipStream_t st) {
+    if (n_leaf == 0) return hipSuccess;
+    if (nep % 16 || kp % 16 || n_eq > nep || kp > 19 * 16) return hipErrorInvalidValue;
+#define KIFMM_S2MF(K) \
+    case K: return s2m_fused_t<K>(n_leaf, pts, sig_s, leaf_ptr, surf, n_eq, A, kp, leaf_row, scale, Y, ldy, st);
+    switch (nep / 16) {
+        KIFMM_S2MF(1) KIFMM_S2MF(2) KIFMM_S2MF(4) KIFMM_S2MF(7) KIFMM_S2MF(10)
+        KIFMM_S2MF(14) KIFMM_S2MF(19)
+        default: return hipErrorNotSupported;
+    }
+#undef KIFMM_S2MF
+}
+
+hipError_t launch_l2p_fused(int64_t n_leaf, const void* pts, const int32_t* leaf_ptr, const int32_t* leaf_row,
+                            const void* A, int kp, int nep, const void* X, const void* surf, int n_eq,
+                            double far_scale, const int32_t* perm, void* out, hipStream_t st) {
+    if (n_leaf == 0) return hipSuccess;
+    if (nep % 16 || kp % 16 || n_eq > nep || kp > nep) return hipErrorInvalidValue;
+    switch (nep / 16) {
+        case 4: return l2p_fused_nr<4>(kp / 16, n_leaf, pts, leaf_ptr, leaf_row, A, X, kp, surf, n_eq, far_scale, perm, out, st);
+        case 7: return l2p_fused_nr<7>(kp / 16, n_leaf, pts, leaf_ptr, leaf_row, A, X, kp, surf, n_eq, far_scale, perm, out, st);
+        case 10: return l2p_fused_nr<10>(kp / 16, n_leaf, pts, leaf_ptr, leaf_row, A, X, kp, surf, n_eq, far_scale, perm, out, st);
+        default: return hipErrorNotSupported;
+    }
 }
 
 }  // namespace kifmm

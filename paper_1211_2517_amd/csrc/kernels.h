@@ -93,6 +93,24 @@ hipError_t launch_eval_near_bem(int elt, int layer, int64_t n_leaf, const void* 
                                 const int32_t* near_leaf, const int32_t* near_code, double scale,
                                 const int32_t* perm, void* out, hipStream_t st);
 
+// FP32 plans with one right-hand side: S2M in one launch. The check
+// potentials of the leaves (as launch_eval_surface) stay in LDS and
+// Y[leaf_row[e] * ldy + i] = scale * sum_a A[i][a] C_e[a] for i < kp (A: kp x nep
+// row-major, zero past n_eq and k); leaves with leaf_row < 0 are not stored.
+// Whether the fused leaf kernels exist for n_eq padded to nep and k to kp.
+bool s2m_fused_supported(int nep, int kp);
+bool l2p_fused_supported(int nep, int kp);
+hipError_t launch_s2m_fused(int64_t n_leaf, const void* pts, const void* sig_s, const int32_t* leaf_ptr,
+                            const void* surf, int n_eq, int nep, const void* A, int kp, const int32_t* leaf_row,
+                            double scale, void* Y, int ldy, hipStream_t st);
+// FP32 plans with one right-hand side: L2P in one launch. E_e = A X[leaf_row[e]]
+// (A: nep x kp row-major; X rows of kp) stays in LDS and the far field of
+// launch_eval_targets mode 2 is added to out (leaves with leaf_row < 0: none).
+// hipErrorNotSupported for a (kp, nep) pair that has no instance.
+hipError_t launch_l2p_fused(int64_t n_leaf, const void* pts, const int32_t* leaf_ptr, const int32_t* leaf_row,
+                            const void* A, int kp, int nep, const void* X, const void* surf, int n_eq,
+                            double far_scale, const int32_t* perm, void* out, hipStream_t st);
+
 // A joined vector of up to kMaxSegments plans' vectors (passed by value to
 // the kernels): segment s holds elements [off[s], off[s+1]) at ptr[s].
 constexpr int kMaxSegments = 64;
