@@ -983,24 +983,51 @@ void gg_build(GGSched& s, int64_t tgt_row0, int64_t n_tgt, const int32_t* ptr, c
         std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.key < b.key; });
         const size_t first_chunk = s.chunk_cls.size();
         size_t i = 0;
+        std::vector<int32_t> slot(s.cp);
         while (i < items.size()) {
             const int64_t key = items[i].key;
             const int64_t g = key / (NCLASS * 8);
             s.chunk_cls.push_back(cls[items[i].q]);
             s.chunk_scale.push_back(group_scale[g]);
-            int used = 0;
+            size_t e = i;
+            while (e < items.size() && e - i < (size_t)s.cp && items[e].key == key) ++e;
+            const int used = (int)(e - i);
+            // Slot order inside the chunk: the kernels add the products of the
+            // slots of a 16-column block into their target columns of an LDS
+            // accumulator whose column stride is 1 modulo 16 banks' groups of
+            // four words, so a block whose columns are distinct modulo 16 (best:
+            // column = slot mod 16) is free of bank conflicts. Every column has
+            // one slot per chunk, so the order changes no sum.
+            std::fill(slot.begin(), slot.end(), -1);
+            const int nslot = s.rhs == 1 ? (used > 16 ? 32 : 16) : s.cp;
+            if (s.rhs == 1 && s.cp == 32) {
+                std::vector<size_t> rest;
+                for (size_t k = i; k < e; ++k) {
+                    const int r = items[k].col & 15;
+                    if (slot[r] < 0)
+                        slot[r] = (int32_t)k;
+                    else if (nslot == 32 && slot[16 + r] < 0)
+                        slot[16 + r] = (int32_t)k;
+                    else
+                        rest.push_back(k);
+                }
+                size_t f = 0;
+                for (int j = 0; j < nslot && f < rest.size(); ++j)
+                    if (slot[j] < 0) slot[j] = (int32_t)rest[f++];
+            } else {
+                for (int j = 0; j < used; ++j) slot[j] = (int32_t)(i + j);
+            }
             for (int j = 0; j < s.cp; ++j) {
-                if (i < items.size() && items[i].key == key) {
-                    s.chunk_src.push_back(src[items[i].q]);
-                    s.chunk_col.push_back(items[i].col);
-                    ++i;
-                    ++used;
+                if (slot[j] >= 0) {
+                    s.chunk_src.push_back(src[items[slot[j]].q]);
+                    s.chunk_col.push_back(items[slot[j]].col);
                 } else {
                     s.chunk_src.push_back(-1);
                     s.chunk_col.push_back(-1);
                 }
             }
-            s.chunk_nblk.push_back((used * s.rhs + 15) / 16);
+            s.chunk_nblk.push_back(s.rhs == 1 && s.cp == 32 ? nslot / 16 : (used * s.rhs + 15) / 16);
+            i = e;
         }
         // class of the next chunk with a different class, within this tile
         const size_t last = s.chunk_cls.size();
