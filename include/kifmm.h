@@ -110,6 +110,11 @@ typedef struct {
                            kernels exist (p <= 6 for L2P); other plans ignore it. Default 3
                            (both); 0 = separate launches (for checks and profiling). The fused
                            and separate forms compute the same sums in the same order */
+    int m2m_direct;     /* FP32 plans with max_nrhs 1: 1 (default) runs M2M (and the adjoint's L2L^T)
+                           on the levels of at most 3072 parents as one product per parent over its
+                           eight children; 0 = the grouped GEMM on every level, as on the larger
+                           levels and in other plans. The two forms sum in different orders
+                           (results agree to FP32 rounding) */
 } kifmm_opts_t;
 
 /* Per-stage counters; index with the KIFMM_STAGE_* values. */

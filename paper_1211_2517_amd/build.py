@@ -12,7 +12,7 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["linalg.cpp", "plan.cpp"]
-HIP_SOURCES = ["gemm.hip", "eval.hip", "capi.hip", "solve.hip"]
+HIP_SOURCES = ["gemm.hip", "eval.hip", "translate.hip", "capi.hip", "solve.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-ffp-contract=off", "-Wall", "-Wno-unused-result", "-Wno-unused-value"]

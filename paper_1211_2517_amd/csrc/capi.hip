@@ -145,6 +145,13 @@ struct kifmm_plan_s {
     // the Q/P row of every leaf (-1: no local expansion)
     bool fuse_s2m = false, fuse_l2p = false;
     int32_t* leaf_row = nullptr;
+    // M2M by one product per parent (FP32, one right-hand side) on the levels
+    // of at most kM2MDirectMax parents: per level, m2m_n parents (0: the
+    // grouped GEMM of d_up), and at d_m2m their Q rows followed by 8 child
+    // rows each
+    bool m2m_direct = false;
+    std::vector<int32_t> m2m_n;
+    std::vector<int32_t*> d_m2m;
     void *bem_qp = nullptr, *bem_tn = nullptr, *bem_tri = nullptr;
     void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
     void *CX = nullptr, *Psi = nullptr;   // adaptive: per W cube, S2L check potentials and U~ q~
@@ -876,6 +883,42 @@ int m2l_tiles_for(const kifmm_plan_s* pl, int variant, int extra_rounds) {
 
 void build_uniform_passes(kifmm_plan_s* pl, const std::function<int(int64_t)>& level_tile);
 
+// The parents of level l (cubes with at least one child) and their eight
+// child rows (-1: no child), every row offset by off, appended to par / ch.
+void m2m_lists(const HostTree& t, int l, int32_t off, std::vector<int32_t>& par, std::vector<int32_t>& ch) {
+    for (int64_t b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b) {
+        bool any = false;
+        for (int o = 0; o < 8; ++o) any = any || t.box_child[8 * b + o] >= 0;
+        if (!any) continue;
+        par.push_back((int32_t)b + off);
+        for (int o = 0; o < 8; ++o) {
+            const int32_t c = t.box_child[8 * b + o];
+            ch.push_back(c < 0 ? -1 : c + off);
+        }
+    }
+}
+
+// Above this many parents a level's M2M runs as the grouped GEMM, which reads
+// each octant matrix once per tile of up to a few hundred parents; the direct
+// kernel reads it once per 16 parents and only wins where launch latency
+// dominates (measured at p = 6: 6-12 us against 26 us per launch up to about
+// 1200 parents, 32 against 27 us at 4700).
+constexpr int64_t kM2MDirectMax = 3072;
+
+void upload_m2m(kifmm_plan_s* pl, Uploader& up, const std::vector<std::vector<int32_t>>& par,
+                const std::vector<std::vector<int32_t>>& ch) {
+    pl->m2m_n.assign(par.size(), 0);
+    pl->d_m2m.assign(par.size(), nullptr);
+    for (size_t l = 0; l < par.size(); ++l) {
+        if (par[l].empty() || (int64_t)par[l].size() > kM2MDirectMax) continue;
+        std::vector<int32_t> v(par[l]);
+        v.insert(v.end(), ch[l].begin(), ch[l].end());
+        pl->m2m_n[l] = (int32_t)par[l].size();
+        pl->d_m2m[l] = (int32_t*)up.put(v);
+    }
+    pl->m2m_direct = up.err == KIFMM_OK;
+}
+
 // Schedules of the upward and downward passes of an adaptive tree (the M2L
 // schedule is the uniform tree's: every cube of levels >= 2). S2M at the
 // leaves of levels >= 2 (a level's leaves come first among its cubes), M2M
@@ -1344,12 +1387,16 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 0));
     if (far) {
-        if (!adjoint) {
-            for (int l = L - 1; l >= 2; --l)   // M2M
-                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->Mt, MBk, KPk, pl->k, pl->k, w.Q, kp, w.Q, kp, R, 0, st));
-        } else {
-            for (int l = L - 1; l >= 2; --l)   // L2L^T: parents at l from children at l+1
-                KIFMM_HIP(launch_gg(pl->d_up[l], elt, pl->LtT, MBk, KPk, pl->k, pl->k, w.P, kp, w.P, kp, R, 0, st));
+        // M2M (forward) / L2L^T (adjoint): parents at l from children at l+1,
+        // by one product per parent on the levels that have the direct lists
+        const void* A = adjoint ? pl->LtT : pl->Mt;
+        void* X = adjoint ? w.P : w.Q;
+        for (int l = L - 1; l >= 2; --l) {
+            const int32_t n = pl->m2m_direct && l < (int)pl->m2m_n.size() ? pl->m2m_n[l] : 0;
+            if (n > 0)
+                KIFMM_HIP(launch_m2m_direct(n, pl->d_m2m[l], pl->d_m2m[l] + n, A, kp, X, X, st));
+            else
+                KIFMM_HIP(launch_gg(pl->d_up[l], elt, A, MBk, KPk, pl->k, pl->k, X, kp, X, kp, R, 0, st));
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 1));
@@ -1697,6 +1744,13 @@ int build_fused_t(kifmm_group_s* g) {
         fp->fuse_s2m = ok && (p0->opts.fused_leaf & 1) && s2m_fused_supported(fp->nep, fp->kp);
         fp->fuse_l2p = ok && (p0->opts.fused_leaf & 2) && l2p_fused_supported(fp->nep, fp->kp);
     }
+    if (D >= 3 && fp->elt == 4 && fp->R == 1 && p0->opts.m2m_direct && m2m_direct_supported(fp->kp)) {
+        std::vector<std::vector<int32_t>> par(D), ch(D);
+        for (int i = 0; i < np; ++i)
+            for (int l = 2; l < std::min(D, ps[i]->tree.depth); ++l)
+                m2m_lists(ps[i]->tree, l, (int32_t)bx[i], par[l], ch[l]);
+        upload_m2m(fp, up, par, ch);
+    }
     g->sig_u = up.zeros((size_t)pt[np] * elt);
     g->out_u = up.zeros((size_t)pt[np] * elt);
     if (up.err == KIFMM_OK &&
@@ -1771,6 +1825,7 @@ int kifmm_opts_default(kifmm_opts_t* o) {
     o->tile_targets = 0;
     o->m2l_shape = -1;
     o->fused_leaf = 3;
+    o->m2m_direct = 1;
     return KIFMM_OK;
 }
 
@@ -1801,6 +1856,7 @@ static int plan_build(const double* points, int64_t n, int p, double eps, int le
         return fail(KIFMM_EINVAL, "c2 > 0 (stage-2 low rank) needs compressed operators in FP32 or FP64");
     if (o.adaptive != 0 && o.adaptive != 1) return fail(KIFMM_EINVAL, "adaptive must be 0 or 1");
     if (o.fused_leaf < 0 || o.fused_leaf > 3) return fail(KIFMM_EINVAL, "fused_leaf must be in [0, 3]");
+    if (o.m2m_direct != 0 && o.m2m_direct != 1) return fail(KIFMM_EINVAL, "m2m_direct must be 0 or 1");
     if (o.adaptive && o.depth > 0) return fail(KIFMM_EINVAL, "adaptive trees take no forced depth (opts.depth)");
     if (bem && (o.adaptive || o.max_nrhs != 1))
         return fail(KIFMM_EINVAL, "BEM plans take uniform trees and one right-hand side (adaptive = 0, max_nrhs = 1)");
@@ -1921,6 +1977,12 @@ static int plan_build(const double* points, int64_t n, int p, double eps, int le
             const bool ok = pl->elt == 4 && pl->R == 1 && o.fused_leaf;
             pl->fuse_s2m = ok && (o.fused_leaf & 1) && !bem && s2m_fused_supported(pl->nep, pl->kp);
             pl->fuse_l2p = ok && (o.fused_leaf & 2) && l2p_fused_supported(pl->nep, pl->kp);
+        }
+        if (up.err == KIFMM_OK && t.depth >= 3 && pl->elt == 4 && pl->R == 1 && o.m2m_direct &&
+            m2m_direct_supported(pl->kp)) {
+            std::vector<std::vector<int32_t>> par(t.depth), ch(t.depth);
+            for (int l = 2; l < t.depth; ++l) m2m_lists(t, l, 0, par[l], ch[l]);
+            upload_m2m(pl, up, par, ch);
         }
         if (up.err == KIFMM_OK &&
             (hipStreamCreateWithFlags(&pl->near_stream, hipStreamNonBlocking) != hipSuccess ||

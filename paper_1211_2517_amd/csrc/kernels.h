@@ -111,6 +111,14 @@ hipError_t launch_l2p_fused(int64_t n_leaf, const void* pts, const int32_t* leaf
                             const void* A, int kp, int nep, const void* X, const void* surf, int n_eq,
                             double far_scale, const int32_t* perm, void* out, hipStream_t st);
 
+// FP32 M2M with one right-hand side as one product per parent:
+// Y[par_row[i]] = sum_o A_o X[child[8 i + o]] (child -1: absent), A_o the kp x kp
+// blocks of octant o (row-major, consecutive), X and Y rows of kp. For
+// 16 <= kp <= 160 (m2m_direct_supported).
+bool m2m_direct_supported(int kp);
+hipError_t launch_m2m_direct(int n_par, const int32_t* par_row, const int32_t* child, const void* A, int kp,
+                             const void* X, void* Y, hipStream_t st);
+
 // A joined vector of up to kMaxSegments plans' vectors (passed by value to
 // the kernels): segment s holds elements [off[s], off[s+1]) at ptr[s].
 constexpr int kMaxSegments = 64;

@@ -564,3 +564,35 @@ def test_fused_leaf_kernels_match_separate_launches(kind):
     gb.apply([s], [ob])
     torch.cuda.synchronize()
     assert torch.equal(oa, ob) and torch.equal(oa, a.apply(s))
+
+
+@pytest.mark.parametrize("kind", ["sphere", "adaptive", "group"])
+def test_direct_m2m_matches_grouped_gemm(kind):
+    # M2M as one product per parent (opts.m2m_direct) against the grouped GEMM
+    # form: the same products summed in another order, so the results agree
+    # to FP32 rounding, forward and adjoint (L2L^T), on a uniform tree, an
+    # adaptive tree (M2M into split cubes only) and a merged group of plans of
+    # different depths (parent and child rows offset per plan)
+    torch = _torch()
+    K = _k()
+    xs = [sphere(20000)[0]] if kind == "sphere" else [workloads.clustered_points(1500, 2500, 3)]
+    if kind == "group":
+        xs = [sphere(20000)[0], workloads.uniform_cube(3000, 4), workloads.clustered_points(1500, 2500, 3)]
+    mk = lambda x, d: K.Plan(x, p=6, eps=1e-6, leaf_size=32, adaptive=(kind == "adaptive"), m2m_direct=d)
+    a, b = [mk(x, True) for x in xs], [mk(x, False) for x in xs]
+    sig = [torch.tensor(workloads.uniform_density(x.shape[0], 11 + i), dtype=torch.float32, device="cuda:0")
+           for i, x in enumerate(xs)]
+    mr = lambda u, v: float((u - v).abs().max() / v.abs().max())
+    if kind == "group":
+        assert len({p.info()["depth"] for p in a}) > 1
+        ga, gb = K.Group(a), K.Group(b)
+        oa, ob = [torch.empty_like(s) for s in sig], [torch.empty_like(s) for s in sig]
+        ga.apply(sig, oa)
+        gb.apply(sig, ob)
+        torch.cuda.synchronize()
+        for u, v in zip(oa, ob):
+            assert mr(u, v) < 2e-6
+        return
+    assert a[0].info()["depth"] >= 4
+    assert mr(a[0].apply(sig[0]), b[0].apply(sig[0])) < 2e-6
+    assert mr(a[0].apply_adjoint(sig[0]), b[0].apply_adjoint(sig[0])) < 2e-6
