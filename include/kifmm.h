@@ -110,11 +110,12 @@ typedef struct {
                            kernels exist (p <= 6 for L2P); other plans ignore it. Default 3
                            (both); 0 = separate launches (for checks and profiling). The fused
                            and separate forms compute the same sums in the same order */
-    int m2m_direct;     /* FP32 plans with max_nrhs 1: 1 (default) runs M2M (and the adjoint's L2L^T)
-                           on the levels of at most 3072 parents as one product per parent over its
-                           eight children; 0 = the grouped GEMM on every level, as on the larger
-                           levels and in other plans. The two forms sum in different orders
-                           (results agree to FP32 rounding) */
+    int direct_passes;  /* FP32 plans with max_nrhs 1: 1 (default) runs M2M (the adjoint: L2L^T) on
+                           the levels of at most 3072 parents as one product per parent over its
+                           eight children, and L2L (the adjoint: M2M^T) by segments of one octant
+                           with the operator rows held in registers; 0 = the grouped GEMM for both,
+                           as in other plans. The forms sum in different orders (results agree to
+                           FP32 rounding) */
 } kifmm_opts_t;
 
 /* Per-stage counters; index with the KIFMM_STAGE_* values. */

@@ -152,6 +152,13 @@ struct kifmm_plan_s {
     bool m2m_direct = false;
     std::vector<int32_t> m2m_n;
     std::vector<int32_t*> d_m2m;
+    // L2L in the direct form (FP32, one right-hand side): per level, dd_nseg
+    // segments of one octant of up to 16 * dd_ncb children; d_dd holds the
+    // segments (class, first item, items), the items' child rows, then their
+    // parent rows (dd_nitem items)
+    bool down_direct = false;
+    std::vector<int32_t> dd_nseg, dd_ncb, dd_nitem;
+    std::vector<int32_t*> d_dd;
     void *bem_qp = nullptr, *bem_tn = nullptr, *bem_tri = nullptr;
     void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
     void *CX = nullptr, *Psi = nullptr;   // adaptive: per W cube, S2L check potentials and U~ q~
@@ -919,6 +926,64 @@ void upload_m2m(kifmm_plan_s* pl, Uploader& up, const std::vector<std::vector<in
     pl->m2m_direct = up.err == KIFMM_OK;
 }
 
+// One L2L product of the direct form: child row tgt from parent row src with
+// the octant class cls.
+struct DownItem {
+    int32_t cls, tgt, src;
+};
+
+// The L2L items of level l (every cube of the level from its parent), rows
+// offset by off, appended to v.
+void down_items(const HostTree& t, int l, int32_t off, std::vector<DownItem>& v) {
+    for (int64_t b = t.level_begin[l]; b < t.level_begin[l + 1]; ++b)
+        v.push_back({(int32_t)(t.box_key[b] & 7), (int32_t)b + off, t.box_parent[b] + off});
+}
+
+// Segments of the direct L2L kernel per level: the items sorted by class
+// (stable: Morton order within a class), cut into runs of one class of up to
+// 16 * nb items, nb (at most kDownMaxBlocks) the fewest 16-column blocks per
+// segment that let every segment of the level be resident at once (two
+// workgroups per CU up to k_pad = 144, one above, by the kernel's register
+// count): a second, partial round of workgroups would double the launch, and
+// longer segments amortise the operator rows a workgroup loads.
+void upload_down(kifmm_plan_s* pl, Uploader& up, std::vector<std::vector<DownItem>>& items) {
+    const size_t nl = items.size();
+    pl->dd_nseg.assign(nl, 0);
+    pl->dd_ncb.assign(nl, 1);
+    pl->dd_nitem.assign(nl, 0);
+    pl->d_dd.assign(nl, nullptr);
+    for (size_t l = 0; l < nl; ++l) {
+        std::vector<DownItem>& v = items[l];
+        if (v.empty()) continue;
+        std::stable_sort(v.begin(), v.end(), [](const DownItem& a, const DownItem& b) { return a.cls < b.cls; });
+        int64_t nblk = 0;
+        for (size_t i = 0; i < v.size();) {
+            size_t e = i;
+            while (e < v.size() && v[e].cls == v[i].cls) ++e;
+            nblk += (int64_t)(e - i + 15) / 16;
+            i = e;
+        }
+        const int64_t slots = (int64_t)pl->num_cu * (pl->kp <= 144 ? 2 : 1);
+        // the class runs add up to 8 partial segments
+        const int ncb = (int)std::min<int64_t>(kDownMaxBlocks, std::max<int64_t>(1, (nblk + slots - 9) / (slots - 8)));
+        std::vector<int32_t> segs;
+        for (size_t i = 0; i < v.size();) {
+            size_t e = i;
+            while (e < v.size() && v[e].cls == v[i].cls && e - i < (size_t)16 * ncb) ++e;
+            segs.insert(segs.end(), {v[i].cls, (int32_t)i, (int32_t)(e - i)});
+            i = e;
+        }
+        std::vector<int32_t> buf(segs);
+        for (const DownItem& d : v) buf.push_back(d.tgt);
+        for (const DownItem& d : v) buf.push_back(d.src);
+        pl->dd_nseg[l] = (int32_t)(segs.size() / 3);
+        pl->dd_ncb[l] = ncb;
+        pl->dd_nitem[l] = (int32_t)v.size();
+        pl->d_dd[l] = (int32_t*)up.put(buf);
+    }
+    pl->down_direct = up.err == KIFMM_OK;
+}
+
 // Schedules of the upward and downward passes of an adaptive tree (the M2L
 // schedule is the uniform tree's: every cube of levels >= 2). S2M at the
 // leaves of levels >= 2 (a level's leaves come first among its cubes), M2M
@@ -983,8 +1048,9 @@ void build_adaptive_passes(kifmm_plan_s* pl, const std::function<int(int64_t)>& 
             cls[b] = (int32_t)(t.box_key[b0 + b] & 7);
         }
         ptr[nb] = (int32_t)nb;
-        gg_build(pl->h_down[l], b0, nb, ptr.data(), src.data(), cls.data(), nullptr, one,
-                 uniform_cuts(nb, level_tile(nb)));
+        // one tile: the direct form runs a workgroup per chunk, so the chunks
+        // of a level are best full (32 children of one octant each)
+        gg_build(pl->h_down[l], b0, nb, ptr.data(), src.data(), cls.data(), nullptr, one, uniform_cuts(nb, nb));
     }
     // W cubes: Psi = U~ q~ (one product each) and P += U~^T CX / (4 pi r_l)
     pl->w_cube_box.clear();
@@ -1106,8 +1172,9 @@ void build_uniform_passes(kifmm_plan_s* pl, const std::function<int(int64_t)>& l
             cls[b] = (int32_t)(t.box_key[b0 + b] & 7);
         }
         ptr[nb] = (int32_t)nb;
-        gg_build(pl->h_down[l], b0, nb, ptr.data(), src.data(), cls.data(), nullptr, one,
-                 uniform_cuts(nb, level_tile(nb)));
+        // one pair per target (the direct form: one workgroup per chunk), so
+        // one tile per level, whose chunks are full: 32 children of one octant
+        gg_build(pl->h_down[l], b0, nb, ptr.data(), src.data(), cls.data(), nullptr, one, uniform_cuts(nb, nb));
     }
 }
 
@@ -1433,12 +1500,18 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 1));
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 0));
     if (far) {
-        if (!adjoint) {
-            for (int l = 3; l <= L; ++l)       // L2L
-                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->Lt, MBk, KPk, pl->k, pl->k, w.P, kp, w.P, kp, R, 1, st));
-        } else {
-            for (int l = 3; l <= L; ++l)       // M2M^T: children at l from parents at l-1
-                KIFMM_HIP(launch_gg(pl->d_down[l], elt, pl->MtT, MBk, KPk, pl->k, pl->k, w.Q, kp, w.Q, kp, R, 1, st));
+        // L2L (forward) / M2M^T (adjoint): children at l from parents at l-1,
+        // one product each, added
+        const void* A = adjoint ? pl->MtT : pl->Lt;
+        void* X = adjoint ? w.Q : w.P;
+        for (int l = 3; l <= L; ++l) {
+            const int32_t ns = pl->down_direct && l < (int)pl->dd_nseg.size() ? pl->dd_nseg[l] : 0;
+            if (ns > 0) {
+                const int32_t* d = pl->d_dd[l];
+                KIFMM_HIP(launch_down_direct(ns, d, d + 3 * ns, d + 3 * ns + pl->dd_nitem[l], A, kp, X, X, st));
+            } else {
+                KIFMM_HIP(launch_gg(pl->d_down[l], elt, A, MBk, KPk, pl->k, pl->k, X, kp, X, kp, R, 1, st));
+            }
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 1));
@@ -1744,12 +1817,16 @@ int build_fused_t(kifmm_group_s* g) {
         fp->fuse_s2m = ok && (p0->opts.fused_leaf & 1) && s2m_fused_supported(fp->nep, fp->kp);
         fp->fuse_l2p = ok && (p0->opts.fused_leaf & 2) && l2p_fused_supported(fp->nep, fp->kp);
     }
-    if (D >= 3 && fp->elt == 4 && fp->R == 1 && p0->opts.m2m_direct && m2m_direct_supported(fp->kp)) {
+    if (D >= 3 && fp->elt == 4 && fp->R == 1 && p0->opts.direct_passes && m2m_direct_supported(fp->kp)) {
         std::vector<std::vector<int32_t>> par(D), ch(D);
         for (int i = 0; i < np; ++i)
             for (int l = 2; l < std::min(D, ps[i]->tree.depth); ++l)
                 m2m_lists(ps[i]->tree, l, (int32_t)bx[i], par[l], ch[l]);
         upload_m2m(fp, up, par, ch);
+        std::vector<std::vector<DownItem>> dn(D + 1);
+        for (int i = 0; i < np; ++i)
+            for (int l = 3; l <= ps[i]->tree.depth; ++l) down_items(ps[i]->tree, l, (int32_t)bx[i], dn[l]);
+        upload_down(fp, up, dn);
     }
     g->sig_u = up.zeros((size_t)pt[np] * elt);
     g->out_u = up.zeros((size_t)pt[np] * elt);
@@ -1825,7 +1902,7 @@ int kifmm_opts_default(kifmm_opts_t* o) {
     o->tile_targets = 0;
     o->m2l_shape = -1;
     o->fused_leaf = 3;
-    o->m2m_direct = 1;
+    o->direct_passes = 1;
     return KIFMM_OK;
 }
 
@@ -1856,7 +1933,7 @@ static int plan_build(const double* points, int64_t n, int p, double eps, int le
         return fail(KIFMM_EINVAL, "c2 > 0 (stage-2 low rank) needs compressed operators in FP32 or FP64");
     if (o.adaptive != 0 && o.adaptive != 1) return fail(KIFMM_EINVAL, "adaptive must be 0 or 1");
     if (o.fused_leaf < 0 || o.fused_leaf > 3) return fail(KIFMM_EINVAL, "fused_leaf must be in [0, 3]");
-    if (o.m2m_direct != 0 && o.m2m_direct != 1) return fail(KIFMM_EINVAL, "m2m_direct must be 0 or 1");
+    if (o.direct_passes != 0 && o.direct_passes != 1) return fail(KIFMM_EINVAL, "direct_passes must be 0 or 1");
     if (o.adaptive && o.depth > 0) return fail(KIFMM_EINVAL, "adaptive trees take no forced depth (opts.depth)");
     if (bem && (o.adaptive || o.max_nrhs != 1))
         return fail(KIFMM_EINVAL, "BEM plans take uniform trees and one right-hand side (adaptive = 0, max_nrhs = 1)");
@@ -1978,11 +2055,14 @@ static int plan_build(const double* points, int64_t n, int p, double eps, int le
             pl->fuse_s2m = ok && (o.fused_leaf & 1) && !bem && s2m_fused_supported(pl->nep, pl->kp);
             pl->fuse_l2p = ok && (o.fused_leaf & 2) && l2p_fused_supported(pl->nep, pl->kp);
         }
-        if (up.err == KIFMM_OK && t.depth >= 3 && pl->elt == 4 && pl->R == 1 && o.m2m_direct &&
+        if (up.err == KIFMM_OK && t.depth >= 3 && pl->elt == 4 && pl->R == 1 && o.direct_passes &&
             m2m_direct_supported(pl->kp)) {
             std::vector<std::vector<int32_t>> par(t.depth), ch(t.depth);
             for (int l = 2; l < t.depth; ++l) m2m_lists(t, l, 0, par[l], ch[l]);
             upload_m2m(pl, up, par, ch);
+            std::vector<std::vector<DownItem>> dn(t.depth + 1);
+            for (int l = 3; l <= t.depth; ++l) down_items(t, l, 0, dn[l]);
+            upload_down(pl, up, dn);
         }
         if (up.err == KIFMM_OK &&
             (hipStreamCreateWithFlags(&pl->near_stream, hipStreamNonBlocking) != hipSuccess ||

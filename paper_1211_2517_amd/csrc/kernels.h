@@ -119,6 +119,16 @@ bool m2m_direct_supported(int kp);
 hipError_t launch_m2m_direct(int n_par, const int32_t* par_row, const int32_t* child, const void* A, int kp,
                              const void* X, void* Y, hipStream_t st);
 
+// FP32 direct-form product with one right-hand side, one class per segment:
+// for segment s = (cls, i0, n) of seg (3 words each, n <= 16 kDownMaxBlocks)
+// and i0 <= i < i0 + n (n >= 1), Y[tgt[i]] += A_cls X[src[i]], A_cls the
+// kp x kp block of class cls (row-major, consecutive), X and Y rows of kp,
+// the tgt rows distinct and none of them a src row. 16 <= kp <= 160,
+// kp % 16 == 0.
+constexpr int kDownMaxBlocks = 16;
+hipError_t launch_down_direct(int n_seg, const int32_t* seg, const int32_t* tgt, const int32_t* src, const void* A,
+                              int kp, const void* X, void* Y, hipStream_t st);
+
 // A joined vector of up to kMaxSegments plans' vectors (passed by value to
 // the kernels): segment s holds elements [off[s], off[s+1]) at ptr[s].
 constexpr int kMaxSegments = 64;

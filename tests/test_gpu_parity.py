@@ -567,18 +567,19 @@ def test_fused_leaf_kernels_match_separate_launches(kind):
 
 
 @pytest.mark.parametrize("kind", ["sphere", "adaptive", "group"])
-def test_direct_m2m_matches_grouped_gemm(kind):
-    # M2M as one product per parent (opts.m2m_direct) against the grouped GEMM
-    # form: the same products summed in another order, so the results agree
-    # to FP32 rounding, forward and adjoint (L2L^T), on a uniform tree, an
-    # adaptive tree (M2M into split cubes only) and a merged group of plans of
-    # different depths (parent and child rows offset per plan)
+def test_direct_passes_match_grouped_gemm(kind):
+    # M2M as one product per parent and L2L by octant segments with the
+    # operator rows in registers (opts.direct_passes) against the grouped GEMM
+    # forms: the same products summed in another order, so the results agree
+    # to FP32 rounding, forward and adjoint (L2L^T, M2M^T), on a uniform tree,
+    # an adaptive tree (M2M into split cubes only) and a merged group of plans
+    # of different depths (rows offset per plan, segments across plans)
     torch = _torch()
     K = _k()
     xs = [sphere(20000)[0]] if kind == "sphere" else [workloads.clustered_points(1500, 2500, 3)]
     if kind == "group":
         xs = [sphere(20000)[0], workloads.uniform_cube(3000, 4), workloads.clustered_points(1500, 2500, 3)]
-    mk = lambda x, d: K.Plan(x, p=6, eps=1e-6, leaf_size=32, adaptive=(kind == "adaptive"), m2m_direct=d)
+    mk = lambda x, d: K.Plan(x, p=6, eps=1e-6, leaf_size=32, adaptive=(kind == "adaptive"), direct_passes=d)
     a, b = [mk(x, True) for x in xs], [mk(x, False) for x in xs]
     sig = [torch.tensor(workloads.uniform_density(x.shape[0], 11 + i), dtype=torch.float32, device="cuda:0")
            for i, x in enumerate(xs)]
@@ -596,3 +597,21 @@ def test_direct_m2m_matches_grouped_gemm(kind):
     assert a[0].info()["depth"] >= 4
     assert mr(a[0].apply(sig[0]), b[0].apply(sig[0])) < 2e-6
     assert mr(a[0].apply_adjoint(sig[0]), b[0].apply_adjoint(sig[0])) < 2e-6
+
+
+@pytest.mark.parametrize("p,eps", [(4, 1e-6), (5, 1e-6), (6, 1e-8)])
+def test_direct_passes_other_widths(p, eps):
+    # k padded to 64, 96 and 160 (k = 56, 94, 152): one, two and three row
+    # blocks per wave in the direct kernels, the last ones partly past k_pad,
+    # against the grouped GEMM forms, forward and adjoint
+    torch = _torch()
+    K = _k()
+    x, s = sphere(20000)
+    a = K.Plan(x, p=p, eps=eps, leaf_size=32)
+    b = K.Plan(x, p=p, eps=eps, leaf_size=32, direct_passes=False)
+    assert a.info()["k"] == b.info()["k"]
+    sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
+    u, v = a.apply(sd), b.apply(sd)
+    assert float((u - v).abs().max() / v.abs().max()) < 2e-6, a.info()["k"]
+    ua, va = a.apply_adjoint(sd), b.apply_adjoint(sd)
+    assert float((ua - va).abs().max() / va.abs().max()) < 2e-6, a.info()["k"]
