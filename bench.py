@@ -72,6 +72,31 @@ def time_plan(plan, sd, out, steps, warmup):
     return timing, wall, {k: v / calls for k, v in stage_ms.items()}
 
 
+def time_graph(K, plan, sd, eager, steps, warmup):
+    """The same apply launched from a captured HIP graph (a group of this one
+    plan): median, min and max per step by events around each replay, and the
+    largest difference from the eager result relative to its largest value
+    (the captured form evaluates the near and far fields in one kernel, the
+    same sums grouped differently)."""
+    import torch
+    grp = K.Group([plan])
+    out = torch.empty_like(sd)
+    for _ in range(warmup):
+        grp.apply([sd], [out])
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        grp.apply([sd], [out])
+        b.record()
+    torch.cuda.synchronize()
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    diff = float((out - eager).abs().max() / eager.abs().max())
+    grp.close()
+    return {"median": round(per[len(per) // 2], 4), "min": round(per[0], 4), "max": round(per[-1], 4),
+            "max_diff_vs_eager": diff}
+
+
 def traffic_record(info):
     """HBM bytes per M2L launch from a committed rocprofv3 --pmc summary, if it
     was taken on the current kernel source; else None."""
@@ -475,6 +500,9 @@ def main():
         err_direct = float(np.linalg.norm(got - ref_direct) / np.linalg.norm(ref_direct))
         log(f"{name}: {ms:.3f} ms/step, err vs FP64 oracle {err:.2e}, stages {stages}")
         res[name] = dict(ms=ms, timing=timing, wall=wall, stages=stages, info=info, err=err, err_direct=err_direct)
+        if name == "svd":
+            res[name]["graph"] = time_graph(K, plan, sd_run, out_run.clone(), args.steps, args.warmup)
+            log(f"{name}: graph-launched {res[name]['graph']}")
         if c2 > 0:
             # per-class ranks of the stage-2 factors (the distribution of Fig. 1)
             ranks = np.bincount(plan.export_operator(7).astype(np.int64))
@@ -524,6 +552,8 @@ def main():
                    "n_eq": info["n_eq"], "v_pairs": info["v_pairs"],
                    "p2p_interactions": info["p2p_interactions"]},
         "timing_ms": tim(svd),
+        # the same matvec replayed from a captured HIP graph (one-plan group)
+        "graph_timing_ms": svd["graph"],
         # No FP32 formulation of the uncompressed operators reaches the 1e-5 bar
         # (their rounding is amplified by the pseudo-inverses), so the
         # same-accuracy dense baseline runs in FP64: this ratio crosses

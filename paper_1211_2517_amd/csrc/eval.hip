@@ -762,13 +762,51 @@ __global__ void __launch_bounds__(256) s2m_fused_kernel(int64_t n_leaf, const P4
         sz[k] = ok ? surf[3 * a + 2] : 0.0f;
     }
     P4<float>* st = sp[wave];
+    // point ranges of the workgroup's leaves: lane l holds leaf_ptr[l0 + l]
+    // (l <= nl), read back with readlane
+    const int lp = leaf_ptr[l0 + min(lane, nl)];
+    // the first batch of a leaf's points is loaded one leaf ahead (the next
+    // leaf of this wave while the current one is computed); the loads are
+    // unconditional (index clamped into the leaf, or into the last leaf past
+    // the workgroup's end) so that the compiler's wait for them is exact
+    auto load_first = [&](int ll, P4<float>& v, float& w) {
+        const int l = min(ll, nl - 1);
+        const int p0 = __builtin_amdgcn_readlane(lp, l), p1 = __builtin_amdgcn_readlane(lp, l + 1);
+        const int i = p1 > p0 ? min(p0 + lane, p1 - 1) : 0;
+        v = pts[i];
+        w = sig[i];
+    };
+    P4<float> vn;
+    float wn;
+    load_first(wave, vn, wn);
     for (int ll = wave; ll < LB; ll += WPB) {
         float acc[NA];
 #pragma unroll
         for (int k = 0; k < NA; ++k) acc[k] = 0.0f;
+        const P4<float> v0 = vn;
+        const float w0 = wn;
+        load_first(ll + WPB, vn, wn);
+        auto batch = [&](int cnt) {
+#pragma unroll 2
+            for (int jj = 0; jj < cnt; ++jj) {
+                const P4<float> f = st[jj];
+#pragma unroll
+                for (int k = 0; k < NA; ++k) {
+                    const float dx = sx[k] - f.x, dy = sy[k] - f.y, dz = sz[k] - f.z;
+                    acc[k] += f.w * rsq(dx * dx + dy * dy + dz * dz);
+                }
+            }
+        };
         if (ll < nl) {
-            const int p0 = leaf_ptr[l0 + ll], p1 = leaf_ptr[l0 + ll + 1];
-            for (int base = p0; base < p1; base += CAP) {
+            const int p0 = __builtin_amdgcn_readlane(lp, ll), p1 = __builtin_amdgcn_readlane(lp, ll + 1);
+            // first batch from the prefetched registers, further ones (leaves of
+            // more than CAP points) loaded in place
+            const int cnt0 = min(CAP, p1 - p0);
+            __builtin_amdgcn_wave_barrier();
+            if (lane < cnt0) st[lane] = P4<float>{v0.x, v0.y, v0.z, w0};
+            __builtin_amdgcn_wave_barrier();
+            batch(cnt0);
+            for (int base = p0 + CAP; base < p1; base += CAP) {
                 const int cnt = min(CAP, p1 - base);
                 __builtin_amdgcn_wave_barrier();
                 if (lane < cnt) {
@@ -776,15 +814,7 @@ __global__ void __launch_bounds__(256) s2m_fused_kernel(int64_t n_leaf, const P4
                     st[lane] = P4<float>{v.x, v.y, v.z, sig[base + lane]};
                 }
                 __builtin_amdgcn_wave_barrier();
-#pragma unroll 2
-                for (int jj = 0; jj < cnt; ++jj) {
-                    const P4<float> f = st[jj];
-#pragma unroll
-                    for (int k = 0; k < NA; ++k) {
-                        const float dx = sx[k] - f.x, dy = sy[k] - f.y, dz = sz[k] - f.z;
-                        acc[k] += f.w * rsq(dx * dx + dy * dy + dz * dz);
-                    }
-                }
+                batch(cnt);
             }
         }
 #pragma unroll
@@ -793,19 +823,26 @@ __global__ void __launch_bounds__(256) s2m_fused_kernel(int64_t n_leaf, const P4
             if (a < KDIM) cs[ll * LDB + a] = (a < n_eq && ll < nl) ? acc[k] : 0.0f;
         }
     }
-    __syncthreads();
+    // rows of A for this wave's first 16-row block, issued before the barrier
+    // so that they arrive while the other waves finish their leaves (a fence
+    // keeps the compiler from spreading the loads over the MFMAs, which would
+    // wait for each in turn); further blocks load theirs in place
     const int j = lane & 15, grp = lane >> 4;
+    fv4 a0[KP16];
+    {
+        const float* ar = A + (int64_t)(min(wave, MB - 1) * 16 + j) * KDIM + 4 * grp;
+#pragma unroll
+        for (int t = 0; t < KP16; ++t) a0[t] = *reinterpret_cast<const fv4*>(ar + 16 * t);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
     int orow[LB / 16];
 #pragma unroll
     for (int b = 0; b < LB / 16; ++b) {
         const int c = b * 16 + j;
         orow[b] = c < nl ? leaf_row[l0 + c] : -1;
     }
-    for (int blk = wave; blk < MB; blk += WPB) {
-        fv4 a[KP16];
-        const float* ar = A + (int64_t)(blk * 16 + j) * KDIM + 4 * grp;
-#pragma unroll
-        for (int t = 0; t < KP16; ++t) a[t] = *reinterpret_cast<const fv4*>(ar + 16 * t);
+    auto rows = [&](int blk, const fv4 (&a)[KP16]) {
 #pragma unroll
         for (int cb = 0; cb < LB / 16; ++cb) {
             if (cb * 16 >= nl) break;
@@ -829,6 +866,15 @@ __global__ void __launch_bounds__(256) s2m_fused_kernel(int64_t n_leaf, const P4
                 for (int q = 0; q < 4; ++q) yp[4 * grp + q] = scale * (d0[q] + d1[q]);
             }
         }
+    };
+    if (wave < MB) rows(wave, a0);
+    for (int blk = wave + WPB; blk < MB; blk += WPB) {
+        fv4 a[KP16];
+        const float* ar = A + (int64_t)(blk * 16 + j) * KDIM + 4 * grp;
+#pragma unroll
+        for (int t = 0; t < KP16; ++t) a[t] = *reinterpret_cast<const fv4*>(ar + 16 * t);
+        __builtin_amdgcn_sched_barrier(0);
+        rows(blk, a);
     }
 }
 
@@ -856,20 +902,48 @@ __global__ void __launch_bounds__(256) l2p_fused_kernel(int64_t n_leaf, const P4
     const int wave = tid >> 6, lane = tid & 63;
     const int64_t l0 = (int64_t)blockIdx.x * LB;
     const int nl = (int)min((int64_t)LB, n_leaf - l0);
-    for (int f = tid; f < LB * (KDIM / 4); f += 256) {
-        const int c = f / (KDIM / 4), part = 4 * (f - c * (KDIM / 4));
-        const int r = c < nl ? leaf_row[l0 + c] : -1;
-        fv4 v = fv4{0, 0, 0, 0};
-        if (r >= 0) v = *reinterpret_cast<const fv4*>(X + (int64_t)r * ldx + part);
-        *reinterpret_cast<fv4*>(xs + c * LDB + part) = v;
-    }
-    __syncthreads();
     const int j = lane & 15, grp = lane >> 4;
-    for (int blk = wave; blk < NR16; blk += WPB) {
-        fv4 a[KP16];
+    // the loads of this phase before its first wait: the rows of A of this
+    // wave's first 16-row block, then the gathered X columns (unconditional:
+    // a leaf without a row, or past the end, reads row 0 and stages zeros);
+    // further blocks load their rows of A in place
+    constexpr int NG = (LB * (KDIM / 4) + 255) / 256;
+    auto load_a = [&](int blk, fv4 (&a)[KP16]) {
         const float* ar = A + (int64_t)(blk * 16 + j) * KDIM + 4 * grp;
 #pragma unroll
         for (int t = 0; t < KP16; ++t) a[t] = *reinterpret_cast<const fv4*>(ar + 16 * t);
+    };
+    fv4 a0[KP16];
+    load_a(min(wave, NR16 - 1), a0);
+    fv4 gv[NG];
+    bool gz[NG];
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+        const int f = min(tid + 256 * i, LB * (KDIM / 4) - 1);
+        const int c = f / (KDIM / 4), part = 4 * (f - c * (KDIM / 4));
+        const int r = c < nl ? leaf_row[l0 + c] : -1;
+        gz[i] = r < 0;
+        gv[i] = *reinterpret_cast<const fv4*>(X + (int64_t)(r < 0 ? 0 : r) * ldx + part);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+        const int f = tid + 256 * i;
+        if (f < LB * (KDIM / 4)) {
+            const int c = f / (KDIM / 4), part = 4 * (f - c * (KDIM / 4));
+            *reinterpret_cast<fv4*>(xs + c * LDB + part) = gz[i] ? fv4{0, 0, 0, 0} : gv[i];
+        }
+    }
+    __syncthreads();
+    for (int blk = wave; blk < NR16; blk += WPB) {
+        fv4 a[KP16];
+        if (blk == wave) {
+#pragma unroll
+            for (int t = 0; t < KP16; ++t) a[t] = a0[t];
+        } else {
+            load_a(blk, a);
+            __builtin_amdgcn_sched_barrier(0);
+        }
 #pragma unroll
         for (int cb = 0; cb < LB / 16; ++cb) {
             fv4 d0 = fv4{0, 0, 0, 0}, d1 = fv4{0, 0, 0, 0};
@@ -891,31 +965,80 @@ __global__ void __launch_bounds__(256) l2p_fused_kernel(int64_t n_leaf, const P4
     }
     __syncthreads();
     P4<float>* fs = reinterpret_cast<P4<float>*>(xs) + wave * NROW;
-    for (int ll = wave; ll < nl; ll += WPB) {
-        if (leaf_row[l0 + ll] < 0) continue;
-        const int p0 = leaf_ptr[l0 + ll];
-        const int ne = leaf_ptr[l0 + ll + 1] - p0;
-        __builtin_amdgcn_wave_barrier();
-        for (int a = lane; a < n_eq; a += 64)
-            fs[a] = P4<float>{surf[3 * a], surf[3 * a + 1], surf[3 * a + 2], es[ll * LDE + a]};
-        __builtin_amdgcn_wave_barrier();
+    // point ranges and Q/P rows of the workgroup's leaves: lane l holds those
+    // of leaf l, read back with readlane
+    const int lp = leaf_ptr[l0 + min(lane, nl)];
+    const int lr = leaf_row[l0 + min(lane, nl - 1)];
+    // the surface in registers (lane a, a + 64, ...), staged with each leaf's E
+    constexpr int NS = (NROW + 63) / 64;
+    float fx[NS], fy[NS], fz[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int a = min(k * 64 + lane, n_eq - 1);
+        fx[k] = surf[3 * a];
+        fy[k] = surf[3 * a + 1];
+        fz[k] = surf[3 * a + 2];
+    }
+    // lanes per target (a power of two) so that one pass covers the leaf's
+    // points where it can. The first pass's target point and output index
+    // are loaded one leaf ahead, unconditionally (the index clamped into the
+    // leaf, or into the last leaf past the workgroup's end), and the old
+    // output value before the next leaf's loads, so that each wait covers
+    // exactly the loads it needs; further passes (leaves of more than 64
+    // points) load in place.
+    auto lanes_per_target = [](int ne) {
         int lpt = 64;
         while (lpt > 1 && (64 / lpt) < ne) lpt >>= 1;
+        return lpt;
+    };
+    auto load_first = [&](int ll, P4<float>& u, int& pi) {
+        const int l = min(ll, nl - 1);
+        const int p0 = __builtin_amdgcn_readlane(lp, l), ne = __builtin_amdgcn_readlane(lp, l + 1) - p0;
+        const int i = ne > 0 ? p0 + min(lane / lanes_per_target(ne), ne - 1) : 0;
+        u = pts[i];
+        pi = perm[i];
+    };
+    auto far_at = [&](const P4<float>& ui, int lpt, int sub) {
+        float far = 0.0f;
+#pragma unroll 4
+        for (int a = sub; a < n_eq; a += lpt) {
+            const P4<float> f = fs[a];
+            const float dx = ui.x - f.x, dy = ui.y - f.y, dz = ui.z - f.z;
+            far += f.w * rsq(dx * dx + dy * dy + dz * dz);
+        }
+        for (int off = lpt >> 1; off > 0; off >>= 1) far += __shfl_xor(far, off);
+        return far;
+    };
+    P4<float> un;
+    int pn;
+    load_first(wave, un, pn);
+    for (int ll = wave; ll < nl; ll += WPB) {
+        const P4<float> u0 = un;
+        const int pi0 = pn;
+        const float old0 = out[pi0];
+        load_first(ll + WPB, un, pn);
+        if (__builtin_amdgcn_readlane(lr, ll) < 0) continue;
+        const int p0 = __builtin_amdgcn_readlane(lp, ll);
+        const int ne = __builtin_amdgcn_readlane(lp, ll + 1) - p0;
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const int a = k * 64 + lane;
+            if (a < n_eq) fs[a] = P4<float>{fx[k], fy[k], fz[k], es[ll * LDE + a]};
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int lpt = lanes_per_target(ne);
         const int tpr = 64 / lpt;
         const int sub = lane & (lpt - 1);
-        for (int tb = 0; tb < ne; tb += tpr) {
+        {
+            const float far = far_at(u0, lpt, sub);
+            if (lane / lpt < ne && sub == 0) out[pi0] = old0 + far_scale * far;
+        }
+        for (int tb = tpr; tb < ne; tb += tpr) {
             const int tl = tb + lane / lpt;
             const bool valid = tl < ne;
             const int i = p0 + (valid ? tl : 0);
-            const P4<float> ui = pts[i];
-            float far = 0.0f;
-#pragma unroll 4
-            for (int a = sub; a < n_eq; a += lpt) {
-                const P4<float> f = fs[a];
-                const float dx = ui.x - f.x, dy = ui.y - f.y, dz = ui.z - f.z;
-                far += f.w * rsq(dx * dx + dy * dy + dz * dz);
-            }
-            for (int off = lpt >> 1; off > 0; off >>= 1) far += __shfl_xor(far, off);
+            const float far = far_at(pts[i], lpt, sub);
             if (valid && sub == 0) out[perm[i]] += far_scale * far;
         }
     }
