@@ -162,6 +162,8 @@ typedef struct {
     double m2t_flops;       /* adaptive: M2T (U~ products and point evaluations) per apply */
     double s2l_flops;       /* adaptive: S2L (point evaluations and U~^T products) per apply */
     int layer;              /* -1 point sources; BEM plans: KIFMM_SINGLE_LAYER / KIFMM_DOUBLE_LAYER */
+    int64_t m2l_chunks;     /* M2L chunks (runs of at most 32 pairs of one class in a tile) */
+    int64_t m2l_blocks;     /* their 16-column MFMA blocks */
 } kifmm_info_t;
 
 /* Fill `o` with the defaults listed above. Returns KIFMM_EINVAL if o is NULL. */

@@ -61,7 +61,7 @@ class _Info(ctypes.Structure):
                 ("m2l_rank_max", ctypes.c_int), ("m2l_rank_mean", ctypes.c_double),
                 ("adaptive", ctypes.c_int), ("leaf_level_min", ctypes.c_int), ("w_pairs", ctypes.c_int64),
                 ("w_cubes", ctypes.c_int64), ("m2t_flops", ctypes.c_double), ("s2l_flops", ctypes.c_double),
-                ("layer", ctypes.c_int)]
+                ("layer", ctypes.c_int), ("m2l_chunks", ctypes.c_int64), ("m2l_blocks", ctypes.c_int64)]
 
 
 _LIB = None

@@ -809,6 +809,8 @@ void fill_info(kifmm_plan_s* pl, double seconds) {
     in.plan_seconds = seconds;
     in.m2l_variant = pl->h_m2l.variant;
     in.m2l_tiles = pl->h_m2l.n_tiles();
+    in.m2l_chunks = pl->h_m2l.n_chunks();
+    for (int32_t b : pl->h_m2l.chunk_nblk) in.m2l_blocks += b & 0xff;
     in.adaptive = t.adaptive ? 1 : 0;
     in.layer = pl->layer;
     in.leaf_level_min = t.depth;
