@@ -599,14 +599,56 @@ __global__ void __launch_bounds__(256) eval_surface_bem_kernel(
 // p ln((R+ + s+)/(R- + s-)) - |h| (atan(p s+ / (R0^2 + |h| R+)) - atan(p s- /
 // (R0^2 + |h| R-))), p = (start - x0).m, s = (end points - x0).t, R0^2 = p^2 +
 // h^2, R = sqrt(s^2 + R0^2) (Wilton et al. 1984); R + s is formed as R0^2 /
-// (R - s) for s < 0, which has no cancellation.
+// (R - s) for s < 0, which has no cancellation. Evaluated with fewer
+// transcendentals: R- and R+ are the distances from x to the edge's end
+// points (three square roots per triangle, not two per edge), and the
+// difference of the two arctangents is one atan2: with D = R0^2 + |h| R > 0,
+// atan(p s+ / D+) - atan(p s- / D-) = atan2(p (s+ D- - s- D+), D+ D- + p^2 s+ s-)
+// (both angles lie in (-pi/2, pi/2), so the difference is the angle of the
+// point (cos, sin) ~ (D+ D- + p^2 s+ s-, p (s+ D- - s- D+)), scaled by D+ D-).
 template <typename T>
 __device__ __forceinline__ T tri_inv_r(T x, T y, T z, const P4<T>& a, const P4<T>& b, const P4<T>& c,
-                                       const P4<T>& n) {
+                                       const P4<T>& n, const P4<T> (&te)[3], const P4<T> (&me)[3]) {
+    // te[e]: unit tangent of edge e (vertex e to e+1) and its length in w;
+    // me[e]: the in-plane outward normal t x n
     const T h = (x - a.x) * n.x + (y - a.y) * n.y + (z - a.z) * n.z;
     const T x0 = x - h * n.x, y0 = y - h * n.y, z0 = z - h * n.z;
     const T ah = fabs(h);
+    const P4<T>* vs[3] = {&a, &b, &c};
+    T dist[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const T dx = vs[e]->x - x, dy = vs[e]->y - y, dz = vs[e]->z - z;
+        dist[e] = sqrt(dx * dx + dy * dy + dz * dz);
+    }
     T total = 0;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const P4<T>& u = *vs[e];
+        const T dx = u.x - x0, dy = u.y - y0, dz = u.z - z0;
+        const T p = dx * me[e].x + dy * me[e].y + dz * me[e].z;
+        const T sm = dx * te[e].x + dy * te[e].y + dz * te[e].z;
+        const T sp = sm + te[e].w;
+        const T r0 = p * p + h * h;
+        const T rm = dist[e], rp = dist[(e + 1) % 3];
+        if (p != T(0)) {
+            const T num = sp >= T(0) ? rp + sp : r0 / (rp - sp);
+            const T den = sm >= T(0) ? rm + sm : r0 / (rm - sm);
+            total += p * log(num / den);
+            if (ah > T(0)) {
+                const T dp = r0 + ah * rp, dm = r0 + ah * rm;
+                total -= ah * atan2(p * (sp * dm - sm * dp), dp * dm + p * p * sp * sm);
+            }
+        }
+    }
+    return total;
+}
+
+// Edge data of a triangle for tri_inv_r: unit tangents with lengths, and
+// in-plane outward normals.
+template <typename T>
+__device__ __forceinline__ void tri_edges(const P4<T>& a, const P4<T>& b, const P4<T>& c, const P4<T>& n,
+                                          P4<T> (&te)[3], P4<T> (&me)[3]) {
     const P4<T>* vs[3] = {&a, &b, &c};
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
@@ -616,21 +658,9 @@ __device__ __forceinline__ T tri_inv_r(T x, T y, T z, const P4<T>& a, const P4<T
         const T len = sqrt(ex * ex + ey * ey + ez * ez);
         const T il = T(1) / len;
         const T tx = ex * il, ty = ey * il, tz = ez * il;
-        const T mx = ty * n.z - tz * n.y, my = tz * n.x - tx * n.z, mz = tx * n.y - ty * n.x;
-        const T dx = u.x - x0, dy = u.y - y0, dz = u.z - z0;
-        const T p = dx * mx + dy * my + dz * mz;
-        const T sm = dx * tx + dy * ty + dz * tz;
-        const T sp = sm + len;
-        const T r0 = p * p + h * h;
-        const T rm = sqrt(sm * sm + r0), rp = sqrt(sp * sp + r0);
-        if (p != T(0)) {
-            const T num = sp >= T(0) ? rp + sp : r0 / (rp - sp);
-            const T den = sm >= T(0) ? rm + sm : r0 / (rm - sm);
-            total += p * log(num / den);
-            if (ah > T(0)) total -= ah * (atan(p * sp / (r0 + ah * rp)) - atan(p * sm / (r0 + ah * rm)));
-        }
+        te[e] = P4<T>{tx, ty, tz, len};
+        me[e] = P4<T>{ty * n.z - tz * n.y, tz * n.x - tx * n.z, tx * n.y - ty * n.x, T(0)};
     }
-    return total;
 }
 
 // signed solid angle of the triangle (a, b, c) seen from x (Van Oosterom and
@@ -650,20 +680,27 @@ __device__ __forceinline__ T tri_solid_angle(T x, T y, T z, const P4<T>& a, cons
 }
 
 // BEM near field (S2T, Sec. 4.2): one wave per target leaf, `lpt` lanes per
-// collocation point splitting the near-field triangles, which are staged as
-// four 4-vectors (vertices shifted into the target leaf's units by the cube
-// offset, unit normal; q in the first vertex's w, the triangle's index in the
-// second's). Single layer: out = scale * sum_j q_j int_T 1/|x - y| (scale =
-// r_L / (4 pi)); double layer: scale * sum_j q_j Omega_j (scale = -1/(4 pi)),
-// the self triangle contributing 0 (principal value). Writes out.
+// collocation point splitting the near-field triangles. The triangles of all
+// near-field leaves are staged in batches of CAP, one per lane, as the near
+// field of points is (entries resolved one per lane, a prefix sum of their
+// triangle counts, each staged triangle's entry found by a binary search over
+// the lanes): one memory latency per batch. A staged triangle is its vertices
+// shifted into the target leaf's units by the cube offset, its unit normal
+// (q in the first vertex's w, the triangle's index in the second's) and, for
+// the single layer, its edge tangents, lengths and in-plane normals, formed
+// once per staged triangle instead of once per pair. Single layer: out =
+// scale * sum_j q_j int_T 1/|x - y| (scale = r_L / (4 pi)); double layer:
+// scale * sum_j q_j Omega_j (scale = -1/(4 pi)), the self triangle
+// contributing 0 (principal value). Writes out.
 template <typename T, bool DL>
 __global__ void __launch_bounds__(256) eval_near_bem_kernel(
     int64_t n_leaf, const P4<T>* __restrict__ pts, const P4<T>* __restrict__ tri, const T* __restrict__ sig,
     const int32_t* __restrict__ leaf_ptr, const int32_t* __restrict__ near_ptr, const int32_t* __restrict__ near_leaf,
     const int32_t* __restrict__ near_code, T scale, const int32_t* __restrict__ perm, T* __restrict__ out) {
     constexpr int WPB = 4;
-    constexpr int CAP = 32;
-    __shared__ P4<T> sp[WPB][4 * CAP];
+    constexpr int CAP = sizeof(T) == 4 ? 64 : 32;
+    constexpr int NP = DL ? 4 : 10;   // 4-vectors per staged triangle
+    __shared__ P4<T> sp[WPB][NP * CAP];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t leaf = (int64_t)blockIdx.x * WPB + wave;
@@ -676,41 +713,86 @@ __global__ void __launch_bounds__(256) eval_near_bem_kernel(
     const int tpr = 64 / lpt;
     const int sub = lane & (lpt - 1);
     const int q0 = near_ptr[leaf], q1 = near_ptr[leaf + 1];
+    // near-field entries, one per lane: first triangle, count, offset code,
+    // and the inclusive prefix sum of the counts
+    const int nq = min(q1 - q0, 64);
+    int e_b0 = 0, e_code = 0, e_cnt = 0;
+    if (lane < nq) {
+        const int nb = near_leaf[q0 + lane];
+        e_code = near_code[q0 + lane];
+        e_b0 = leaf_ptr[nb];
+        e_cnt = leaf_ptr[nb + 1] - e_b0;
+    }
+    int incl = e_cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    const int n_near = __shfl(incl, 63);
     for (int tb = 0; tb < ne; tb += tpr) {
         const int tl = tb + lane / lpt;
         const bool valid = tl < ne;
         const int i = p0 + (valid ? tl : 0);
         const P4<T> ui = pts[i];
         T acc = 0;
-        for (int q = q0; q < q1; ++q) {
-            const int nb = near_leaf[q];
-            const int code = near_code[q];
-            // source shifted into target-leaf units: s - 2 d, d = target - source cube
-            const T ox = T(-2 * (code / 9 - 1)), oy = T(-2 * ((code / 3) % 3 - 1)), oz = T(-2 * (code % 3 - 1));
-            const int b0 = leaf_ptr[nb], b1 = leaf_ptr[nb + 1];
-            for (int base = b0; base < b1; base += CAP) {
-                const int cnt = min(CAP, b1 - base);
-                __builtin_amdgcn_wave_barrier();
-                for (int f = lane; f < 4 * cnt; f += 64) {
-                    const int t = f >> 2, part = f & 3;
-                    P4<T> v = tri[4 * (int64_t)(base + t) + part];
-                    if (part < 3) {
-                        v.x += ox;
-                        v.y += oy;
-                        v.z += oz;
-                    }
-                    if (part == 0) v.w = sig[base + t];
-                    if (part == 1) v.w = T(base + t);
-                    st[f] = v;
+        for (int base = 0; base < n_near; base += CAP) {
+            const int cnt = min(CAP, n_near - base);
+            __builtin_amdgcn_wave_barrier();
+            for (int slot = lane; slot < CAP; slot += 64) {
+                const int sidx = base + slot;
+                int e = 0;
+#pragma unroll
+                for (int stp = 32; stp > 0; stp >>= 1) {
+                    const int v = __shfl(incl, e + stp - 1);
+                    if (v <= sidx) e += stp;
                 }
-                __builtin_amdgcn_wave_barrier();
-                for (int t = sub; t < cnt; t += lpt) {
-                    const P4<T> a = st[4 * t], b = st[4 * t + 1], c = st[4 * t + 2], n = st[4 * t + 3];
-                    if constexpr (DL) {
-                        if ((int)b.w != i) acc += a.w * tri_solid_angle(ui.x, ui.y, ui.z, a, b, c);
-                    } else {
-                        acc += a.w * tri_inv_r(ui.x, ui.y, ui.z, a, b, c, n);
+                e = min(e, 63);
+                const int b0 = __shfl(e_b0, e);
+                const int ex = __shfl(incl, e) - __shfl(e_cnt, e);
+                const int code = __shfl(e_code, e);
+                if (slot < cnt) {
+                    const int j = b0 + (sidx - ex);
+                    // source shifted into target-leaf units: s - 2 d, d = target - source cube
+                    const T ox = T(-2 * (code / 9 - 1)), oy = T(-2 * ((code / 3) % 3 - 1)), oz = T(-2 * (code % 3 - 1));
+                    P4<T> v[4];
+#pragma unroll
+                    for (int part = 0; part < 4; ++part) v[part] = tri[4 * (int64_t)j + part];
+#pragma unroll
+                    for (int part = 0; part < 3; ++part) {
+                        v[part].x += ox;
+                        v[part].y += oy;
+                        v[part].z += oz;
                     }
+                    v[0].w = sig[j];
+                    v[1].w = T(j);
+#pragma unroll
+                    for (int part = 0; part < 4; ++part) st[NP * slot + part] = v[part];
+                    if constexpr (!DL) {
+                        P4<T> te[3], me[3];
+                        tri_edges(v[0], v[1], v[2], v[3], te, me);
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) {
+                            st[NP * slot + 4 + k] = te[k];
+                            st[NP * slot + 7 + k] = me[k];
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            for (int t = sub; t < cnt; t += lpt) {
+                const P4<T> a = st[NP * t], b = st[NP * t + 1], c = st[NP * t + 2];
+                if constexpr (DL) {
+                    if ((int)b.w != i) acc += a.w * tri_solid_angle(ui.x, ui.y, ui.z, a, b, c);
+                } else {
+                    const P4<T> n = st[NP * t + 3];
+                    P4<T> te[3], me[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        te[k] = st[NP * t + 4 + k];
+                        me[k] = st[NP * t + 7 + k];
+                    }
+                    acc += a.w * tri_inv_r(ui.x, ui.y, ui.z, a, b, c, n, te, me);
                 }
             }
         }
