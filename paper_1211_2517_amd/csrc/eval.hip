@@ -593,6 +593,39 @@ __global__ void __launch_bounds__(256) eval_surface_bem_kernel(
     }
 }
 
+// Elementary functions of the BEM element integrals. FP32: the hardware
+// square root, reciprocal and log2 (about 1 ulp each), and an arctangent
+// from a degree-8 polynomial in t^2 (atan(t) ~ t P(t^2) on [0, 1], fitted by
+// fit_atan.py; largest error 9e-8) with the octant reduction of atan2; the
+// integrals are sums of many such terms checked against the FP64 oracle at
+// 1e-5. FP64: the library functions.
+__device__ __forceinline__ float bem_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double bem_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float bem_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double bem_div(double a, double b) { return a / b; }
+__device__ __forceinline__ float bem_log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
+__device__ __forceinline__ double bem_log(double x) { return log(x); }
+__device__ __forceinline__ float bem_atan2(float y, float x) {
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float s = t * t;
+    float p = 0.0024567225482314825f;
+    p = __builtin_fmaf(p, s, -0.01440135296434164f);
+    p = __builtin_fmaf(p, s, 0.039781223982572556f);
+    p = __builtin_fmaf(p, s, -0.07234857976436615f);
+    p = __builtin_fmaf(p, s, 0.10498946905136108f);
+    p = __builtin_fmaf(p, s, -0.14161229133605957f);
+    p = __builtin_fmaf(p, s, 0.19985906779766083f);
+    p = __builtin_fmaf(p, s, -0.33332598209381104f);
+    p = __builtin_fmaf(p, s, 0.9999998807907104f);
+    float r = t * p;
+    if (ay > ax) r = 1.5707963267948966f - r;
+    if (x < 0.0f) r = 3.1415926535897932f - r;
+    return copysignf(r, y);
+}
+__device__ __forceinline__ double bem_atan2(double y, double x) { return atan2(y, x); }
+
 // int_T 1/|x - y| dS_y over a flat triangle (vertices a, b, c, unit normal n)
 // in closed form: for the projection x0 of x on the plane and its height h,
 // every edge with in-plane outward normal m and unit tangent t adds
@@ -619,7 +652,7 @@ __device__ __forceinline__ T tri_inv_r(T x, T y, T z, const P4<T>& a, const P4<T
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
         const T dx = vs[e]->x - x, dy = vs[e]->y - y, dz = vs[e]->z - z;
-        dist[e] = sqrt(dx * dx + dy * dy + dz * dz);
+        dist[e] = bem_sqrt(dx * dx + dy * dy + dz * dz);
     }
     T total = 0;
 #pragma unroll
@@ -632,12 +665,12 @@ __device__ __forceinline__ T tri_inv_r(T x, T y, T z, const P4<T>& a, const P4<T
         const T r0 = p * p + h * h;
         const T rm = dist[e], rp = dist[(e + 1) % 3];
         if (p != T(0)) {
-            const T num = sp >= T(0) ? rp + sp : r0 / (rp - sp);
-            const T den = sm >= T(0) ? rm + sm : r0 / (rm - sm);
-            total += p * log(num / den);
+            const T num = sp >= T(0) ? rp + sp : bem_div(r0, rp - sp);
+            const T den = sm >= T(0) ? rm + sm : bem_div(r0, rm - sm);
+            total += p * bem_log(bem_div(num, den));
             if (ah > T(0)) {
                 const T dp = r0 + ah * rp, dm = r0 + ah * rm;
-                total -= ah * atan2(p * (sp * dm - sm * dp), dp * dm + p * p * sp * sm);
+                total -= ah * bem_atan2(p * (sp * dm - sm * dp), dp * dm + p * p * sp * sm);
             }
         }
     }
@@ -655,8 +688,8 @@ __device__ __forceinline__ void tri_edges(const P4<T>& a, const P4<T>& b, const 
         const P4<T>& u = *vs[e];
         const P4<T>& w = *vs[(e + 1) % 3];
         const T ex = w.x - u.x, ey = w.y - u.y, ez = w.z - u.z;
-        const T len = sqrt(ex * ex + ey * ey + ez * ez);
-        const T il = T(1) / len;
+        const T len = bem_sqrt(ex * ex + ey * ey + ez * ez);
+        const T il = bem_div(T(1), len);
         const T tx = ex * il, ty = ey * il, tz = ez * il;
         te[e] = P4<T>{tx, ty, tz, len};
         me[e] = P4<T>{ty * n.z - tz * n.y, tz * n.x - tx * n.z, tx * n.y - ty * n.x, T(0)};
@@ -670,13 +703,13 @@ __device__ __forceinline__ T tri_solid_angle(T x, T y, T z, const P4<T>& a, cons
     const T r1x = a.x - x, r1y = a.y - y, r1z = a.z - z;
     const T r2x = b.x - x, r2y = b.y - y, r2z = b.z - z;
     const T r3x = c.x - x, r3y = c.y - y, r3z = c.z - z;
-    const T l1 = sqrt(r1x * r1x + r1y * r1y + r1z * r1z);
-    const T l2 = sqrt(r2x * r2x + r2y * r2y + r2z * r2z);
-    const T l3 = sqrt(r3x * r3x + r3y * r3y + r3z * r3z);
+    const T l1 = bem_sqrt(r1x * r1x + r1y * r1y + r1z * r1z);
+    const T l2 = bem_sqrt(r2x * r2x + r2y * r2y + r2z * r2z);
+    const T l3 = bem_sqrt(r3x * r3x + r3y * r3y + r3z * r3z);
     const T num = r1x * (r2y * r3z - r2z * r3y) + r1y * (r2z * r3x - r2x * r3z) + r1z * (r2x * r3y - r2y * r3x);
     const T den = l1 * l2 * l3 + (r1x * r2x + r1y * r2y + r1z * r2z) * l3 + (r1x * r3x + r1y * r3y + r1z * r3z) * l2 +
                   (r2x * r3x + r2y * r3y + r2z * r3z) * l1;
-    return T(2) * atan2(num, den);
+    return T(2) * bem_atan2(num, den);
 }
 
 // BEM near field (S2T, Sec. 4.2): one wave per target leaf, `lpt` lanes per
