@@ -400,6 +400,66 @@ __global__ void __launch_bounds__(256) eval_m2t_kernel(
     const int sub = lane & (lpt - 1);
     const int k0 = ent_ptr[wi], k1 = ent_ptr[wi + 1];
     P4<T>* st = fs[wave];
+    if constexpr (R == 1) {
+        // one right-hand side: the surface in registers (lane a, a + 64, ...),
+        // the entries' cubes and geometry one per lane (batches of 64), and
+        // the Psi values of the next entry loaded while the current one is
+        // evaluated (unconditional loads, the entry index clamped)
+        constexpr int NS = MAXEQ / 64 + 1;
+        T sx[NS], sy[NS], sz[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int a = min(q * 64 + lane, n_eq - 1);
+            sx[q] = surf_in[3 * a];
+            sy[q] = surf_in[3 * a + 1];
+            sz[q] = surf_in[3 * a + 2];
+        }
+        const int nsq = (n_eq + 63) / 64;
+        for (int tb = 0; tb < ne; tb += tpr) {
+            const int tl = tb + lane / lpt;
+            const bool valid = tl < ne;
+            const int i = p0 + (valid ? tl : 0);
+            const P4<T> ui = pts[i];
+            T acc = 0;
+            for (int kb = k0; kb < k1; kb += 64) {
+                const int nk = min(64, k1 - kb);
+                const int kl = kb + min(lane, nk - 1);
+                const int e_cube = ent_cube[kl];
+                const T g_rho = ent_geo[4 * kl], g_ox = ent_geo[4 * kl + 1], g_oy = ent_geo[4 * kl + 2],
+                        g_oz = ent_geo[4 * kl + 3];
+                auto load_psi = [&](int e, T (&v)[NS]) {
+                    const T* ps = Psi + (int64_t)__builtin_amdgcn_readlane(e_cube, min(e, nk - 1)) * nep;
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) v[q] = ps[min(q * 64 + lane, n_eq - 1)];
+                };
+                T pn[NS];
+                load_psi(0, pn);
+                for (int e = 0; e < nk; ++e) {
+                    T pc[NS];
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) pc[q] = pn[q];
+                    load_psi(e + 1, pn);
+                    const T rho = __shfl(g_rho, e), ox = __shfl(g_ox, e), oy = __shfl(g_oy, e), oz = __shfl(g_oz, e);
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) {
+                        const int a = q * 64 + lane;
+                        if (q < nsq && a < n_eq) st[a] = P4<T>{rho * sx[q] + ox, rho * sy[q] + oy, rho * sz[q] + oz, pc[q]};
+                    }
+                    __builtin_amdgcn_wave_barrier();
+#pragma unroll 4
+                    for (int a = sub; a < n_eq; a += lpt) {
+                        const P4<T> f = st[a];
+                        const T dx = ui.x - f.x, dy = ui.y - f.y, dz = ui.z - f.z;
+                        acc += f.w * rsq(dx * dx + dy * dy + dz * dz);
+                    }
+                }
+            }
+            for (int off = lpt >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            if (valid && sub == 0 && nrhs > 0) out[perm[i]] += scale * acc;
+        }
+        return;
+    }
     for (int tb = 0; tb < ne; tb += tpr) {
         const int tl = tb + lane / lpt;
         const bool valid = tl < ne;
