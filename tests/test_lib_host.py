@@ -229,3 +229,43 @@ def test_stage2_rejected_with_dense_or_bf16x3():
     pl = K.Plan(x, p=4, eps=1e-6, leaf_size=64, device=-1)
     with pytest.raises(K.KifmmError):
         pl.export_operator(7)
+
+
+def test_fp32_arctangent_coefficients_match_fit():
+    # the FP32 arctangent of the BEM element integrals (eval.hip, bem_atan2)
+    # uses the polynomial that csrc/fit_atan.py fits: the coefficients in the
+    # source equal the script's, the FP32 evaluation stays within 1e-7 of
+    # atan on [0, 1], and the octant reduction reproduces atan2 to 4e-7
+    import importlib.util
+    import os
+    import re
+    here = os.path.join(os.path.dirname(K.__file__), "csrc")
+    spec = importlib.util.spec_from_file_location("fit_atan", os.path.join(here, "fit_atan.py"))
+    fa = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fa)
+    cf = fa.fit()
+    src = open(os.path.join(here, "eval.hip")).read()
+    body = src[src.index("__device__ __forceinline__ float bem_atan2"):]
+    body = body[:body.index("return copysignf")]
+    # Horner order in the source: the highest-degree coefficient, then one per fmaf step
+    lits = [float(re.search(r"float p = (-?\d+\.\d+)f;", body).group(1))]
+    lits += [float(v) for v in re.findall(r"__builtin_fmaf\(p, s, (-?\d+\.\d+)f\)", body)]
+    assert np.array_equal(np.float32(lits), cf[::-1]), (lits, cf)
+    assert fa.fp32_error(cf) < 1e-7
+
+    def atan2_32(y, x):
+        ax, ay = np.abs(x), np.abs(y)
+        mx, mn = np.maximum(ax, ay), np.minimum(ax, ay)
+        t = np.where(mx > 0, mn / np.where(mx > 0, mx, 1), 0).astype(np.float32)
+        s = (t * t).astype(np.float32)
+        p = np.full_like(t, cf[-1])
+        for k in range(len(cf) - 2, -1, -1):
+            p = (p * s + cf[k]).astype(np.float32)
+        r = (t * p).astype(np.float32)
+        r = np.where(ay > ax, np.float32(np.pi / 2) - r, r)
+        r = np.where(x < 0, np.float32(np.pi) - r, r)
+        return np.copysign(r, y)
+
+    rng = np.random.default_rng(0)
+    y, x = (rng.normal(size=(2, 100000)) * 10.0 ** rng.uniform(-3, 3, (2, 100000))).astype(np.float32)
+    assert np.abs(atan2_32(y, x) - np.arctan2(y.astype(np.float64), x.astype(np.float64))).max() < 4e-7
