@@ -422,7 +422,8 @@ def main():
                     help="run the adaptive-tree workload only and print its record")
     ap.add_argument("--only-bem", action="store_true",
                     help="run the BEM conductor workload only and print its record")
-    ap.add_argument("--only", choices=["svd", "dense64", "dense32", "svd_bf16x3", "svd_stage2"], default=None,
+    ap.add_argument("--only", choices=["svd", "svd_near_early", "dense64", "dense32", "svd_bf16x3", "svd_stage2"],
+                    default=None,
                     help="time one plan only (profiling runs); prints no JSON line")
     ap.add_argument("--m2l-shape", type=int, default=-1,
                     help="force the M2L kernel shape (profiling runs; -1 = autotuned)")
@@ -474,15 +475,18 @@ def main():
     # not reach the accuracy because the uncompressed translations amplify it).
     # svd_bf16x3: the compressed path with the split-BF16 M2L (precision mode).
     # svd_stage2: the compressed path with the stage-2 low-rank M2L factors
-    # (Sec. 3.2, C2 = 10), FP32.
-    for name, dense, prec, c2 in (("svd", False, "fp32", 0.0), ("dense64", True, "fp64", 0.0),
-                                  ("dense32", True, "fp32", 0.0), ("svd_bf16x3", False, "bf16x3", 0.0),
-                                  ("svd_stage2", False, "fp32", STAGE2_C2)):
+    # (Sec. 3.2, C2 = 10), FP32. svd_near_early: the compressed path with the
+    # near field forked after the permute (alongside S2M and M2M) instead of
+    # just before M2L: the M2L launch then runs alone.
+    for name, dense, prec, c2, ovl in (("svd", False, "fp32", 0.0, True), ("svd_near_early", False, "fp32", 0.0, False),
+                                       ("dense64", True, "fp64", 0.0, True), ("dense32", True, "fp32", 0.0, True),
+                                       ("svd_bf16x3", False, "bf16x3", 0.0, True),
+                                       ("svd_stage2", False, "fp32", STAGE2_C2, True)):
         if args.only and name != args.only:
             continue
         log(f"plan {name}")
         plan = K.Plan(x, p=P, eps=EPS, leaf_size=LEAF, precision=prec, dense_m2l=dense, c2=c2,
-                      m2l_shape=args.m2l_shape if args.only else -1)
+                      m2l_shape=args.m2l_shape if args.only else -1, near_overlap=ovl)
         if prec == "fp64":
             sd_run = sd.double()
             out_run = torch.empty_like(sd_run)
@@ -554,6 +558,13 @@ def main():
         "timing_ms": tim(svd),
         # the same matvec replayed from a captured HIP graph (one-plan group)
         "graph_timing_ms": svd["graph"],
+        # the near field forked after the permute: the M2L launch alone on the GPU
+        "svd_near_forked_early": {
+            "ms_per_step": round(res["svd_near_early"]["ms"], 4), "timing_ms": tim(res["svd_near_early"]),
+            "m2l_ms": round(res["svd_near_early"]["stages"]["m2l"], 4),
+            "m2l_mfma_util": round(info["flops"]["m2l"] / (res["svd_near_early"]["stages"]["m2l"] * 1e-3)
+                                   / (PEAK_FP32_MFMA_TFLOPS * 1e12), 4),
+            "err_vs_fp64_dense_oracle": res["svd_near_early"]["err"]},
         # No FP32 formulation of the uncompressed operators reaches the 1e-5 bar
         # (their rounding is amplified by the pseudo-inverses), so the
         # same-accuracy dense baseline runs in FP64: this ratio crosses

@@ -45,7 +45,7 @@ class _Opts(ctypes.Structure):
                 ("depth", ctypes.c_int), ("max_depth", ctypes.c_int), ("dense_m2l", ctypes.c_int),
                 ("max_nrhs", ctypes.c_int), ("device", ctypes.c_int), ("mem_limit", ctypes.c_size_t),
                 ("tile_targets", ctypes.c_int), ("m2l_shape", ctypes.c_int), ("c2", ctypes.c_double),
-                ("adaptive", ctypes.c_int), ("fused_leaf", ctypes.c_int), ("direct_passes", ctypes.c_int)]
+                ("adaptive", ctypes.c_int), ("fused_leaf", ctypes.c_int), ("direct_passes", ctypes.c_int), ("near_overlap", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
@@ -129,7 +129,7 @@ class Plan:
                  precision: str = "fp32", dense_m2l: bool = False, max_nrhs: int = 1, device: int = 0,
                  depth: int = 0, max_depth: int = 16, cd: float = 0.5, pinv_rcond: float = 1e-10,
                  mem_limit: int = 0, tile_targets: int = 0, m2l_shape: int = -1, c2: float = 0.0,
-                 adaptive: bool = False, fused_leaf: int = 3, direct_passes: bool = True, _mesh=None):
+                 adaptive: bool = False, fused_leaf: int = 3, direct_passes: bool = True, near_overlap: bool = True, _mesh=None):
         lib = load_library()
         pts = np.ascontiguousarray(np.asarray(points.cpu().numpy() if hasattr(points, "cpu") else points,
                                               dtype=np.float64))
@@ -152,6 +152,7 @@ class Plan:
         o.adaptive = int(bool(adaptive))
         o.fused_leaf = int(fused_leaf)
         o.direct_passes = int(bool(direct_passes))
+        o.near_overlap = int(bool(near_overlap))
         h = ctypes.c_void_p()
         if _mesh is None:
             _check(lib.kifmm_plan_ex(pts.ctypes.data, pts.shape[0], int(p), float(eps), int(leaf_size),

@@ -159,6 +159,9 @@ struct kifmm_plan_s {
     bool down_direct = false;
     std::vector<int32_t> dd_nseg, dd_ncb, dd_nitem;
     std::vector<int32_t*> d_dd;
+    // near field with register-staged sources, forked just before M2L so that
+    // it runs on the CUs the M2L launch holds (opts.near_overlap)
+    bool near_late = false;
     void *bem_qp = nullptr, *bem_tn = nullptr, *bem_tri = nullptr;
     void *sig_s = nullptr, *C = nullptr, *Q = nullptr, *P = nullptr, *E = nullptr;
     void *CX = nullptr, *Psi = nullptr;   // adaptive: per W cube, S2L check potentials and U~ q~
@@ -1419,7 +1422,10 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     // also recorded by eager applies, and an event recorded during a capture
     // must not be reused outside it.
     const bool fork = far && cap_status == hipStreamCaptureStatusNone;
-    if (fork) {
+    // the near field on the plan's own stream: forked after the permute, or
+    // (near_late) just before M2L with the register-staged kernel
+    const bool late = fork && pl->near_late && !adjoint;
+    auto launch_near = [&]() -> int {
         hipStream_t ns = pl->near_stream;
         KIFMM_HIP(hipEventRecord(pl->ev_fork, st));
         KIFMM_HIP(hipStreamWaitEvent(ns, pl->ev_fork, 0));
@@ -1427,12 +1433,20 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         if (bem)
             KIFMM_HIP(launch_eval_near_bem(elt, pl->layer, nleaf, pl->pts, pl->bem_tri, w.sig_s, pl->leaf_ptr,
                                            pl->near_ptr, pl->near_leaf, pl->near_code, bem_scale, pl->perm, out, ns));
+        else if (late)
+            KIFMM_HIP(launch_near_reg(nleaf, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr, pl->near_leaf,
+                                      pl->near_code, near_scale, pl->perm, out, ns));
         else
-        KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
-                                      pl->near_leaf, pl->near_code, lev, lsc, nullptr, pl->surf, n_eq, nep,
-                                      near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, ns));
+            KIFMM_HIP(launch_eval_targets(1, elt, R, nleaf, pl->pts, pl->qpts, w.sig_s, pl->leaf_ptr, pl->near_ptr,
+                                          pl->near_leaf, pl->near_code, lev, lsc, nullptr, pl->surf, n_eq, nep,
+                                          near_scale, 1.0 / kFourPi, pl->perm, out, ld, nrhs, ns));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P + 1], ns));
         KIFMM_HIP(hipEventRecord(pl->ev_join, ns));
+        return KIFMM_OK;
+    };
+    if (fork && !late) {
+        const int rc = launch_near();
+        if (rc != KIFMM_OK) return rc;
     }
     KIFMM_HIP(mark(KIFMM_STAGE_P2M, 0));
     if (far) {
@@ -1469,6 +1483,10 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 1));
+    if (late) {
+        const int rc = launch_near();
+        if (rc != KIFMM_OK) return rc;
+    }
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 0));
     if (far && ad && nw > 0) {
         // M2T: U~ q~ of every W cube (the adjoint: of the upward pass of its transpose, in P)
@@ -1905,6 +1923,7 @@ int kifmm_opts_default(kifmm_opts_t* o) {
     o->m2l_shape = -1;
     o->fused_leaf = 3;
     o->direct_passes = 1;
+    o->near_overlap = 1;
     return KIFMM_OK;
 }
 
@@ -1936,6 +1955,7 @@ static int plan_build(const double* points, int64_t n, int p, double eps, int le
     if (o.adaptive != 0 && o.adaptive != 1) return fail(KIFMM_EINVAL, "adaptive must be 0 or 1");
     if (o.fused_leaf < 0 || o.fused_leaf > 3) return fail(KIFMM_EINVAL, "fused_leaf must be in [0, 3]");
     if (o.direct_passes != 0 && o.direct_passes != 1) return fail(KIFMM_EINVAL, "direct_passes must be 0 or 1");
+    if (o.near_overlap != 0 && o.near_overlap != 1) return fail(KIFMM_EINVAL, "near_overlap must be 0 or 1");
     if (o.adaptive && o.depth > 0) return fail(KIFMM_EINVAL, "adaptive trees take no forced depth (opts.depth)");
     if (bem && (o.adaptive || o.max_nrhs != 1))
         return fail(KIFMM_EINVAL, "BEM plans take uniform trees and one right-hand side (adaptive = 0, max_nrhs = 1)");
@@ -2056,6 +2076,7 @@ static int plan_build(const double* points, int64_t n, int p, double eps, int le
             const bool ok = pl->elt == 4 && pl->R == 1 && o.fused_leaf;
             pl->fuse_s2m = ok && (o.fused_leaf & 1) && !bem && s2m_fused_supported(pl->nep, pl->kp);
             pl->fuse_l2p = ok && (o.fused_leaf & 2) && l2p_fused_supported(pl->nep, pl->kp);
+            pl->near_late = o.near_overlap && pl->elt == 4 && pl->R == 1 && !bem && !t.adaptive;
         }
         if (up.err == KIFMM_OK && t.depth >= 3 && pl->elt == 4 && pl->R == 1 && o.direct_passes &&
             m2m_direct_supported(pl->kp)) {

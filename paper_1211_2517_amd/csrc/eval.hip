@@ -369,6 +369,100 @@ __global__ void __launch_bounds__(256) eval_targets_kernel(
     }
 }
 
+// Near field (S2T) of FP32 uniform plans with one right-hand side, the form
+// of eval_targets_kernel's near mode (fixed-point differences, entries one
+// per lane, prefix sum, binary search) with its batches of 64 staged sources
+// held in registers, one per lane, and read across lanes (ds_bpermute)
+// instead of from LDS. It allocates no LDS, so its workgroups can share a CU
+// with a launch that holds the CU's LDS (the M2L launch) and use the vector
+// ALU that launch leaves idle. Every lane runs the same number of steps per
+// batch (sources past the batch are masked), so the cross-lane reads never
+// execute under divergence; the per-lane sums are those of
+// eval_targets_kernel in the same order (bitwise the same result).
+__global__ void __launch_bounds__(256) near_reg_kernel(int64_t n_leaf, const P4<int32_t>* __restrict__ qpts,
+                                                       const float* __restrict__ sig,
+                                                       const int32_t* __restrict__ leaf_ptr,
+                                                       const int32_t* __restrict__ near_ptr,
+                                                       const int32_t* __restrict__ near_leaf,
+                                                       const int32_t* __restrict__ near_code, float near_scale,
+                                                       const int32_t* __restrict__ perm, float* __restrict__ out) {
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t leaf = (int64_t)blockIdx.x * 4 + wave;
+    if (leaf >= n_leaf) return;
+    const float nscale = near_scale * 268435456.0f;
+    const int p0 = leaf_ptr[leaf];
+    const int ne = leaf_ptr[leaf + 1] - p0;
+    int lpt = 64;
+    while (lpt > 1 && (64 / lpt) < ne) lpt >>= 1;
+    const int tpr = 64 / lpt;
+    const int sub = lane & (lpt - 1);
+    const int q0 = near_ptr[leaf], q1 = near_ptr[leaf + 1];
+    const int nq = min(q1 - q0, 64);
+    int e_b0 = 0, e_code = 0, e_cnt = 0;
+    if (lane < nq) {
+        const int nb = near_leaf[q0 + lane];
+        e_code = near_code[q0 + lane];
+        e_b0 = leaf_ptr[nb];
+        e_cnt = leaf_ptr[nb + 1] - e_b0;
+    }
+    int incl = e_cnt;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off);
+        if (lane >= off) incl += v;
+    }
+    const int n_near = __shfl(incl, 63);
+    for (int tb = 0; tb < ne; tb += tpr) {
+        const int tl = tb + lane / lpt;
+        const bool valid = tl < ne;
+        const int i = p0 + (valid ? tl : 0);
+        const P4<int32_t> qi = qpts[i];
+        float acc = 0.0f;
+        for (int base = 0; base < n_near; base += 64) {
+            const int cnt = min(64, n_near - base);
+            // this lane's staged source: slot = lane of the batch
+            const int sidx = base + lane;
+            int e = 0;
+#pragma unroll
+            for (int stp = 32; stp > 0; stp >>= 1) {
+                const int v = __shfl(incl, e + stp - 1);
+                if (v <= sidx) e += stp;
+            }
+            e = min(e, 63);
+            const int b0 = __shfl(e_b0, e);
+            const int ex = __shfl(incl, e) - __shfl(e_cnt, e);
+            const int code = __shfl(e_code, e);
+            int sx = 0, sy = 0, sz = 0;
+            float sw = 0.0f;
+            if (lane < cnt) {
+                const int jj = b0 + (sidx - ex);
+                // the source in target-leaf units: s - 2 d (d = target - source cube)
+                const int ox = -2 * (code / 9 - 1), oy = -2 * ((code / 3) % 3 - 1), oz = -2 * (code % 3 - 1);
+                const P4<int32_t> sq = qpts[jj];
+                sx = sq.x + ox * (1 << 28);
+                sy = sq.y + oy * (1 << 28);
+                sz = sq.z + oz * (1 << 28);
+                sw = sig[jj];
+            }
+            const int steps = (cnt + lpt - 1) / lpt;
+#pragma unroll 4
+            for (int k = 0; k < steps; ++k) {
+                const int jj = sub + k * lpt;
+                const int src = jj < cnt ? jj : 0;
+                const int fx = __shfl(sx, src), fy = __shfl(sy, src), fz = __shfl(sz, src);
+                const float fw = __shfl(sw, src);
+                const float dx = (float)(qi.x - fx), dy = (float)(qi.y - fy), dz = (float)(qi.z - fz);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float rinv = r2 > 0.0f ? rsq(r2) : 0.0f;
+                if (jj < cnt) acc += fw * rinv;
+            }
+        }
+        for (int off = lpt >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (valid && sub == 0) out[perm[i]] = nscale * acc;
+    }
+}
+
 // M2T at the points of the leaves in `lf_list` (one wave per leaf, `lpt`
 // lanes per target point splitting the surface points): for every W entry of
 // the leaf, the U~ q~ values Psi of its cube, placed on the cube's (1+d)
@@ -1310,6 +1404,17 @@ hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const v
     }
 #undef KIFMM_EVT_AD
 #undef KIFMM_EVT
+    return hipGetLastError();
+}
+
+hipError_t launch_near_reg(int64_t n_leaf, const void* qpts, const void* sig_s, const int32_t* leaf_ptr,
+                           const int32_t* near_ptr, const int32_t* near_leaf, const int32_t* near_code,
+                           double near_scale, const int32_t* perm, void* out, hipStream_t st) {
+    if (n_leaf == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n_leaf + 3) / 4));
+    hipLaunchKernelGGL(near_reg_kernel, grid, dim3(256), 0, st, n_leaf, (const P4<int32_t>*)qpts,
+                       (const float*)sig_s, leaf_ptr, near_ptr, near_leaf, near_code, (float)near_scale, perm,
+                       (float*)out);
     return hipGetLastError();
 }
 

@@ -171,6 +171,13 @@ hipError_t launch_eval_targets(int mode, int elt, int R, int64_t n_leaf, const v
                                double near_scale, double far_scale, const int32_t* perm, void* out, int64_t ld,
                                int nrhs, hipStream_t st);
 
+// Near field of an FP32 uniform plan with one right-hand side (launch_eval_targets
+// mode 1 with R = 1 and no adaptive form), its staged sources in registers:
+// no LDS. Writes out; the same result bit for bit.
+hipError_t launch_near_reg(int64_t n_leaf, const void* qpts, const void* sig_s, const int32_t* leaf_ptr,
+                           const int32_t* near_ptr, const int32_t* near_leaf, const int32_t* near_code,
+                           double near_scale, const int32_t* perm, void* out, hipStream_t st);
+
 // M2T (adaptive trees): for every leaf lf_list[w] and each of its entries k in
 // [ent_ptr[w], ent_ptr[w+1]), the values Psi[(ent_cube[k]*R + r)*nep + a] on the
 // surface points rho * surf_in[a] + o (ent_geo[4k..4k+3] = rho, o; leaf units)

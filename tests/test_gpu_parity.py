@@ -615,3 +615,25 @@ def test_direct_passes_other_widths(p, eps):
     assert float((u - v).abs().max() / v.abs().max()) < 2e-6, a.info()["k"]
     ua, va = a.apply_adjoint(sd), b.apply_adjoint(sd)
     assert float((ua - va).abs().max() / va.abs().max()) < 2e-6, a.info()["k"]
+
+
+def test_near_field_overlap_is_bitwise_the_same():
+    # the near field with register-staged sources forked just before M2L
+    # (opts.near_overlap, the default) against the LDS-staged one forked after
+    # the permute: the same sums in the same order, so the matvec, its adjoint
+    # and the no-allocation apply agree bit for bit
+    torch = _torch()
+    K = _k()
+    x, s = sphere(20000)
+    a = K.Plan(x, p=6, eps=1e-6, leaf_size=32)
+    b = K.Plan(x, p=6, eps=1e-6, leaf_size=32, near_overlap=False)
+    sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
+    fa = a.apply(sd).clone()
+    assert torch.equal(fa, b.apply(sd))
+    assert torch.equal(a.apply_adjoint(sd), b.apply_adjoint(sd))
+    o = torch.full_like(sd, float("nan"))
+    a.apply_noalloc(sd, o)
+    torch.cuda.synchronize()
+    assert torch.equal(o, fa)
+    want = oracle_phi("sphere", 20000, 6, 1e-6, 32, "dense")
+    assert rel(fa.double().cpu().numpy(), want) < 1e-5
