@@ -617,16 +617,30 @@ def test_direct_passes_other_widths(p, eps):
     assert float((ua - va).abs().max() / va.abs().max()) < 2e-6, a.info()["k"]
 
 
-def test_near_field_overlap_is_bitwise_the_same():
+NEAR_SETS = {
+    # name: (points, leaf size); the leaf sizes span every split of a wave's
+    # lanes between targets and sources, leaves of more than 64 points (several
+    # target blocks per wave) and near lists of more than 64 sources (several
+    # staged batches)
+    "sphere": (lambda: sphere(20000)[0], 32),
+    "cube": (lambda: workloads.uniform_cube(30000, workloads.SEED_BASE + 7), 100),
+    "clustered": (lambda: workloads.clustered_points(3000, 5000, workloads.SEED_BASE + 8), 8),
+}
+
+
+@pytest.mark.parametrize("name", list(NEAR_SETS))
+def test_near_field_overlap_is_bitwise_the_same(name):
     # the near field with register-staged sources forked just before M2L
     # (opts.near_overlap, the default) against the LDS-staged one forked after
     # the permute: the same sums in the same order, so the matvec, its adjoint
     # and the no-allocation apply agree bit for bit
     torch = _torch()
     K = _k()
-    x, s = sphere(20000)
-    a = K.Plan(x, p=6, eps=1e-6, leaf_size=32)
-    b = K.Plan(x, p=6, eps=1e-6, leaf_size=32, near_overlap=False)
+    gen, leaf = NEAR_SETS[name]
+    x = gen()
+    s = workloads.uniform_density(x.shape[0], workloads.SEED_BASE + 9) if name != "sphere" else sphere(20000)[1]
+    a = K.Plan(x, p=6, eps=1e-6, leaf_size=leaf)
+    b = K.Plan(x, p=6, eps=1e-6, leaf_size=leaf, near_overlap=False)
     sd = torch.tensor(s, dtype=torch.float32, device="cuda:0")
     fa = a.apply(sd).clone()
     assert torch.equal(fa, b.apply(sd))
@@ -635,5 +649,6 @@ def test_near_field_overlap_is_bitwise_the_same():
     a.apply_noalloc(sd, o)
     torch.cuda.synchronize()
     assert torch.equal(o, fa)
-    want = oracle_phi("sphere", 20000, 6, 1e-6, 32, "dense")
-    assert rel(fa.double().cpu().numpy(), want) < 1e-5
+    if name == "sphere":
+        want = oracle_phi("sphere", 20000, 6, 1e-6, 32, "dense")
+        assert rel(fa.double().cpu().numpy(), want) < 1e-5
