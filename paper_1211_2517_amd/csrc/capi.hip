@@ -1423,11 +1423,13 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
     // must not be reused outside it.
     const bool fork = far && cap_status == hipStreamCaptureStatusNone;
     // the near field on the plan's own stream: forked after the permute, or
-    // (near_late) just before M2L with the register-staged kernel
+    // (near_late) just before M2L with the register-staged kernel; its launch
+    // is then submitted after the M2L launch's (the fork event recorded before
+    // it), so the M2L workgroups are dispatched first (measured 0.6% faster)
     const bool late = fork && pl->near_late && !adjoint;
     auto launch_near = [&]() -> int {
         hipStream_t ns = pl->near_stream;
-        KIFMM_HIP(hipEventRecord(pl->ev_fork, st));
+        if (!late) KIFMM_HIP(hipEventRecord(pl->ev_fork, st));
         KIFMM_HIP(hipStreamWaitEvent(ns, pl->ev_fork, 0));
         if (ev) KIFMM_HIP(hipEventRecord((*ev)[2 * KIFMM_STAGE_P2P], ns));
         if (bem)
@@ -1483,10 +1485,7 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
         }
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2M, 1));
-    if (late) {
-        const int rc = launch_near();
-        if (rc != KIFMM_OK) return rc;
-    }
+    if (late) KIFMM_HIP(hipEventRecord(pl->ev_fork, st));
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 0));
     if (far && ad && nw > 0) {
         // M2T: U~ q~ of every W cube (the adjoint: of the upward pass of its transpose, in P)
@@ -1518,6 +1517,10 @@ int run_passes(kifmm_plan_s* pl, const Work& w, const void* in, void* out, int n
                             1, st));
     }
     KIFMM_HIP(mark(KIFMM_STAGE_M2L, 1));
+    if (late) {
+        const int rc = launch_near();
+        if (rc != KIFMM_OK) return rc;
+    }
     KIFMM_HIP(mark(KIFMM_STAGE_L2L, 0));
     if (far) {
         // L2L (forward) / M2M^T (adjoint): children at l from parents at l-1,
