@@ -116,7 +116,7 @@ typedef struct {
                            with the operator rows held in registers; 0 = the grouped GEMM for both,
                            as in other plans. The forms sum in different orders (results agree to
                            FP32 rounding) */
-    int near_overlap;   /* FP32 uniform point plans with max_nrhs 1: 1 (default) runs the near field
+    int near_overlap;   /* FP32 uniform point plans with max_nrhs 1 and c2 = 0: 1 (default) runs the near field
                            with its staged sources in registers (no LDS) and forks it just before
                            M2L, so it shares the CUs of the M2L launch (which holds their LDS and
                            leaves the vector ALU idle); 0 forks it after the permute, alongside S2M

@@ -2079,7 +2079,9 @@ static int plan_build(const double* points, int64_t n, int p, double eps, int le
             const bool ok = pl->elt == 4 && pl->R == 1 && o.fused_leaf;
             pl->fuse_s2m = ok && (o.fused_leaf & 1) && !bem && s2m_fused_supported(pl->nep, pl->kp);
             pl->fuse_l2p = ok && (o.fused_leaf & 2) && l2p_fused_supported(pl->nep, pl->kp);
-            pl->near_late = o.near_overlap && pl->elt == 4 && pl->R == 1 && !bem && !t.adaptive;
+            // not for stage-2 plans: beside their two M2L phases the near field
+            // costs more than it hides (measured 2.14 -> 2.21 ms at C2 = 10)
+            pl->near_late = o.near_overlap && pl->elt == 4 && pl->R == 1 && !bem && !t.adaptive && !pl->st2;
         }
         if (up.err == KIFMM_OK && t.depth >= 3 && pl->elt == 4 && pl->R == 1 && o.direct_passes &&
             m2m_direct_supported(pl->kp)) {
