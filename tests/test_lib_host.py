@@ -127,6 +127,26 @@ def test_invalid_arguments_are_rejected():
     assert _err(lambda: K.Plan(x, p=9, device=-1)) == -1     # n_eq 386 beyond the device kernels
 
 
+def test_flag_options_out_of_range_are_rejected():
+    # through the C ABI directly (the binding passes these as booleans):
+    # fused_leaf outside [0, 3], direct_passes or near_overlap outside {0, 1}
+    import ctypes
+    lib = K.load_library()
+    x = np.ascontiguousarray(workloads.uniform_cube(100, 1))
+    for field, value in (("fused_leaf", 4), ("fused_leaf", -1), ("direct_passes", 2), ("near_overlap", 2),
+                         ("near_overlap", -1)):
+        o = K._Opts()
+        lib.kifmm_opts_default(ctypes.byref(o))
+        o.device = -1
+        setattr(o, field, value)
+        h = ctypes.c_void_p()
+        rc = lib.kifmm_plan_ex(x.ctypes.data, x.shape[0], 4, 1e-6, 16, ctypes.byref(o), ctypes.byref(h))
+        assert rc == -1 and not h.value, (field, value, rc)
+    o = K._Opts()
+    lib.kifmm_opts_default(ctypes.byref(o))
+    assert (o.fused_leaf, o.direct_passes, o.near_overlap) == (3, 1, 1)
+
+
 def test_host_only_plan_refuses_apply():
     lib = K.load_library()
     _, pl = _host_plan("cube", 4096, 4, 1e-6, 64)
